@@ -1,0 +1,75 @@
+/*
+ * CPU oracle for the negacyclic NTT library -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, slow, obviously-correct reference arithmetic. Only the test suite,
+ * the smoke check and the benchmark's cpu_baseline leg may load it; the
+ * product path never links, imports or calls it, and it shares no code with
+ * the GPU path. All arithmetic is exact over Z_q with 128-bit products and a
+ * '%' reduction per operation (no lazy ranges, no precomputed quotients).
+ *
+ * Notation follows the paper (NTTSuite, "Twiddle Factors" paragraph, Eq. 1-3):
+ * N = 2^L points, q the prime (the paper's P), W_N^i the twiddle factors.
+ * The negacyclic twist, the inverse transform and the pointwise product are
+ * not in the paper; their definitions are the textbook ones:
+ *   psi     = c^((q-1)/(2N)), c the smallest quadratic non-residue mod q
+ *             (a primitive 2N-th root of unity: psi^N = -1), omega = psi^2
+ *   NTT(x)_k  = sum_j x_j psi^((2k+1) j)                    k = 0..N-1
+ *   INTT(X)_j = N^-1 psi^-j sum_k X_k omega^(-jk)           j = 0..N-1
+ *   (a*b)_k   = sum_{i+j=k} a_i b_j - sum_{i+j=k+N} a_i b_j (mod x^N + 1)
+ * Parity status of each function is listed beside it.
+ */
+#ifndef NTT_ORACLE_H
+#define NTT_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* --- scalar arithmetic mod q (modulo_add / modulo_mult semantics, Alg. 4-5,
+ *     computed the slow way: a full product and '%') ------------------------ */
+uint64_t orc_addmod(uint64_t a, uint64_t b, uint64_t q);
+uint64_t orc_submod(uint64_t a, uint64_t b, uint64_t q);
+uint64_t orc_mulmod(uint64_t a, uint64_t b, uint64_t q);
+uint64_t orc_powmod(uint64_t a, uint64_t e, uint64_t q);
+uint64_t orc_invmod(uint64_t a, uint64_t q);           /* a^(q-2), q prime */
+
+/* --- parameters ------------------------------------------------------------ */
+/* smallest c >= 2 with c^((q-1)/2) == q-1 (Euler's criterion); 0 if none < 1000 */
+uint64_t orc_smallest_qnr(uint64_t q);
+/* psi = c^((q-1)/(2N)); returns 0 if 2N does not divide q-1 */
+uint64_t orc_psi(uint64_t q, uint32_t N);
+
+/* --- transforms on one length-N vector, values canonical in [0,q) --------- */
+/* bit_reverse(x): the index permutation used by DIT (before) and DIF (after) */
+void orc_bit_reverse(uint64_t* x, uint32_t N);
+/* forward negacyclic NTT, natural order in and out: twist by psi^j, then the
+ * paper's iterative DIT (Alg. 1, loop bounds read as m = 2^s, k < m/2)       */
+void orc_ntt_forward(uint64_t* x, uint32_t N, uint64_t q, uint64_t psi);
+/* inverse: the paper's DIF (Alg. 2) with omega^-1 twiddles, bit_reverse,
+ * then untwist by psi^-j and scale by N^-1                                   */
+void orc_ntt_inverse(uint64_t* x, uint32_t N, uint64_t q, uint64_t psi);
+/* O(N^2) direct evaluation of the definition (the pin for the two above)    */
+void orc_ntt_direct(const uint64_t* x, uint64_t* X, uint32_t N, uint64_t q, uint64_t psi);
+/* single outputs of the definitions, O(N) each: sampled parity at full size */
+uint64_t orc_ntt_direct_coeff(const uint64_t* x, uint32_t N, uint64_t q, uint64_t psi, uint32_t k);
+uint64_t orc_intt_direct_coeff(const uint64_t* X, uint32_t N, uint64_t q, uint64_t psi, uint32_t j);
+/* pointwise product Z_k = X_k Y_k mod q                                     */
+void orc_pointwise(const uint64_t* a, const uint64_t* b, uint64_t* c, uint32_t N, uint64_t q);
+/* negacyclic schoolbook product mod (x^N + 1, q), O(N^2), and one output     */
+void orc_negacyclic_mul(const uint64_t* a, const uint64_t* b, uint64_t* c, uint32_t N, uint64_t q);
+uint64_t orc_negacyclic_coeff(const uint64_t* a, const uint64_t* b, uint32_t N, uint64_t q, uint32_t k);
+
+/* --- batched drivers over a row-major [B][L][N] array (limb l uses q[l]) ---
+ * nthreads <= 0 means all OpenMP threads; returns the thread count used.    */
+int orc_ntt_forward_batch(uint64_t* x, uint32_t B, uint32_t L, uint32_t N,
+                          const uint64_t* q, const uint64_t* psi, int nthreads);
+int orc_ntt_inverse_batch(uint64_t* x, uint32_t B, uint32_t L, uint32_t N,
+                          const uint64_t* q, const uint64_t* psi, int nthreads);
+int orc_pointwise_batch(const uint64_t* a, const uint64_t* b, uint64_t* c, uint32_t B,
+                        uint32_t L, uint32_t N, const uint64_t* q, int nthreads);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
