@@ -1,0 +1,124 @@
+/*
+ * ntt.h -- C ABI of the MI355X negacyclic NTT library (libntt.so).
+ *
+ * What is computed (NTTSuite, "Twiddle Factors" paragraph, Eq. 1 and 3, with
+ * the negacyclic twist and the inverse made explicit):
+ *   psi_l     = c^((q_l - 1) / 2N), c the smallest quadratic non-residue mod q_l
+ *               (a primitive 2N-th root of unity; the paper leaves g unnamed)
+ *   forward   X_k = sum_{j<N} x_j psi^((2k+1) j)          mod q_l,  k = 0..N-1
+ *   inverse   x_j = N^-1 psi^-j sum_{k<N} X_k psi^(-2jk)   mod q_l
+ *   pointwise Z_k = X_k Y_k                                mod q_l
+ * so that inverse(pointwise(forward(a), forward(b))) is the product of a and b
+ * in Z_q[x]/(x^N + 1). Results are exact (integer arithmetic); every output is
+ * canonical in [0, q_l).
+ *
+ * Data layout: contiguous row-major [batch][L][N] words, limb l of every
+ * polynomial reduced mod moduli[l]. Words are uint64_t, or uint32_t for plans
+ * created with NTT_WORD32. The spectrum is in natural order k = 0..N-1 unless
+ * the plan has NTT_ORDER_BITREV, in which case position i holds X[brv(i)]
+ * (brv reverses log2(N) bits); inverse() consumes the order forward()
+ * produces, and pointwise() works in either.
+ *
+ * Ownership: the caller owns every data buffer (device pointers, e.g. from
+ * hipMalloc or a framework tensor) and the stream. A plan owns its device
+ * twiddle tables (about 16N bytes per limb and direction for 64-bit words)
+ * and, for natural-order spectra with N >= 2^15, a scratch buffer of
+ * batch*L*N words per stream it is used on; ntt_plan_destroy frees both.
+ * Plans live on the device that was current when they were created.
+ *
+ * Asynchrony and errors: ntt_forward / ntt_inverse / ntt_pointwise_mul only
+ * enqueue work on `stream` (a hipStream_t; NULL is the default stream) and
+ * return NTT_OK; argument errors are detected before anything is enqueued and
+ * returned as negative codes. Inputs must be canonical (in [0, q_l)); other
+ * values give unspecified (but in-bounds) results. The functions are
+ * thread-safe for concurrent use of one plan on different streams.
+ */
+#ifndef NTT_H
+#define NTT_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define NTT_OK 0
+#define NTT_ERR_ARG (-1)         /* null pointer, zero count, unknown flag     */
+#define NTT_ERR_N (-2)           /* N not a power of two in [2, 2^17]          */
+#define NTT_ERR_MODULUS (-3)     /* q not prime, 2N does not divide q-1, or q  */
+                                 /* too large (>= 2^61; >= 2^30 with WORD32)   */
+#define NTT_ERR_NOMEM (-4)       /* device or host allocation failed           */
+#define NTT_ERR_HIP (-5)         /* a HIP call or kernel launch failed         */
+#define NTT_ERR_BUDGET (-6)      /* server: job larger than the whole budget   */
+#define NTT_ERR_UNSUPPORTED (-7) /* no kernel for this shape/variant           */
+#define NTT_ERR_STATE (-8)       /* unknown ticket, or object shut down        */
+#define NTT_ERR_TIMEOUT (-9)     /* wait timed out; the job is still pending   */
+
+/* ---- plan flags ---------------------------------------------------------- */
+#define NTT_WORD32 0x1u          /* uint32_t words, every q_l < 2^30            */
+#define NTT_ORDER_BITREV 0x2u    /* spectrum in bit-reversed order              */
+
+/* ---- kernel variants (for tuning and measurement) ------------------------- */
+#define NTT_PATH_AUTO 0          /* library default for (N, word)               */
+#define NTT_PATH_TINY 1          /* N < 16: one thread per transform            */
+#define NTT_PATH_LDS 2           /* whole transform in one workgroup's LDS      */
+#define NTT_PATH_FOURSTEP 3      /* column pass + row pass (N = N1 x N2)        */
+
+typedef struct ntt_plan ntt_plan;
+
+/* Create a plan for length N = 2^n (2 <= N <= 2^17) and L moduli. Each modulus
+ * must be prime with 2N | q-1 and q < 2^61 (q < 2^30 with NTT_WORD32); the
+ * array is copied. Computes psi_l, the twiddle tables and their Shoup
+ * companions floor(w * 2^64 / q) (the paper's tw_h, Alg. 5) on the host and
+ * uploads them. Synchronous. Returns NULL on error (see ntt_last_error). */
+ntt_plan* ntt_plan_create(uint32_t N, const uint64_t* moduli, uint32_t L);
+
+/* As ntt_plan_create with NTT_* flags and optional per-limb roots: psi may be
+ * NULL (default root above) or L values, each a primitive 2N-th root of unity
+ * mod q_l (checked: psi^N == q_l - 1). */
+ntt_plan* ntt_plan_create_ex(uint32_t N, const uint64_t* moduli, uint32_t L, uint32_t flags,
+                             const uint64_t* psi);
+
+void ntt_plan_destroy(ntt_plan* plan);
+
+/* Forward negacyclic NTT of `batch` polynomials, in place on d_data
+ * ([batch][L][N] words on the plan's device). Asynchronous on stream. */
+int ntt_forward(const ntt_plan* plan, void* d_data, uint32_t batch, void* stream);
+
+/* Inverse NTT (including the N^-1 scaling), in place. Asynchronous. */
+int ntt_inverse(const ntt_plan* plan, void* d_data, uint32_t batch, void* stream);
+
+/* d_c = d_a * d_b elementwise mod q_l over [batch][L][N]; d_c may alias d_a
+ * or d_b (exactly, not partially). Asynchronous. */
+int ntt_pointwise_mul(const ntt_plan* plan, const void* d_a, const void* d_b, void* d_c,
+                      uint32_t batch, void* stream);
+
+/* Plan queries: the root used for each limb (L values) and the variant. */
+int ntt_plan_get_psi(const ntt_plan* plan, uint64_t* psi_out);
+int ntt_plan_get_variant(const ntt_plan* plan, int* path, int* log_n1);
+
+/* Select the kernel variant of a plan: path NTT_PATH_*, and for
+ * NTT_PATH_FOURSTEP the column length 2^log_n1 (6 <= log_n1, log2(N)-log_n1
+ * <= 9). Not safe while other threads use the plan. */
+int ntt_plan_set_variant(ntt_plan* plan, int path, int log_n1);
+
+/* Quotient flavour of the 64-bit Shoup product: 0 (default) estimates
+ * floor(y * w' / 2^64) from three of the four 32x32 partial products (off by
+ * at most 2, lazy bound 4q); 1 computes it exactly (lazy bound 2q). Exact is
+ * available on NTT_PATH_FOURSTEP only; kept for measurement. */
+int ntt_plan_set_quotient(ntt_plan* plan, int exact);
+
+/* Scratch a natural-order four-step call of `batch` polynomials needs (bytes;
+ * 0 when the chosen variant works in place). The plan allocates it. */
+size_t ntt_workspace_bytes(const ntt_plan* plan, uint32_t batch);
+
+/* Thread-local code of the last failed call that returns a pointer, and a
+ * static description of any code. */
+int ntt_last_error(void);
+const char* ntt_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NTT_H */

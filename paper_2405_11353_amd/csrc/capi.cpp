@@ -1,0 +1,309 @@
+// C ABI of libntt.so: plans (parameters and resident twiddle tables),
+// argument checking, variant dispatch and per-stream scratch.
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "launch.hpp"
+#include "ntt.h"
+#include "params.hpp"
+
+namespace {
+thread_local int g_last_error = NTT_OK;
+
+int fail(int code) {
+  g_last_error = code;
+  return code;
+}
+
+struct ScratchSlot {
+  void* stream;
+  void* ptr;
+  size_t bytes;
+};
+}  // namespace
+
+struct ntt_plan {
+  uint32_t N = 0, logN = 0, L = 0, flags = 0;
+  int word = 64;
+  int device = 0;
+  std::vector<uint64_t> moduli, psi;
+  void* d_tw_fwd = nullptr;
+  void* d_tw_inv = nullptr;
+  void* d_mod = nullptr;
+  int path = NTT_PATH_LDS;
+  int logN1 = 0;
+  int exact = 0;
+  std::mutex mu;  // guards scratch
+  std::vector<ScratchSlot> scratch;
+};
+
+static int ilog2(uint32_t N) {
+  int l = 0;
+  while ((1u << l) < N) ++l;
+  return l;
+}
+
+static bool variant_ok(const ntt_plan* p, int path, int logN1, int exact) {
+  using namespace nttk;
+  const int lg = (int)p->logN;
+  switch (path) {
+    case NTT_PATH_TINY: return shape_supported(p->word, exact, PATH_TINY, lg, 0);
+    case NTT_PATH_LDS: return shape_supported(p->word, exact, PATH_LDS, lg, 0);
+    case NTT_PATH_FOURSTEP: return shape_supported(p->word, exact, PATH_TWO, lg, logN1);
+    default: return false;
+  }
+}
+
+static void default_variant(ntt_plan* p) {
+  const int lg = (int)p->logN;
+  p->exact = 0;
+  if (lg <= 3) {
+    p->path = NTT_PATH_TINY;
+  } else if (lg <= (p->word == 32 ? 14 : 13)) {
+    p->path = NTT_PATH_LDS;
+  } else {
+    p->path = NTT_PATH_FOURSTEP;
+    p->logN1 = lg / 2;
+  }
+}
+
+static void release(ntt_plan* p) {
+  if (!p) return;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(p->device);
+  for (auto& s : p->scratch)
+    if (s.ptr) (void)hipFree(s.ptr);
+  if (p->d_tw_fwd) (void)hipFree(p->d_tw_fwd);
+  if (p->d_tw_inv) (void)hipFree(p->d_tw_inv);
+  if (p->d_mod) (void)hipFree(p->d_mod);
+  (void)hipSetDevice(cur);
+  delete p;
+}
+
+extern "C" {
+
+int ntt_last_error(void) { return g_last_error; }
+
+const char* ntt_strerror(int code) {
+  switch (code) {
+    case NTT_OK: return "ok";
+    case NTT_ERR_ARG: return "invalid argument";
+    case NTT_ERR_N: return "N must be a power of two in [2, 2^17]";
+    case NTT_ERR_MODULUS: return "modulus is not prime, 2N does not divide q-1, or q is too large for the word size";
+    case NTT_ERR_NOMEM: return "out of memory";
+    case NTT_ERR_HIP: return "HIP runtime or kernel launch error";
+    case NTT_ERR_BUDGET: return "job larger than the memory budget";
+    case NTT_ERR_UNSUPPORTED: return "no kernel for this shape or variant";
+    case NTT_ERR_STATE: return "unknown ticket or object shut down";
+    case NTT_ERR_TIMEOUT: return "timed out";
+    default: return "unknown error";
+  }
+}
+
+ntt_plan* ntt_plan_create_ex(uint32_t N, const uint64_t* moduli, uint32_t L, uint32_t flags,
+                             const uint64_t* psi) {
+  g_last_error = NTT_OK;
+  if (!moduli || L == 0 || (flags & ~(NTT_WORD32 | NTT_ORDER_BITREV))) {
+    fail(NTT_ERR_ARG);
+    return nullptr;
+  }
+  if (N < 2 || N > (1u << 17) || (N & (N - 1))) {
+    fail(NTT_ERR_N);
+    return nullptr;
+  }
+  const int word = (flags & NTT_WORD32) ? 32 : 64;
+  const uint64_t qmax = word == 32 ? (1ull << 30) : (1ull << 61);
+  std::vector<uint64_t> roots(L);
+  for (uint32_t l = 0; l < L; ++l) {
+    const uint64_t q = moduli[l];
+    if (q < 3 || q >= qmax || (q - 1) % (2ull * N) || !nttp::is_prime(q)) {
+      fail(NTT_ERR_MODULUS);
+      return nullptr;
+    }
+    if (psi) {
+      const uint64_t r = psi[l];
+      if (r == 0 || r >= q || nttp::powmod(r, N, q) != q - 1) {
+        fail(NTT_ERR_ARG);
+        return nullptr;
+      }
+      roots[l] = r;
+    } else {
+      roots[l] = nttp::default_psi(q, N);
+      if (!roots[l]) {
+        fail(NTT_ERR_MODULUS);
+        return nullptr;
+      }
+    }
+  }
+  ntt_plan* p = new (std::nothrow) ntt_plan;
+  if (!p) {
+    fail(NTT_ERR_NOMEM);
+    return nullptr;
+  }
+  p->N = N;
+  p->logN = (uint32_t)ilog2(N);
+  p->L = L;
+  p->flags = flags;
+  p->word = word;
+  p->moduli.assign(moduli, moduli + L);
+  p->psi = roots;
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    release(p);
+    fail(NTT_ERR_HIP);
+    return nullptr;
+  }
+  default_variant(p);
+
+  const size_t tw_bytes = (size_t)N * nttp::tw_entry_bytes(word);
+  const size_t mod_bytes = nttp::modinfo_bytes(word);
+  std::vector<unsigned char> fwd(tw_bytes * L), inv(tw_bytes * L), mod(mod_bytes * L);
+  for (uint32_t l = 0; l < L; ++l) {
+    nttp::twiddles(moduli[l], roots[l], p->logN, word, false, fwd.data() + l * tw_bytes);
+    nttp::twiddles(moduli[l], roots[l], p->logN, word, true, inv.data() + l * tw_bytes);
+    nttp::modinfo(moduli[l], word, mod.data() + l * mod_bytes);
+  }
+  if (hipMalloc(&p->d_tw_fwd, fwd.size()) != hipSuccess || hipMalloc(&p->d_tw_inv, inv.size()) != hipSuccess ||
+      hipMalloc(&p->d_mod, mod.size()) != hipSuccess) {
+    release(p);
+    fail(NTT_ERR_NOMEM);
+    return nullptr;
+  }
+  if (hipMemcpy(p->d_tw_fwd, fwd.data(), fwd.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(p->d_tw_inv, inv.data(), inv.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(p->d_mod, mod.data(), mod.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    release(p);
+    fail(NTT_ERR_HIP);
+    return nullptr;
+  }
+  return p;
+}
+
+ntt_plan* ntt_plan_create(uint32_t N, const uint64_t* moduli, uint32_t L) {
+  return ntt_plan_create_ex(N, moduli, L, 0, nullptr);
+}
+
+void ntt_plan_destroy(ntt_plan* plan) { release(plan); }
+
+int ntt_plan_get_psi(const ntt_plan* p, uint64_t* out) {
+  if (!p || !out) return NTT_ERR_ARG;
+  memcpy(out, p->psi.data(), p->L * sizeof(uint64_t));
+  return NTT_OK;
+}
+
+int ntt_plan_get_variant(const ntt_plan* p, int* path, int* log_n1) {
+  if (!p) return NTT_ERR_ARG;
+  if (path) *path = p->path;
+  if (log_n1) *log_n1 = p->path == NTT_PATH_FOURSTEP ? p->logN1 : 0;
+  return NTT_OK;
+}
+
+int ntt_plan_set_variant(ntt_plan* p, int path, int log_n1) {
+  if (!p) return NTT_ERR_ARG;
+  if (path == NTT_PATH_AUTO) {
+    default_variant(p);
+    return NTT_OK;
+  }
+  if (!variant_ok(p, path, log_n1, 0)) return NTT_ERR_UNSUPPORTED;
+  p->path = path;
+  p->logN1 = path == NTT_PATH_FOURSTEP ? log_n1 : 0;
+  p->exact = 0;
+  return NTT_OK;
+}
+
+int ntt_plan_set_quotient(ntt_plan* p, int exact) {
+  if (!p || p->word != 64) return NTT_ERR_ARG;
+  if (!variant_ok(p, p->path, p->logN1, exact ? 1 : 0)) return NTT_ERR_UNSUPPORTED;
+  p->exact = exact ? 1 : 0;
+  return NTT_OK;
+}
+
+size_t ntt_workspace_bytes(const ntt_plan* p, uint32_t batch) {
+  if (!p || p->path != NTT_PATH_FOURSTEP || (p->flags & NTT_ORDER_BITREV)) return 0;
+  return ((size_t)batch * p->L << p->logN) * (p->word / 8);
+}
+
+}  // extern "C"
+
+// scratch for one stream, grown on demand (the stream is drained before an
+// old buffer is released, since kernels queued on it may still use it)
+static int get_scratch(ntt_plan* p, void* stream, size_t bytes, void** out) {
+  std::lock_guard<std::mutex> g(p->mu);
+  for (auto& s : p->scratch) {
+    if (s.stream != stream) continue;
+    if (s.bytes >= bytes) {
+      *out = s.ptr;
+      return NTT_OK;
+    }
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return NTT_ERR_HIP;
+    (void)hipFree(s.ptr);
+    s.ptr = nullptr;
+    s.bytes = 0;
+    if (hipMalloc(&s.ptr, bytes) != hipSuccess) return NTT_ERR_NOMEM;
+    s.bytes = bytes;
+    *out = s.ptr;
+    return NTT_OK;
+  }
+  void* ptr = nullptr;
+  if (hipMalloc(&ptr, bytes) != hipSuccess) return NTT_ERR_NOMEM;
+  p->scratch.push_back({stream, ptr, bytes});
+  *out = ptr;
+  return NTT_OK;
+}
+
+static int check_common(const ntt_plan* p, uint32_t batch) {
+  if (!p || batch == 0) return NTT_ERR_ARG;
+  if ((uint64_t)batch * p->L > 0xFFFFFFFFull / 64) return NTT_ERR_ARG;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return NTT_ERR_HIP;
+  if (dev != p->device) return NTT_ERR_ARG;
+  return NTT_OK;
+}
+
+static int run_ntt(const ntt_plan* pc, void* data, uint32_t batch, void* stream, bool fwd) {
+  int rc = check_common(pc, batch);
+  if (rc != NTT_OK) return rc;
+  if (!data) return NTT_ERR_ARG;
+  ntt_plan* p = const_cast<ntt_plan*>(pc);
+  nttk::Launch c;
+  c.word = p->word;
+  c.exact = p->exact;
+  c.path = p->path == NTT_PATH_TINY ? nttk::PATH_TINY : p->path == NTT_PATH_LDS ? nttk::PATH_LDS : nttk::PATH_TWO;
+  c.logN = (int)p->logN;
+  c.logN1 = p->logN1;
+  c.natural = (p->flags & NTT_ORDER_BITREV) ? 0 : 1;
+  c.data = data;
+  c.tw = fwd ? p->d_tw_fwd : p->d_tw_inv;
+  c.mods = p->d_mod;
+  c.L = p->L;
+  c.batch = batch;
+  c.items = batch * p->L;
+  c.stream = (hipStream_t)stream;
+  if (c.path == nttk::PATH_TWO && c.natural) {
+    rc = get_scratch(p, stream, ntt_workspace_bytes(p, batch), &c.scratch);
+    if (rc != NTT_OK) return rc;
+  }
+  const hipError_t e = nttk::launch_ntt(c, fwd);
+  if (e == hipErrorNotSupported) return NTT_ERR_UNSUPPORTED;
+  return e == hipSuccess ? NTT_OK : NTT_ERR_HIP;
+}
+
+extern "C" {
+
+int ntt_forward(const ntt_plan* p, void* d, uint32_t batch, void* stream) { return run_ntt(p, d, batch, stream, true); }
+int ntt_inverse(const ntt_plan* p, void* d, uint32_t batch, void* stream) { return run_ntt(p, d, batch, stream, false); }
+
+int ntt_pointwise_mul(const ntt_plan* p, const void* a, const void* b, void* c, uint32_t batch, void* stream) {
+  int rc = check_common(p, batch);
+  if (rc != NTT_OK) return rc;
+  if (!a || !b || !c) return NTT_ERR_ARG;
+  const hipError_t e = nttk::launch_pointwise(p->word, a, b, c, p->d_mod, p->L, p->logN, batch * p->L,
+                                              (hipStream_t)stream);
+  return e == hipSuccess ? NTT_OK : NTT_ERR_HIP;
+}
+
+}  // extern "C"

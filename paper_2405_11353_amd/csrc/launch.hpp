@@ -1,0 +1,52 @@
+// Internal launch interface between the C ABI (host C++) and the kernel
+// translation units. Not part of the public header.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nttk {
+
+enum Path { PATH_TINY = 0, PATH_LDS = 1, PATH_TWO = 2 };
+
+struct Launch {
+  int word = 64;      // 32 or 64-bit coefficients
+  int exact = 0;      // 64-bit: exact Shoup quotient (lazy bound 2q) instead of approx (4q)
+  int path = PATH_LDS;
+  int logN = 0;
+  int logN1 = 0;      // PATH_TWO: column length 2^logN1, row length 2^(logN-logN1)
+  int natural = 1;    // natural-order spectrum (else bit-reversed)
+  void* data = nullptr;
+  void* scratch = nullptr;  // PATH_TWO with natural order: items << logN words
+  const void* tw = nullptr; // [L][N] twiddle pairs of the direction being run
+  const void* mods = nullptr;
+  uint32_t L = 0, items = 0, batch = 0;  // items = batch * L
+  hipStream_t stream = nullptr;
+};
+
+// Each returns hipErrorNotSupported for a shape it has no kernel for.
+hipError_t launch_u64(const Launch& c, bool forward);
+hipError_t launch_u64x(const Launch& c, bool forward);
+hipError_t launch_u32(const Launch& c, bool forward);
+hipError_t launch_pointwise(int word, const void* a, const void* b, void* out, const void* mods,
+                            uint32_t L, uint32_t logN, uint32_t items, hipStream_t s);
+
+inline hipError_t launch_ntt(const Launch& c, bool forward) {
+  if (c.word == 32) return launch_u32(c, forward);
+  return c.exact ? launch_u64x(c, forward) : launch_u64(c, forward);
+}
+
+// shape support, kept next to the instantiation lists in the .hip files
+constexpr int kTwoPassMinLog = 6, kTwoPassMaxLog = 9;
+inline int lds_max_logn(int word) { return word == 32 ? 15 : 14; }
+inline bool shape_supported(int word, int exact, int path, int logN, int logN1) {
+  if (path == PATH_TINY) return !exact && logN >= 1 && logN <= 3;
+  if (path == PATH_LDS) return !exact && logN >= 4 && logN <= lds_max_logn(word);
+  if (path == PATH_TWO) {
+    const int logN2 = logN - logN1;
+    return logN1 >= kTwoPassMinLog && logN1 <= kTwoPassMaxLog && logN2 >= kTwoPassMinLog &&
+           logN2 <= kTwoPassMaxLog;
+  }
+  return false;
+}
+
+}  // namespace nttk

@@ -1,0 +1,208 @@
+// Modular arithmetic for the gfx950 NTT kernels.
+//
+// The multiply-by-twiddle is Shoup's precomputed-quotient product (the paper's
+// modulo_mult, Alg. 5, with tw_h = floor(tw * 2^w / q)), here at w = 64 built
+// from 32-bit integer operations, and at w = 32 for moduli below 2^30. The
+// add/sub of each butterfly follows modulo_add (Alg. 4) but keeps values in a
+// lazy range [0, k*q) and reduces with one conditional subtraction of a
+// multiple of q, as in Harvey's NTT butterflies; results are made canonical
+// once, before they are stored.
+//
+// Measured on MI355X: v_mul_lo/hi_u32 and v_mad_u64_u32 issue at the same rate
+// as 64-bit adds and compares (about one wave instruction per 4 clocks per
+// SIMD), so the cost of a butterfly is its instruction count. The "approx"
+// quotient below saves the lowest 32x32 partial product and two carries.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nttk {
+
+// ---------------------------------------------------------------- 64-bit
+struct ModInfo64 {
+  uint64_t q;     // modulus, q < 2^62
+  uint64_t rsv;   // reserved (the lazy bound 4q or 2q is derived from the flavour)
+  uint64_t nq;    // 2^64 - q, so that lo64(Q*q) is subtracted by an add
+  uint64_t qinv;  // q^-1 mod 2^64 (Montgomery reduction in the pointwise product)
+  uint64_t r1;    // 2^64 mod q
+  uint64_t r1p;   // floor(r1 * 2^64 / q), Shoup companion of r1
+  uint64_t pad0, pad1;
+};
+
+struct Tw64 {
+  uint64_t w;   // twiddle in [0, q)
+  uint64_t wp;  // floor(w * 2^64 / q)
+};
+
+__device__ __forceinline__ uint32_t lo32(uint64_t x) { return (uint32_t)x; }
+__device__ __forceinline__ uint32_t hi32(uint64_t x) { return (uint32_t)(x >> 32); }
+__device__ __forceinline__ uint64_t mad32(uint32_t a, uint32_t b, uint64_t c) {
+  return (uint64_t)a * b + c;  // v_mad_u64_u32
+}
+
+// Quotient estimate floor(y * wp / 2^64) minus 0, 1 or 2: drops the low half
+// of the two cross products and the whole low product (each < 2^64 in weight,
+// so the sum dropped is < 3 * 2^64).
+__device__ __forceinline__ uint64_t shoup_q_approx(uint64_t y, uint64_t wp) {
+  uint32_t y0 = lo32(y), y1 = hi32(y), p0 = lo32(wp), p1 = hi32(wp);
+  uint64_t s = (uint64_t)__umulhi(y1, p0) + __umulhi(y0, p1);
+  return mad32(y1, p1, s);
+}
+// Exact high half of y * wp.
+__device__ __forceinline__ uint64_t shoup_q_exact(uint64_t y, uint64_t wp) {
+  uint32_t y0 = lo32(y), y1 = hi32(y), p0 = lo32(wp), p1 = hi32(wp);
+  uint64_t t = mad32(y1, p0, __umulhi(y0, p0));
+  uint64_t u = mad32(y0, p1, lo32(t));
+  return mad32(y1, p1, (uint64_t)hi32(t) + hi32(u));
+}
+// r = y*w - Q*q mod 2^64, computed as y*w + Q*(2^64 - q): the true value is
+// below 2^64 whenever Q is one of the estimates above.
+__device__ __forceinline__ uint64_t shoup_r(uint64_t y, uint64_t w, uint64_t Q, uint64_t nq) {
+  uint32_t y0 = lo32(y), y1 = hi32(y), w0 = lo32(w), w1 = hi32(w);
+  uint32_t Q0 = lo32(Q), Q1 = hi32(Q), n0 = lo32(nq), n1 = hi32(nq);
+  uint64_t lo = mad32(Q0, n0, mad32(y0, w0, 0));
+  uint32_t hi = hi32(lo) + y1 * w0 + y0 * w1 + Q1 * n0 + Q0 * n1;
+  return ((uint64_t)hi << 32) | lo32(lo);
+}
+
+template <bool EXACT>
+struct Arith64 {
+  using word = uint64_t;
+  using tw_t = Tw64;
+  static constexpr bool kExact = EXACT;
+  uint64_t q, L, nq;
+
+  __device__ __forceinline__ void load(const ModInfo64& m) { q = m.q; L = EXACT ? 2 * m.q : 4 * m.q; nq = m.nq; }
+
+  // y * w mod q, result in [0, L) (L = 4q approx, 2q exact), any y < 2^64
+  __device__ __forceinline__ uint64_t mul(uint64_t y, const Tw64& t) const {
+    uint64_t Q = EXACT ? shoup_q_exact(y, t.wp) : shoup_q_approx(y, t.wp);
+    return shoup_r(y, t.w, Q, nq);
+  }
+  __device__ __forceinline__ static uint64_t csub(uint64_t x, uint64_t m) { return x >= m ? x - m : x; }
+
+  // Cooley-Tukey butterfly (x, y) -> (x + w y, x - w y); values in [0, 2L)
+  __device__ __forceinline__ void ct(uint64_t& x, uint64_t& y, const Tw64& t) const {
+    uint64_t xr = csub(x, L);
+    uint64_t T = mul(y, t);
+    x = xr + T;
+    y = xr + L - T;
+  }
+  // Gentleman-Sande butterfly (x, y) -> (x + y, (x - y) w); values in [0, L)
+  __device__ __forceinline__ void gs(uint64_t& x, uint64_t& y, const Tw64& t) const {
+    uint64_t s = x + y;
+    uint64_t d = x + L - y;
+    x = csub(s, L);
+    y = mul(d, t);
+  }
+  // last inverse stage: both outputs scaled (N^-1 folded into two twiddles)
+  __device__ __forceinline__ void gs_last(uint64_t& x, uint64_t& y, const Tw64& t0, const Tw64& t1) const {
+    uint64_t s = x + y;
+    uint64_t d = x + L - y;
+    x = mul(s, t0);
+    y = mul(d, t1);
+  }
+  // canonical from [0, 2L) (forward) or [0, L) (inverse)
+  __device__ __forceinline__ uint64_t canon_fwd(uint64_t x) const {
+    x = csub(x, L);
+    if (!EXACT) x = csub(x, 2 * q);
+    return csub(x, q);
+  }
+  __device__ __forceinline__ uint64_t canon_inv(uint64_t x) const {
+    if (!EXACT) x = csub(x, 2 * q);
+    return csub(x, q);
+  }
+};
+
+// General product x*y mod q for the pointwise kernel (neither operand known in
+// advance): Montgomery reduction of the 128-bit product gives x*y*2^-64 in
+// (-q, q), then a Shoup product by 2^64 mod q restores the factor.
+__device__ __forceinline__ uint64_t mulmod_general(uint64_t x, uint64_t y, const ModInfo64& m) {
+  uint32_t x0 = lo32(x), x1 = hi32(x), y0 = lo32(y), y1 = hi32(y);
+  // 128-bit product t = th:tl
+  uint64_t p00 = mad32(x0, y0, 0);
+  uint64_t p10 = mad32(x1, y0, hi32(p00));
+  uint64_t p01 = mad32(x0, y1, lo32(p10));
+  uint64_t th = mad32(x1, y1, (uint64_t)hi32(p10) + hi32(p01));
+  uint64_t tl = ((uint64_t)lo32(p01) << 32) | lo32(p00);
+  // u = tl * q^-1 mod 2^64; then t - u*q = 0 mod 2^64 and (t - u*q)/2^64 = th - hi64(u*q)
+  uint32_t u0 = lo32(tl), u1 = hi32(tl), i0 = lo32(m.qinv), i1 = hi32(m.qinv);
+  uint64_t u = mad32(u0, i0, 0);
+  u = ((uint64_t)(hi32(u) + u1 * i0 + u0 * i1) << 32) | lo32(u);
+  uint64_t uq_hi;
+  {
+    uint32_t a0 = lo32(u), a1 = hi32(u), q0 = lo32(m.q), q1 = hi32(m.q);
+    uint64_t s00 = mad32(a0, q0, 0);
+    uint64_t s10 = mad32(a1, q0, hi32(s00));
+    uint64_t s01 = mad32(a0, q1, lo32(s10));
+    uint64_t s11 = mad32(a1, q1, (uint64_t)hi32(s10) + hi32(s01));
+    uq_hi = s11;
+  }
+  uint64_t r = th - uq_hi;            // in (-q, q) as a signed value
+  r = (th < uq_hi) ? r + m.q : r;     // [0, q)
+  // times 2^64 mod q (Shoup, exact quotient): [0, 2q) then canonical
+  uint64_t Q = shoup_q_exact(r, m.r1p);
+  uint64_t z = shoup_r(r, m.r1, Q, m.nq);
+  return z >= m.q ? z - m.q : z;
+}
+
+// ---------------------------------------------------------------- 32-bit
+struct ModInfo32 {
+  uint32_t q;     // q < 2^30
+  uint32_t rsv;   // reserved
+  uint32_t qinv;  // q^-1 mod 2^32
+  uint32_t r1;    // 2^32 mod q
+  uint32_t r1p;   // floor(r1 * 2^32 / q)
+  uint32_t pad[3];
+};
+struct Tw32 {
+  uint32_t w, wp;  // wp = floor(w * 2^32 / q)
+};
+
+struct Arith32 {
+  using word = uint32_t;
+  using tw_t = Tw32;
+  static constexpr bool kExact = true;
+  uint32_t q, L;
+  __device__ __forceinline__ void load(const ModInfo32& m) { q = m.q; L = 2 * m.q; }
+  // Shoup at w = 32 (Alg. 5 with the paper's word size): result in [0, 2q)
+  __device__ __forceinline__ uint32_t mul(uint32_t y, const Tw32& t) const {
+    uint32_t Q = __umulhi(y, t.wp);
+    return y * t.w - Q * q;
+  }
+  __device__ __forceinline__ static uint32_t csub(uint32_t x, uint32_t m) { return x >= m ? x - m : x; }
+  __device__ __forceinline__ void ct(uint32_t& x, uint32_t& y, const Tw32& t) const {
+    uint32_t xr = csub(x, L);
+    uint32_t T = mul(y, t);
+    x = xr + T;
+    y = xr + L - T;
+  }
+  __device__ __forceinline__ void gs(uint32_t& x, uint32_t& y, const Tw32& t) const {
+    uint32_t s = x + y;
+    uint32_t d = x + L - y;
+    x = csub(s, L);
+    y = mul(d, t);
+  }
+  __device__ __forceinline__ void gs_last(uint32_t& x, uint32_t& y, const Tw32& t0, const Tw32& t1) const {
+    uint32_t s = x + y;
+    uint32_t d = x + L - y;
+    x = mul(s, t0);
+    y = mul(d, t1);
+  }
+  __device__ __forceinline__ uint32_t canon_fwd(uint32_t x) const { return csub(csub(x, L), q); }
+  __device__ __forceinline__ uint32_t canon_inv(uint32_t x) const { return csub(x, q); }
+};
+
+__device__ __forceinline__ uint32_t mulmod_general(uint32_t x, uint32_t y, const ModInfo32& m) {
+  uint64_t t = (uint64_t)x * y;
+  uint32_t u = (uint32_t)t * m.qinv;                 // t - u q = 0 mod 2^32
+  uint32_t uq_hi = __umulhi(u, m.q);
+  uint32_t th = (uint32_t)(t >> 32);
+  uint32_t r = th - uq_hi;
+  r = (th < uq_hi) ? r + m.q : r;                    // x y 2^-32 mod q
+  uint32_t Q = __umulhi(r, m.r1p);
+  uint32_t z = r * m.r1 - Q * m.q;                   // [0, 2q)
+  return z >= m.q ? z - m.q : z;
+}
+
+}  // namespace nttk

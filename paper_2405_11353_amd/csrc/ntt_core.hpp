@@ -1,0 +1,467 @@
+// Kernel templates for the negacyclic NTT on gfx950.
+//
+// Transform: the merged-twiddle Cooley-Tukey form of the negacyclic NTT. Stage
+// s (0-based) pairs positions p and p + N/2^(s+1) and multiplies by
+// psi^brv(2^s + (p >> (logN - s))); after logN stages position p holds
+// X[brv(p)], the evaluation at psi^(2 brv(p) + 1). The inverse runs the stages
+// backwards as Gentleman-Sande butterflies with psi^-brv(k), and the factor
+// N^-1 is folded into the two twiddles of the last stage (table slots 0, 1).
+// Compared with the paper's DIT (Alg. 1) the psi^j twist is absorbed into the
+// twiddles and the bit reversal is done by the store, through LDS.
+//
+// Work split: each thread holds 16 values and applies up to 4 stages to them
+// in registers (a "phase"); values are exchanged through LDS between phases.
+// A remainder phase of logN mod 4 stages comes first, so that in every phase
+// the 16 values of a thread sit at a power-of-two stride with the stride of
+// the phase's last stage. Twiddles are read from global memory (L1/L2 hits:
+// the per-limb table is shared by all polynomials of that limb).
+//
+// Kernel shapes:
+//  * k_lds   : the whole transform in one workgroup (N <= 2^14 for 64-bit words)
+//  * k_col/k_row : the four-step split N = N1 x N2 (the paper's six-step idea
+//    without the explicit transposes): the first logN1 stages act on the N2
+//    columns of the N1 x N2 row-major matrix with the shared twiddles
+//    psi^brv(k), k < N1; the last logN2 stages act on each row r with the
+//    twiddles of the subtree under node N1 + r. The natural-order output
+//    position of row element (r, c) is brv(c) * N1 + brv(r), so a tile of 16
+//    rows with consecutive brv(r) is written as 128-byte segments.
+//  * k_tiny  : N < 16, one thread per transform.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "modarith.hpp"
+
+namespace nttk {
+
+// compile-time loops: f(integral_constant<int, k>) for k = B..E-1 / B down to E
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(static_cast<F&&>(f));
+  }
+}
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for_down(F&& f) {
+  if constexpr (B >= E) {
+    f(std::integral_constant<int, B>{});
+    static_for_down<B - 1, E>(static_cast<F&&>(f));
+  }
+}
+
+template <class A> struct ModOf;
+template <bool E> struct ModOf<Arith64<E>> { using type = ModInfo64; };
+template <> struct ModOf<Arith32> { using type = ModInfo32; };
+
+__device__ __forceinline__ uint32_t brv(uint32_t x, uint32_t bits) {
+  return bits ? (__builtin_bitreverse32(x) >> (32 - bits)) : 0u;
+}
+
+// Blocks are dispatched round-robin over the 8 XCDs of the chip; this maps
+// consecutive logical work items onto the same XCD (and so the same L2).
+// A permutation of [0, G) for any G, so correctness does not depend on the
+// hardware's dispatch order.
+__device__ __forceinline__ uint32_t xcd_remap(uint32_t bid, uint32_t G) {
+  const uint32_t x = bid & 7u, i = bid >> 3;
+  const uint32_t q = G >> 3, r = G & 7u;
+  return (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
+// ----------------------------------------------------------- phase schedule
+template <int LOGN> struct Sched {
+  static_assert(LOGN >= 4, "16 values per thread need N >= 16");
+  static constexpr int R0 = LOGN % 4;
+  static constexpr int NPH = LOGN / 4 + (R0 ? 1 : 0);
+  __host__ __device__ static constexpr int rs(int p) { return (R0 && p == 0) ? R0 : 4; }
+  __host__ __device__ static constexpr int s0(int p) { return p == 0 ? 0 : (R0 ? R0 + 4 * (p - 1) : 4 * p); }
+  __host__ __device__ static constexpr int lgs(int p) { return LOGN - s0(p) - 4; }  // log2 of the stride
+};
+
+// position of value i of thread t in phase p (transform-local)
+template <int LOGN>
+__device__ __forceinline__ uint32_t pos(int p, uint32_t t, int i) {
+  const int lg = Sched<LOGN>::lgs(p);
+  const uint32_t H = t >> lg, low = t & ((1u << lg) - 1u);
+  return (H << (lg + 4)) + ((uint32_t)i << lg) + low;
+}
+// group index of thread t at the first stage of phase p (transform-local)
+template <int LOGN>
+__device__ __forceinline__ uint32_t grp(int p, uint32_t t) { return t >> Sched<LOGN>::lgs(p); }
+
+// ----------------------------------------------------------- register phases
+// RS stages starting at global stage S0; Hg = global group index at S0.
+template <class A, int RS>
+__device__ __forceinline__ void ct_phase(const A& a, typename A::word (&v)[16],
+                                         const typename A::tw_t* __restrict__ tw, uint32_t S0, uint32_t Hg) {
+#pragma unroll
+  for (int k = 0; k < RS; ++k) {
+    const typename A::tw_t* tk = tw + (1u << (S0 + k)) + (Hg << k);
+#pragma unroll
+    for (int j = 0; j < (1 << k); ++j) {
+      const typename A::tw_t w = tk[j];
+#pragma unroll
+      for (int m = 0; m < (8 >> k); ++m) {
+        const int i0 = j * (16 >> k) + m;
+        a.ct(v[i0], v[i0 + (8 >> k)], w);
+      }
+    }
+  }
+}
+
+// Inverse: the same pairs, stages in reverse order. HAS0: this phase contains
+// global stage 0, whose two outputs are both scaled (tables slots 0 and 1).
+template <class A, int RS, bool HAS0>
+__device__ __forceinline__ void gs_phase(const A& a, typename A::word (&v)[16],
+                                         const typename A::tw_t* __restrict__ tw, uint32_t S0, uint32_t Hg) {
+#pragma unroll
+  for (int k = RS - 1; k >= 0; --k) {
+    if (HAS0 && k == 0) {
+      const typename A::tw_t w0 = tw[0], w1 = tw[1];
+#pragma unroll
+      for (int m = 0; m < 8; ++m) a.gs_last(v[m], v[m + 8], w0, w1);
+    } else {
+      const typename A::tw_t* tk = tw + (1u << (S0 + k)) + (Hg << k);
+#pragma unroll
+      for (int j = 0; j < (1 << k); ++j) {
+        const typename A::tw_t w = tk[j];
+#pragma unroll
+        for (int m = 0; m < (8 >> k); ++m) {
+          const int i0 = j * (16 >> k) + m;
+          a.gs(v[i0], v[i0 + (8 >> k)], w);
+        }
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ uint32_t pad16(uint32_t x) { return x + (x >> 4); }
+
+// ordering of LDS traffic inside one wavefront (no workgroup barrier needed)
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ============================================================ k_lds
+// P transforms per workgroup, N/16 threads each, whole transform in LDS.
+template <class A, int LOGN, int P, bool FWD, bool NATURAL>
+__global__ void __launch_bounds__(P << (LOGN - 4))
+k_lds(typename A::word* __restrict__ data, const typename A::tw_t* __restrict__ tw_all,
+      const typename ModOf<A>::type* __restrict__ mods, uint32_t L, uint32_t items) {
+  using W = typename A::word;
+  using S = Sched<LOGN>;
+  constexpr uint32_t N = 1u << LOGN, T = N / 16, SPAN = N + N / 16;
+  __shared__ W lds[P * SPAN];
+  const uint32_t g = threadIdx.x / T, t = threadIdx.x % T;
+  const uint32_t item = blockIdx.x * P + g;
+  const bool valid = item < items;
+  const uint32_t l = valid ? item % L : 0;
+  A a;
+  a.load(mods[l]);
+  const typename A::tw_t* tw = tw_all + ((size_t)l << LOGN);
+  W* x = data + ((size_t)(valid ? item : 0) << LOGN);
+  W* sh = lds + g * SPAN;
+  W v[16];
+  if constexpr (FWD) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = valid ? x[i * T + t] : W(0);
+    static_for<0, S::NPH>([&](auto P_) {
+      constexpr int p = decltype(P_)::value;
+      if constexpr (p > 0) {
+        if constexpr (p > 1) __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 16; ++i) sh[pad16(pos<LOGN>(p - 1, t, i))] = v[i];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 16; ++i) v[i] = sh[pad16(pos<LOGN>(p, t, i))];
+      }
+      ct_phase<A, S::rs(p)>(a, v, tw, S::s0(p), grp<LOGN>(p, t));
+    });
+    if (S::NPH > 1) __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const uint32_t ps = pos<LOGN>(S::NPH - 1, t, i);
+      sh[pad16(NATURAL ? brv(ps, LOGN) : ps)] = a.canon_fwd(v[i]);
+    }
+    __syncthreads();
+    if (valid) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) x[i * T + t] = sh[pad16(i * T + t)];
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const uint32_t m = i * T + t;
+      sh[pad16(NATURAL ? brv(m, LOGN) : m)] = valid ? x[m] : W(0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = sh[pad16(pos<LOGN>(S::NPH - 1, t, i))];
+    static_for_down<S::NPH - 1, 0>([&](auto P_) {
+      constexpr int p = decltype(P_)::value;
+      if constexpr (p < S::NPH - 1) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 16; ++i) sh[pad16(pos<LOGN>(p + 1, t, i))] = v[i];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 16; ++i) v[i] = sh[pad16(pos<LOGN>(p, t, i))];
+      }
+      gs_phase<A, S::rs(p), p == 0>(a, v, tw, S::s0(p), grp<LOGN>(p, t));
+    });
+    if (valid) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) x[i * T + t] = a.canon_inv(v[i]);
+    }
+  }
+}
+
+// ============================================================ column pass
+// NC columns per workgroup, N1/16 threads per column; columns are adjacent so
+// each row segment read or written is NC words (128 bytes).
+// Forward: global stages [0, logN1), out-of-place allowed (in == out is fine).
+// Inverse: global stages [logN1-1 .. 0] with the N^-1 fold, canonical output.
+template <class A, int LOGN1, int NC, bool FWD>
+__global__ void __launch_bounds__(NC << (LOGN1 - 4))
+k_col(const typename A::word* in, typename A::word* out, const typename A::tw_t* __restrict__ tw_all,
+      const typename ModOf<A>::type* __restrict__ mods, uint32_t L, uint32_t logN, uint32_t items) {
+  using W = typename A::word;
+  using S = Sched<LOGN1>;
+  constexpr uint32_t N1 = 1u << LOGN1, TPC = N1 / 16, LD = NC + 1;
+  __shared__ W lds[N1 * LD];
+  const uint32_t N2 = 1u << (logN - LOGN1);
+  const uint32_t tiles = N2 / NC;
+  const uint32_t bid = xcd_remap(blockIdx.x, gridDim.x);
+  const uint32_t tile = bid % tiles, item = bid / tiles;
+  if (item >= items) return;  // whole workgroup leaves together
+  const uint32_t l = item % L;
+  const uint32_t c = threadIdx.x % NC, t = threadIdx.x / NC;
+  A a;
+  a.load(mods[l]);
+  const typename A::tw_t* tw = tw_all + ((size_t)l << logN);
+  const size_t base = ((size_t)item << logN) + tile * NC + c;
+  const W* src = in + base;
+  W* dst = out + base;
+  W v[16];
+  if constexpr (FWD) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = src[(size_t)(i * TPC + t) * N2];
+    static_for<0, S::NPH>([&](auto P_) {
+      constexpr int p = decltype(P_)::value;
+      if constexpr (p > 0) {
+        if constexpr (p > 1) __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 16; ++i) lds[pos<LOGN1>(p - 1, t, i) * LD + c] = v[i];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 16; ++i) v[i] = lds[pos<LOGN1>(p, t, i) * LD + c];
+      }
+      ct_phase<A, S::rs(p)>(a, v, tw, S::s0(p), grp<LOGN1>(p, t));
+    });
+#pragma unroll
+    for (int i = 0; i < 16; ++i) dst[(size_t)pos<LOGN1>(S::NPH - 1, t, i) * N2] = v[i];
+  } else {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = src[(size_t)pos<LOGN1>(S::NPH - 1, t, i) * N2];
+    static_for_down<S::NPH - 1, 0>([&](auto P_) {
+      constexpr int p = decltype(P_)::value;
+      if constexpr (p < S::NPH - 1) {
+        if constexpr (p < S::NPH - 2) __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 16; ++i) lds[pos<LOGN1>(p + 1, t, i) * LD + c] = v[i];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 16; ++i) v[i] = lds[pos<LOGN1>(p, t, i) * LD + c];
+      }
+      gs_phase<A, S::rs(p), p == 0>(a, v, tw, S::s0(p), grp<LOGN1>(p, t));
+    });
+#pragma unroll
+    for (int i = 0; i < 16; ++i) dst[(size_t)(i * TPC + t) * N2] = a.canon_inv(v[i]);
+  }
+}
+
+// ============================================================ row pass
+// 16 rows per workgroup, N2/16 threads per row (a row never spans two waves,
+// so exchanges between phases only need wavefront ordering).
+// Forward: global stages [logN1, logN), canonical output; NATURAL writes
+// element (r, c) to brv(c) * N1 + brv(r) with rows r = brv(k1), k1 in the tile.
+// Inverse: reads that layout (or rows in place), runs the row stages
+// backwards and writes rows in lazy range for the column pass.
+template <class A, int LOGN2, bool FWD, bool NATURAL>
+__global__ void __launch_bounds__(16 << (LOGN2 - 4))
+k_row(const typename A::word* in, typename A::word* out, const typename A::tw_t* __restrict__ tw_all,
+      const typename ModOf<A>::type* __restrict__ mods, uint32_t L, uint32_t logN, uint32_t items,
+      uint32_t batch) {
+  using W = typename A::word;
+  using S = Sched<LOGN2>;
+  constexpr uint32_t N2 = 1u << LOGN2, TPR = N2 / 16, RSTR = N2 + N2 / 16 + 1;
+  static_assert(TPR <= 64, "a row must fit in one wavefront");
+  __shared__ W lds[16 * RSTR];
+  const uint32_t logN1 = logN - LOGN2, N1 = 1u << logN1;
+  const uint32_t tiles = N1 / 16;
+  // logical order (limb, tile, poly): the polynomials sharing a limb's row
+  // twiddles run back to back on one XCD
+  const uint32_t bid = xcd_remap(blockIdx.x, gridDim.x);
+  const uint32_t b = bid % batch, rest = bid / batch;
+  const uint32_t tile = rest % tiles, l = rest / tiles;
+  if (l >= L) return;
+  const uint32_t item = b * L + l;
+  const uint32_t t = threadIdx.x % TPR, rl = threadIdx.x / TPR;
+  const uint32_t k1 = tile * 16 + rl;
+  const uint32_t r = NATURAL ? brv(k1, logN1) : k1;
+  A a;
+  a.load(mods[l]);
+  const typename A::tw_t* tw = tw_all + ((size_t)l << logN);
+  const size_t pbase = (size_t)item << logN;
+  W* sh = lds + rl * RSTR;
+  W v[16];
+  if constexpr (FWD) {
+    const W* src = in + pbase + (size_t)r * N2;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = src[i * TPR + t];
+    static_for<0, S::NPH>([&](auto P_) {
+      constexpr int p = decltype(P_)::value;
+      if constexpr (p > 0) {
+        if constexpr (p > 1) wave_lds_sync();
+#pragma unroll
+        for (int i = 0; i < 16; ++i) sh[pad16(pos<LOGN2>(p - 1, t, i))] = v[i];
+        wave_lds_sync();
+#pragma unroll
+        for (int i = 0; i < 16; ++i) v[i] = sh[pad16(pos<LOGN2>(p, t, i))];
+      }
+      ct_phase<A, S::rs(p)>(a, v, tw, logN1 + S::s0(p), (r << S::s0(p)) + grp<LOGN2>(p, t));
+    });
+    if constexpr (NATURAL) {
+      if (S::NPH > 1) wave_lds_sync();
+#pragma unroll
+      for (int i = 0; i < 16; ++i) sh[pad16(pos<LOGN2>(S::NPH - 1, t, i))] = a.canon_fwd(v[i]);
+      __syncthreads();
+      const uint32_t rr = threadIdx.x % 16, cg = threadIdx.x / 16;
+      W* dst = out + pbase + tile * 16 + rr;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const uint32_t cc = cg + TPR * j;
+        dst[(size_t)brv(cc, LOGN2) * N1] = lds[rr * RSTR + pad16(cc)];
+      }
+    } else {
+      if (S::NPH > 1) wave_lds_sync();
+#pragma unroll
+      for (int i = 0; i < 16; ++i) sh[pad16(pos<LOGN2>(S::NPH - 1, t, i))] = a.canon_fwd(v[i]);
+      wave_lds_sync();
+      W* dst = out + pbase + (size_t)r * N2;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) dst[i * TPR + t] = sh[pad16(i * TPR + t)];
+    }
+  } else {
+    if constexpr (NATURAL) {
+      const uint32_t rr = threadIdx.x % 16, cg = threadIdx.x / 16;
+      const W* src = in + pbase + tile * 16 + rr;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const uint32_t cc = cg + TPR * j;
+        lds[rr * RSTR + pad16(cc)] = src[(size_t)brv(cc, LOGN2) * N1];
+      }
+      __syncthreads();
+    } else {
+      const W* src = in + pbase + (size_t)r * N2;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) sh[pad16(i * TPR + t)] = src[i * TPR + t];
+      wave_lds_sync();
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = sh[pad16(pos<LOGN2>(S::NPH - 1, t, i))];
+    static_for_down<S::NPH - 1, 0>([&](auto P_) {
+      constexpr int p = decltype(P_)::value;
+      if constexpr (p < S::NPH - 1) {
+        wave_lds_sync();
+#pragma unroll
+        for (int i = 0; i < 16; ++i) sh[pad16(pos<LOGN2>(p + 1, t, i))] = v[i];
+        wave_lds_sync();
+#pragma unroll
+        for (int i = 0; i < 16; ++i) v[i] = sh[pad16(pos<LOGN2>(p, t, i))];
+      }
+      gs_phase<A, S::rs(p), false>(a, v, tw, logN1 + S::s0(p), (r << S::s0(p)) + grp<LOGN2>(p, t));
+    });
+    W* dst = out + pbase + (size_t)r * N2;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) dst[i * TPR + t] = v[i];
+  }
+}
+
+// ============================================================ tiny N
+// N in {2, 4, 8}: one thread per transform, the same stage structure.
+template <class A, int LOGN, bool FWD, bool NATURAL>
+__global__ void __launch_bounds__(256)
+k_tiny(typename A::word* __restrict__ data, const typename A::tw_t* __restrict__ tw_all,
+       const typename ModOf<A>::type* __restrict__ mods, uint32_t L, uint32_t items) {
+  using W = typename A::word;
+  constexpr uint32_t N = 1u << LOGN;
+  const uint32_t item = blockIdx.x * blockDim.x + threadIdx.x;
+  if (item >= items) return;
+  const uint32_t l = item % L;
+  A a;
+  a.load(mods[l]);
+  const typename A::tw_t* tw = tw_all + ((size_t)l << LOGN);
+  W* x = data + ((size_t)item << LOGN);
+  W v[N];
+  if constexpr (FWD) {
+#pragma unroll
+    for (uint32_t i = 0; i < N; ++i) v[i] = x[i];
+#pragma unroll
+    for (int s = 0; s < LOGN; ++s) {
+      const uint32_t h = N >> (s + 1);
+#pragma unroll
+      for (uint32_t g = 0; g < (1u << s); ++g) {
+        const typename A::tw_t w = tw[(1u << s) + g];
+#pragma unroll
+        for (uint32_t m = 0; m < h; ++m) a.ct(v[g * 2 * h + m], v[g * 2 * h + m + h], w);
+      }
+    }
+#pragma unroll
+    for (uint32_t i = 0; i < N; ++i) x[NATURAL ? brv(i, LOGN) : i] = a.canon_fwd(v[i]);
+  } else {
+#pragma unroll
+    for (uint32_t i = 0; i < N; ++i) v[i] = x[NATURAL ? brv(i, LOGN) : i];
+#pragma unroll
+    for (int s = LOGN - 1; s >= 0; --s) {
+      const uint32_t h = N >> (s + 1);
+      if (s == 0) {
+        const typename A::tw_t w0 = tw[0], w1 = tw[1];
+#pragma unroll
+        for (uint32_t m = 0; m < h; ++m) a.gs_last(v[m], v[m + h], w0, w1);
+      } else {
+#pragma unroll
+        for (uint32_t g = 0; g < (1u << s); ++g) {
+          const typename A::tw_t w = tw[(1u << s) + g];
+#pragma unroll
+          for (uint32_t m = 0; m < h; ++m) a.gs(v[g * 2 * h + m], v[g * 2 * h + m + h], w);
+        }
+      }
+    }
+#pragma unroll
+    for (uint32_t i = 0; i < N; ++i) x[i] = a.canon_inv(v[i]);
+  }
+}
+
+// ============================================================ pointwise
+// c = a * b mod q_l elementwise over [items][N]; two words per thread per step.
+template <class M, class W>
+__global__ void __launch_bounds__(256)
+k_pointwise(const W* __restrict__ a, const W* __restrict__ b, W* c, const M* __restrict__ mods,
+            uint32_t L, uint32_t logN, size_t n_pairs) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_pairs; i += stride) {
+    const size_t e = 2 * i;
+    const uint32_t l = (uint32_t)((e >> logN) % L);
+    const M m = mods[l];
+    const W a0 = a[e], a1 = a[e + 1], b0 = b[e], b1 = b[e + 1];
+    c[e] = mulmod_general(a0, b0, m);
+    c[e + 1] = mulmod_general(a1, b1, m);
+  }
+}
+
+}  // namespace nttk

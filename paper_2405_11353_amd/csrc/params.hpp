@@ -1,0 +1,30 @@
+// Host-side parameter generation for the GPU library: primality, the root
+// psi, twiddle tables with Shoup companions, per-limb constants. Written
+// independently of the CPU oracle (which the library never links).
+#pragma once
+#include <stdint.h>
+
+#include <vector>
+
+namespace nttp {
+
+uint64_t mulmod(uint64_t a, uint64_t b, uint64_t q);
+uint64_t powmod(uint64_t a, uint64_t e, uint64_t q);
+bool is_prime(uint64_t n);
+// smallest c >= 2 with c^((q-1)/2) == -1 mod q (0 if none below 1000)
+uint64_t smallest_qnr(uint64_t q);
+// psi = c^((q-1)/2N); 0 if 2N does not divide q-1
+uint64_t default_psi(uint64_t q, uint32_t N);
+
+// Twiddle tables, N entries of (w, floor(w * 2^word / q)), word = 64 or 32:
+//  forward: slot k >= 1 holds psi^brv(k), the factor of butterfly group k
+//           (stage floor(log2 k)); slot 0 holds 1 (unused)
+//  inverse: slot k >= 2 holds psi^-brv(k); slot 1 holds psi^(-N/2) * N^-1 and
+//           slot 0 holds N^-1 (the last inverse stage scales both outputs)
+void twiddles(uint64_t q, uint64_t psi, uint32_t logN, int word, bool inverse, void* out);
+// per-limb constants in the layout of nttk::ModInfo64 / ModInfo32
+void modinfo(uint64_t q, int word, void* out);
+size_t tw_entry_bytes(int word);
+size_t modinfo_bytes(int word);
+
+}  // namespace nttp

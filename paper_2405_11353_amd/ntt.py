@@ -1,0 +1,240 @@
+"""ctypes binding of libntt.so with the C ABI's names (include/ntt.h).
+
+Argument marshalling only: every step of a transform runs in the HIP
+kernels. Device buffers are passed as torch tensors (or raw device pointers)
+and streams as torch streams (or raw hipStream_t handles). If the library
+is not built this module raises on first use; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(PKG, "libntt.so")
+
+NTT_OK = 0
+NTT_WORD32 = 0x1
+NTT_ORDER_BITREV = 0x2
+NTT_PATH_AUTO, NTT_PATH_TINY, NTT_PATH_LDS, NTT_PATH_FOURSTEP = 0, 1, 2, 3
+
+_lib = None
+
+
+class NttError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        self.code = code
+        msg = ntt_strerror(code) if _lib is not None else str(code)
+        super().__init__(f"{what}: {msg} ({code})" if what else f"{msg} ({code})")
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def lib() -> ctypes.CDLL:
+    """Load libntt.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError(f"{_LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(_LIB_PATH)
+        vp, u32, u64p, i32, sz = ctypes.c_void_p, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint64), ctypes.c_int, ctypes.c_size_t
+        sig = {
+            "ntt_plan_create": (vp, [u32, u64p, u32]),
+            "ntt_plan_create_ex": (vp, [u32, u64p, u32, u32, u64p]),
+            "ntt_plan_destroy": (None, [vp]),
+            "ntt_forward": (i32, [vp, vp, u32, vp]),
+            "ntt_inverse": (i32, [vp, vp, u32, vp]),
+            "ntt_pointwise_mul": (i32, [vp, vp, vp, vp, u32, vp]),
+            "ntt_plan_get_psi": (i32, [vp, u64p]),
+            "ntt_plan_get_variant": (i32, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+            "ntt_plan_set_variant": (i32, [vp, i32, i32]),
+            "ntt_plan_set_quotient": (i32, [vp, i32]),
+            "ntt_workspace_bytes": (sz, [vp, u32]),
+            "ntt_last_error": (i32, []),
+            "ntt_strerror": (ctypes.c_char_p, [i32]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def ntt_strerror(code: int) -> str:
+    return lib().ntt_strerror(code).decode()
+
+
+def ntt_last_error() -> int:
+    return lib().ntt_last_error()
+
+
+def _u64_array(vals):
+    vals = [int(v) for v in vals]
+    return (ctypes.c_uint64 * len(vals))(*vals)
+
+
+def _ptr(x) -> int:
+    """Device pointer of a tensor (or an int address)."""
+    if isinstance(x, int):
+        return x
+    if hasattr(x, "data_ptr"):
+        if not x.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return x.data_ptr()
+    raise TypeError(f"expected a tensor or a device address, got {type(x)}")
+
+
+def _stream(s) -> int | None:
+    if s is None:
+        try:
+            import torch
+            if torch.cuda.is_available():
+                return torch.cuda.current_stream().cuda_stream
+        except ImportError:  # pragma: no cover
+            pass
+        return None
+    if isinstance(s, int):
+        return s
+    return s.cuda_stream
+
+
+def _check(rc: int, what: str):
+    if rc != NTT_OK:
+        raise NttError(rc, what)
+
+
+# ---- C ABI names ----------------------------------------------------------------
+def ntt_plan_create(N: int, moduli, L: int | None = None) -> int:
+    L = len(moduli) if L is None else L
+    h = lib().ntt_plan_create(N, _u64_array(moduli), L)
+    if not h:
+        raise NttError(ntt_last_error(), "ntt_plan_create")
+    return h
+
+
+def ntt_plan_create_ex(N: int, moduli, L: int | None = None, flags: int = 0, psi=None) -> int:
+    L = len(moduli) if L is None else L
+    h = lib().ntt_plan_create_ex(N, _u64_array(moduli), L, flags, _u64_array(psi) if psi is not None else None)
+    if not h:
+        raise NttError(ntt_last_error(), "ntt_plan_create_ex")
+    return h
+
+
+def ntt_plan_destroy(plan: int) -> None:
+    lib().ntt_plan_destroy(plan)
+
+
+def ntt_forward(plan: int, data, batch: int, stream=None) -> None:
+    _check(lib().ntt_forward(plan, _ptr(data), batch, _stream(stream)), "ntt_forward")
+
+
+def ntt_inverse(plan: int, data, batch: int, stream=None) -> None:
+    _check(lib().ntt_inverse(plan, _ptr(data), batch, _stream(stream)), "ntt_inverse")
+
+
+def ntt_pointwise_mul(plan: int, a, b, c, batch: int, stream=None) -> None:
+    _check(lib().ntt_pointwise_mul(plan, _ptr(a), _ptr(b), _ptr(c), batch, _stream(stream)), "ntt_pointwise_mul")
+
+
+def ntt_plan_get_psi(plan: int, L: int) -> list[int]:
+    out = (ctypes.c_uint64 * L)()
+    _check(lib().ntt_plan_get_psi(plan, out), "ntt_plan_get_psi")
+    return [int(v) for v in out]
+
+
+def ntt_plan_get_variant(plan: int) -> tuple[int, int]:
+    p, n1 = ctypes.c_int(), ctypes.c_int()
+    _check(lib().ntt_plan_get_variant(plan, ctypes.byref(p), ctypes.byref(n1)), "ntt_plan_get_variant")
+    return p.value, n1.value
+
+
+def ntt_plan_set_variant(plan: int, path: int, log_n1: int = 0) -> None:
+    _check(lib().ntt_plan_set_variant(plan, path, log_n1), "ntt_plan_set_variant")
+
+
+def ntt_plan_set_quotient(plan: int, exact: bool) -> None:
+    _check(lib().ntt_plan_set_quotient(plan, 1 if exact else 0), "ntt_plan_set_quotient")
+
+
+def ntt_workspace_bytes(plan: int, batch: int) -> int:
+    return int(lib().ntt_workspace_bytes(plan, batch))
+
+
+# ---- convenience object ------------------------------------------------------
+class Plan:
+    """Owns an ntt_plan*; methods check tensor shape/dtype/device, then call the C ABI."""
+
+    def __init__(self, N: int, moduli, flags: int = 0, psi=None):
+        self.N = int(N)
+        self.moduli = [int(q) for q in moduli]
+        self.L = len(self.moduli)
+        self.flags = flags
+        self.word = 32 if flags & NTT_WORD32 else 64
+        self.handle = ntt_plan_create_ex(self.N, self.moduli, self.L, flags, psi)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            ntt_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def psi(self) -> list[int]:
+        return ntt_plan_get_psi(self.handle, self.L)
+
+    @property
+    def variant(self) -> tuple[int, int]:
+        return ntt_plan_get_variant(self.handle)
+
+    def set_variant(self, path: int, log_n1: int = 0):
+        ntt_plan_set_variant(self.handle, path, log_n1)
+
+    def set_exact_quotient(self, exact: bool):
+        ntt_plan_set_quotient(self.handle, exact)
+
+    def _batch(self, t, batch):
+        if batch is None:
+            n = t.numel()
+            if n % (self.L * self.N):
+                raise ValueError("tensor size is not a multiple of L*N")
+            batch = n // (self.L * self.N)
+        if not t.is_cuda:
+            raise ValueError("tensor must be on the GPU")
+        if t.element_size() * 8 != self.word:
+            raise ValueError(f"tensor words must be {self.word}-bit")
+        if t.numel() < batch * self.L * self.N:
+            raise ValueError("tensor smaller than batch*L*N")
+        return batch
+
+    def forward(self, t, batch=None, stream=None):
+        ntt_forward(self.handle, t, self._batch(t, batch), stream)
+        return t
+
+    def inverse(self, t, batch=None, stream=None):
+        ntt_inverse(self.handle, t, self._batch(t, batch), stream)
+        return t
+
+    def pointwise(self, a, b, out=None, batch=None, stream=None):
+        out = a if out is None else out
+        bt = self._batch(a, batch)
+        self._batch(b, bt)
+        self._batch(out, bt)
+        ntt_pointwise_mul(self.handle, a, b, out, bt, stream)
+        return out
+
+    def workspace_bytes(self, batch: int) -> int:
+        return ntt_workspace_bytes(self.handle, batch)

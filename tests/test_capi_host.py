@@ -1,0 +1,66 @@
+"""The C ABI on the host: the library loads, exports every symbol the header
+declares, and rejects bad arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import seeded_inputs as si
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    names = []
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", fn)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names += re.findall(r"\b(ntt_[a-z0-9_]+)\s*\(", src)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2405_11353_amd as ntt
+    return ntt.lib()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_symbols()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def u64s(vals):
+    return (ctypes.c_uint64 * len(vals))(*vals)
+
+
+def test_plan_argument_validation(lib):
+    q = si.ntt_primes(60, 18, 1)[0]
+    lib.ntt_plan_create_ex.restype = ctypes.c_void_p
+    lib.ntt_plan_create_ex.argtypes = [ctypes.c_uint32, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p]
+    cases = [
+        ((1000, u64s([q]), 1, 0, None), -2),          # N not a power of two
+        ((1 << 18, u64s([q]), 1, 0, None), -2),       # N too large
+        ((1, u64s([q]), 1, 0, None), -2),
+        ((1024, u64s([q + 2]), 1, 0, None), -3),      # not prime
+        ((1024, u64s([q]), 1, 0x1, None), -3),        # too large for 32-bit words
+        ((4096, u64s([12289]), 1, 0, None), -3),      # 2N does not divide q-1
+        ((1024, u64s([(1 << 61) + 1]), 1, 0, None), -3),
+        ((1024, None, 1, 0, None), -1),
+        ((1024, u64s([q]), 0, 0, None), -1),
+        ((1024, u64s([q]), 1, 0x80, None), -1),       # unknown flag
+        ((1024, u64s([q]), 1, 0, u64s([2])), -1),     # not a primitive 2N-th root
+    ]
+    for args, code in cases:
+        assert lib.ntt_plan_create_ex(*args) is None
+        assert lib.ntt_last_error() == code, (args, lib.ntt_last_error())
+
+
+def test_strerror_covers_codes(lib):
+    lib.ntt_strerror.restype = ctypes.c_char_p
+    for c in range(0, -10, -1):
+        assert lib.ntt_strerror(c) and lib.ntt_strerror(c) != b"unknown error"
