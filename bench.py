@@ -1,0 +1,241 @@
+"""Benchmark: negacyclic polynomial product of two ciphertexts, N=2^16, L=24.
+
+One step = forward NTT of 2 ciphertexts x 2 components x 24 limbs (96 NTTs),
+pointwise product of the components (48), inverse NTT of the products (48),
+all through libntt.so on one MI355X. Inputs are seeded synthetic residues,
+resident in HBM before timing; the step rotates over buffer sets totalling
+more than 1 GiB so each step reads data that is not in the 256 MB last-level
+cache. Prints one JSON line (metric, value in NTT/s, roofline of the dominant
+kernel measured with HIP events, per-call baseline, CPU oracle baseline).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0                 # MI355X HBM3E
+INT32_MUL_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # 39.3: one int32 multiply per lane per clock
+MULS_PER_SHOUP = 9                    # 32x32 products in one 64-bit Shoup product (approx quotient)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-per-call", action="store_true")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the NTT batch is independent per (polynomial, limb), "
+              "so more GPUs would shard limbs with no exchange; run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2405_11353_amd as ntt
+    import seeded_inputs as si
+
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    torch.cuda.set_device(0)
+    w = si.workload_polymul_n16()
+    N, moduli, L = w.N, w.moduli, len(w.moduli)
+    polys = 4                                       # 2 ciphertexts x 2 components
+    set_words = polys * L * N
+    set_bytes = set_words * 8
+    n_sets = max(2, math.ceil((1 << 30) / set_bytes))
+    log(f"workload {w.name}: N={N} L={L} polys={polys}; {n_sets} rotating sets of {set_bytes >> 20} MiB")
+
+    host = si.poly_batch(w.seed, polys, moduli, N)  # [4][24][N]: polys 0,1 = ciphertext A, 2,3 = B
+    base = torch.from_numpy(host.view(np.int64)).cuda()
+    sets = [base.clone() for _ in range(n_sets)]
+    plan = ntt.Plan(N, moduli)
+    path, logn1 = plan.variant
+    stream = torch.cuda.current_stream()
+
+    def step(buf):
+        plan.forward(buf, batch=4)
+        a, b = buf[:2], buf[2:]
+        plan.pointwise(a, b, a, batch=2)
+        plan.inverse(a, batch=2)
+
+    # ---- correctness of the timed configuration on one set (vs. an independent
+    # GPU check: forward then inverse must return the input exactly)
+    chk = base.clone()
+    plan.forward(chk, batch=4)
+    plan.inverse(chk, batch=4)
+    torch.cuda.synchronize()
+    assert torch.equal(chk, base), "round trip in the bench configuration is not exact"
+
+    for s in range(args.warmup):
+        step(sets[s % n_sets])
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for s in range(args.steps):
+        step(sets[s % n_sets])
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_wall = (t1 - t0) * 1e3 / args.steps
+    ms_event = e0.elapsed_time(e1) / args.steps
+    ntts_per_step = polys * L + 2 * L               # 96 forward + 48 inverse
+    value = ntts_per_step / (ms_wall / 1e3)
+    log(f"step: {ms_wall * 1e3:.1f} us wall, {ms_event * 1e3:.1f} us events; {value / 1e6:.3f} M NTT/s")
+
+    # ---- per-kernel durations with HIP events on the launch stream
+    def time_kernel(fn, reps):
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        for r in range(3):
+            fn(sets[r % n_sets])
+        torch.cuda.synchronize()
+        evs[0].record(stream)
+        for r in range(reps):
+            fn(sets[r % n_sets])
+        evs[1].record(stream)
+        torch.cuda.synchronize()
+        return evs[0].elapsed_time(evs[1]) / reps * 1e3   # us per launch
+
+    kernels = {}
+    if path == ntt.NTT_PATH_FOURSTEP:
+        logn2 = int(math.log2(N)) - logn1
+        kernels["fwd_col_pass"] = dict(fn=lambda b: plan.forward_stage(b, 0, batch=4), items=polys * L,
+                                       stages=logn1, extra_muls=0, words_in=1, words_out=1)
+        kernels["fwd_row_pass"] = dict(fn=lambda b: plan.forward_stage(b, 1, batch=4), items=polys * L,
+                                       stages=logn2, extra_muls=0, words_in=1, words_out=1)
+        kernels["inv_row_pass"] = dict(fn=lambda b: plan.inverse_stage(b[:2], 0, batch=2), items=2 * L,
+                                       stages=logn2, extra_muls=0, words_in=1, words_out=1)
+        kernels["inv_col_pass"] = dict(fn=lambda b: plan.inverse_stage(b[:2], 1, batch=2), items=2 * L,
+                                       stages=logn1, extra_muls=N // 2, words_in=1, words_out=1)
+    kernels["pointwise"] = dict(fn=lambda b: plan.pointwise(b[:2], b[2:], b[:2], batch=2), items=2 * L,
+                                stages=0, extra_muls=0, words_in=2, words_out=1)
+    per_kernel = {}
+    for name, k in kernels.items():
+        us = time_kernel(k["fn"], args.kernel_reps)
+        bytes_alg = k["items"] * N * 8 * (k["words_in"] + k["words_out"])
+        muls = k["items"] * ((N // 2) * k["stages"] + k["extra_muls"]) * MULS_PER_SHOUP
+        gbs = bytes_alg / (us * 1e-6) / 1e9
+        tops = muls / (us * 1e-6) / 1e12
+        per_kernel[name] = dict(us=round(us, 2), alg_bytes=bytes_alg, alg_int32_muls=muls,
+                                hbm_GBs=round(gbs, 1), hbm_frac=round(gbs / HBM_PEAK_GBS, 4),
+                                mul_TOPs=round(tops, 3), mul_frac=round(tops / INT32_MUL_PEAK_TOPS, 4))
+        log(f"  {name}: {us:.1f} us  {gbs:.0f} GB/s ({gbs / HBM_PEAK_GBS:.1%} HBM)  "
+            f"{tops:.2f} TOP/s int32 mul ({tops / INT32_MUL_PEAK_TOPS:.1%})")
+    # time share per step: forward passes run on 4 polys, inverse on 2
+    dominant = max(per_kernel, key=lambda n: per_kernel[n]["us"])
+    dk = per_kernel[dominant]
+    if dk["mul_frac"] >= dk["hbm_frac"] and dk["alg_int32_muls"] > 0:
+        roofline = {"bound": "alu", "achieved": dk["mul_TOPs"], "peak": round(INT32_MUL_PEAK_TOPS, 2),
+                    "unit": "TOP/s", "frac": dk["mul_frac"], "traffic": None}
+    else:
+        roofline = {"bound": "hbm", "achieved": dk["hbm_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": dk["hbm_frac"], "traffic": None}
+    roofline["kernel"] = dominant
+    roofline["avg_launch_us"] = dk["us"]
+
+    # ---- per-call baseline: the same step as one call per (polynomial, limb)
+    per_call = None
+    if not args.no_per_call:
+        plans = [ntt.Plan(N, [q]) for q in moduli]
+        buf = sets[0]
+
+        def step_per_call(bb):
+            for p in range(polys):
+                for l in range(L):
+                    plans[l].forward(bb[p, l], batch=1)
+            for p in range(2):
+                for l in range(L):
+                    plans[l].pointwise(bb[p, l], bb[p + 2, l], bb[p, l], batch=1)
+                    plans[l].inverse(bb[p, l], batch=1)
+
+        reps = max(3, args.steps // 20)
+        step_per_call(buf)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for r in range(reps):
+            step_per_call(sets[r % n_sets])
+        torch.cuda.synchronize()
+        ms_pc = (time.perf_counter() - t0) * 1e3 / reps
+        per_call = {"ms_per_step": round(ms_pc, 4), "value": round(ntts_per_step / (ms_pc / 1e3), 1),
+                    "unit": "NTT/s", "launches_per_step": polys * L * 2 + 2 * L * 3,
+                    "batched_speedup": round(ms_pc / ms_wall, 2)}
+        log(f"per-call: {ms_pc * 1e3:.1f} us/step, batched speedup {ms_pc / ms_wall:.1f}x")
+        for p_ in plans:
+            p_.close()
+
+    # ---- CPU oracle on a bounded sample of the same step (and a bit-exact
+    # comparison of the GPU's product on that sample)
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        sub = 4                                     # limbs in the sample
+        a = host[:, :sub].copy()
+        ref_in = np.ascontiguousarray(a)
+        done_ntts, t_cpu, threads = 0, 0.0, 0
+        out = None
+        while t_cpu < args.cpu_seconds:
+            t0 = time.perf_counter()
+            spec, threads = oracle.ntt_forward_batch(ref_in, moduli[:sub])
+            prod, _ = oracle.pointwise_batch(spec[:2], spec[2:], moduli[:sub])
+            out, _ = oracle.ntt_inverse_batch(prod, moduli[:sub])
+            t_cpu += time.perf_counter() - t0
+            done_ntts += polys * sub + 2 * sub
+        gpu_buf = base.clone()
+        step(gpu_buf)
+        torch.cuda.synchronize()
+        gpu_out = gpu_buf.cpu().numpy().view(np.uint64).reshape(host.shape)[:2, :sub]
+        exact = bool((gpu_out == out).all())
+        cpu = {"value": round(done_ntts / t_cpu, 2), "unit": "NTT/s", "cores": int(threads), "kind": "oracle",
+               "sample": f"the step restricted to limbs 0..{sub - 1} ({polys * sub} forward + {2 * sub} inverse "
+                         f"NTTs + {2 * sub} pointwise), repeated for {t_cpu:.1f} s; OpenMP over (poly, limb)",
+               "gpu_matches_oracle_on_sample": exact}
+        log(f"cpu oracle: {cpu['value']:.1f} NTT/s on {threads} threads; GPU sample bit-exact: {exact}")
+        assert exact, "GPU result differs from the oracle on the CPU sample"
+
+    res = {
+        "metric": "NTT/s at N=2^16 x 24 limbs (forward + inverse NTTs of a batched 2-ciphertext negacyclic product)",
+        "value": round(value, 1),
+        "unit": "NTT/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_wall, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic: seeded uniform residues mod 24 primes q < 2^60, q = 1 mod 2^17",
+        "config": {"workload": w.name, "N": N, "L": L, "polys": polys, "ntts_per_step": ntts_per_step,
+                   "variant": {"path": "fourstep" if path == ntt.NTT_PATH_FOURSTEP else "lds", "log_n1": logn1},
+                   "rotating_sets": n_sets, "footprint_MiB": n_sets * set_bytes >> 20},
+        "roofline": roofline,
+        "kernels": per_kernel,
+        "per_call": per_call,
+        "cpu_baseline": cpu,
+        "ms_per_step_events": round(ms_event, 5),
+    }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -94,6 +94,14 @@ int ntt_inverse(const ntt_plan* plan, void* d_data, uint32_t batch, void* stream
 int ntt_pointwise_mul(const ntt_plan* plan, const void* d_a, const void* d_b, void* d_c,
                       uint32_t batch, void* stream);
 
+/* One kernel of a four-step transform, for timing and profiling: stage 0 is
+ * the first kernel (forward: column pass, data -> scratch; inverse: row pass,
+ * data -> scratch), stage 1 the second (scratch -> data). Running stage 0 then
+ * stage 1 on the same stream equals ntt_forward / ntt_inverse. Returns
+ * NTT_ERR_UNSUPPORTED unless the plan's variant is NTT_PATH_FOURSTEP. */
+int ntt_forward_stage(const ntt_plan* plan, void* d_data, uint32_t batch, int stage, void* stream);
+int ntt_inverse_stage(const ntt_plan* plan, void* d_data, uint32_t batch, int stage, void* stream);
+
 /* Plan queries: the root used for each limb (L values) and the variant. */
 int ntt_plan_get_psi(const ntt_plan* plan, uint64_t* psi_out);
 int ntt_plan_get_variant(const ntt_plan* plan, int* path, int* log_n1);

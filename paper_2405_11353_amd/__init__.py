@@ -16,7 +16,9 @@ from .ntt import (  # noqa: F401
     lib,
     library_path,
     ntt_forward,
+    ntt_forward_stage,
     ntt_inverse,
+    ntt_inverse_stage,
     ntt_last_error,
     ntt_plan_create,
     ntt_plan_create_ex,

@@ -264,7 +264,7 @@ static int check_common(const ntt_plan* p, uint32_t batch) {
   return NTT_OK;
 }
 
-static int run_ntt(const ntt_plan* pc, void* data, uint32_t batch, void* stream, bool fwd) {
+static int run_ntt(const ntt_plan* pc, void* data, uint32_t batch, void* stream, bool fwd, int stage_mask = 3) {
   int rc = check_common(pc, batch);
   if (rc != NTT_OK) return rc;
   if (!data) return NTT_ERR_ARG;
@@ -283,6 +283,8 @@ static int run_ntt(const ntt_plan* pc, void* data, uint32_t batch, void* stream,
   c.batch = batch;
   c.items = batch * p->L;
   c.stream = (hipStream_t)stream;
+  c.stage_mask = stage_mask;
+  if (stage_mask != 3 && c.path != nttk::PATH_TWO) return NTT_ERR_UNSUPPORTED;
   if (c.path == nttk::PATH_TWO && c.natural) {
     rc = get_scratch(p, stream, ntt_workspace_bytes(p, batch), &c.scratch);
     if (rc != NTT_OK) return rc;
@@ -296,6 +298,15 @@ extern "C" {
 
 int ntt_forward(const ntt_plan* p, void* d, uint32_t batch, void* stream) { return run_ntt(p, d, batch, stream, true); }
 int ntt_inverse(const ntt_plan* p, void* d, uint32_t batch, void* stream) { return run_ntt(p, d, batch, stream, false); }
+
+int ntt_forward_stage(const ntt_plan* p, void* d, uint32_t batch, int stage, void* stream) {
+  if (stage != 0 && stage != 1) return NTT_ERR_ARG;
+  return run_ntt(p, d, batch, stream, true, 1 << stage);
+}
+int ntt_inverse_stage(const ntt_plan* p, void* d, uint32_t batch, int stage, void* stream) {
+  if (stage != 0 && stage != 1) return NTT_ERR_ARG;
+  return run_ntt(p, d, batch, stream, false, 1 << stage);
+}
 
 int ntt_pointwise_mul(const ntt_plan* p, const void* a, const void* b, void* c, uint32_t batch, void* stream) {
   int rc = check_common(p, batch);

@@ -21,6 +21,7 @@ struct Launch {
   const void* mods = nullptr;
   uint32_t L = 0, items = 0, batch = 0;  // items = batch * L
   hipStream_t stream = nullptr;
+  int stage_mask = 3;       // PATH_TWO: bit 0 runs the first kernel, bit 1 the second
 };
 
 // Each returns hipErrorNotSupported for a shape it has no kernel for.

@@ -47,6 +47,8 @@ def lib() -> ctypes.CDLL:
             "ntt_forward": (i32, [vp, vp, u32, vp]),
             "ntt_inverse": (i32, [vp, vp, u32, vp]),
             "ntt_pointwise_mul": (i32, [vp, vp, vp, vp, u32, vp]),
+            "ntt_forward_stage": (i32, [vp, vp, u32, i32, vp]),
+            "ntt_inverse_stage": (i32, [vp, vp, u32, i32, vp]),
             "ntt_plan_get_psi": (i32, [vp, u64p]),
             "ntt_plan_get_variant": (i32, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
             "ntt_plan_set_variant": (i32, [vp, i32, i32]),
@@ -133,6 +135,14 @@ def ntt_forward(plan: int, data, batch: int, stream=None) -> None:
 
 def ntt_inverse(plan: int, data, batch: int, stream=None) -> None:
     _check(lib().ntt_inverse(plan, _ptr(data), batch, _stream(stream)), "ntt_inverse")
+
+
+def ntt_forward_stage(plan: int, data, batch: int, stage: int, stream=None) -> None:
+    _check(lib().ntt_forward_stage(plan, _ptr(data), batch, stage, _stream(stream)), "ntt_forward_stage")
+
+
+def ntt_inverse_stage(plan: int, data, batch: int, stage: int, stream=None) -> None:
+    _check(lib().ntt_inverse_stage(plan, _ptr(data), batch, stage, _stream(stream)), "ntt_inverse_stage")
 
 
 def ntt_pointwise_mul(plan: int, a, b, c, batch: int, stream=None) -> None:
@@ -226,6 +236,14 @@ class Plan:
 
     def inverse(self, t, batch=None, stream=None):
         ntt_inverse(self.handle, t, self._batch(t, batch), stream)
+        return t
+
+    def forward_stage(self, t, stage: int, batch=None, stream=None):
+        ntt_forward_stage(self.handle, t, self._batch(t, batch), stage, stream)
+        return t
+
+    def inverse_stage(self, t, stage: int, batch=None, stream=None):
+        ntt_inverse_stage(self.handle, t, self._batch(t, batch), stage, stream)
         return t
 
     def pointwise(self, a, b, out=None, batch=None, stream=None):

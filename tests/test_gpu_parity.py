@@ -153,7 +153,7 @@ def test_pointwise_edge_values(ntt):
     plan = ntt.Plan(N, [q])
     da, db = to_dev(a), to_dev(b)
     plan.pointwise(da, db, da)
-    np.testing.assert_array_equal(from_dev(da), [int(x) * int(y) % q for x, y in zip(a.ravel(), b.ravel())])
+    np.testing.assert_array_equal(from_dev(da).ravel(), [int(x) * int(y) % q for x, y in zip(a.ravel(), b.ravel())])
 
 
 @pytest.mark.parametrize("logn", [10, 12])
@@ -270,3 +270,21 @@ def test_argument_errors_on_gpu(ntt):
     assert lib.ntt_pointwise_mul(plan.handle, None, t.data_ptr(), t.data_ptr(), 1, None) == -1
     with pytest.raises(ntt.NttError):
         plan.set_variant(ntt.NTT_PATH_FOURSTEP, 5)
+
+
+def test_stage_entry_points_compose(ntt):
+    N, moduli = 1 << 16, P17[:3]
+    log("case stage entry points")
+    x = si.poly_batch(21, 2, moduli, N)
+    plan = ntt.Plan(N, moduli)
+    assert plan.variant[0] == ntt.NTT_PATH_FOURSTEP
+    d = to_dev(x)
+    plan.forward_stage(d, 0)
+    plan.forward_stage(d, 1)
+    np.testing.assert_array_equal(from_dev(d).reshape(x.shape), oracle_fwd(x, moduli))
+    plan.inverse_stage(d, 0)
+    plan.inverse_stage(d, 1)
+    np.testing.assert_array_equal(from_dev(d).reshape(x.shape), x)
+    small = ntt.Plan(1024, moduli)
+    with pytest.raises(ntt.NttError):
+        small.forward_stage(to_dev(si.poly_batch(1, 1, moduli, 1024)), 0)
