@@ -25,6 +25,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0                 # MI355X HBM3E
 INT32_MUL_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # 39.3: one int32 multiply per lane per clock
 MULS_PER_SHOUP = 9                    # 32x32 products in one 64-bit Shoup product (approx quotient)
+MULS_PER_GENERAL = 21                 # 32x32 products in one general 64-bit modular product
 
 
 def log(*a):
@@ -75,8 +76,7 @@ def main():
     def step(buf):
         plan.forward(buf, batch=4)
         a, b = buf[:2], buf[2:]
-        plan.pointwise(a, b, a, batch=2)
-        plan.inverse(a, batch=2)
+        plan.pointwise_inverse(a, b, a, batch=2)   # pointwise product fused into the inverse
 
     # ---- correctness of the timed configuration on one set (vs. an independent
     # GPU check: forward then inverse must return the input exactly)
@@ -123,17 +123,20 @@ def main():
                                        stages=logn1, extra_muls=0, words_in=1, words_out=1)
         kernels["fwd_row_pass"] = dict(fn=lambda b: plan.forward_stage(b, 1, batch=4), items=polys * L,
                                        stages=logn2, extra_muls=0, words_in=1, words_out=1)
-        kernels["inv_row_pass"] = dict(fn=lambda b: plan.inverse_stage(b[:2], 0, batch=2), items=2 * L,
-                                       stages=logn2, extra_muls=0, words_in=1, words_out=1)
+        kernels["inv_row_pass_mul"] = dict(fn=lambda b: plan.pointwise_inverse_stage(b[:2], b[2:], b[:2], 0, batch=2),
+                                           items=2 * L, stages=logn2, extra_muls=0, words_in=2, words_out=1,
+                                           general_muls=N)
         kernels["inv_col_pass"] = dict(fn=lambda b: plan.inverse_stage(b[:2], 1, batch=2), items=2 * L,
                                        stages=logn1, extra_muls=N // 2, words_in=1, words_out=1)
-    kernels["pointwise"] = dict(fn=lambda b: plan.pointwise(b[:2], b[2:], b[:2], batch=2), items=2 * L,
-                                stages=0, extra_muls=0, words_in=2, words_out=1)
+    else:
+        kernels["pointwise"] = dict(fn=lambda b: plan.pointwise(b[:2], b[2:], b[:2], batch=2), items=2 * L,
+                                    stages=0, extra_muls=0, words_in=2, words_out=1)
     per_kernel = {}
     for name, k in kernels.items():
         us = time_kernel(k["fn"], args.kernel_reps)
         bytes_alg = k["items"] * N * 8 * (k["words_in"] + k["words_out"])
-        muls = k["items"] * ((N // 2) * k["stages"] + k["extra_muls"]) * MULS_PER_SHOUP
+        muls = k["items"] * (((N // 2) * k["stages"] + k["extra_muls"]) * MULS_PER_SHOUP
+                             + k.get("general_muls", 0) * MULS_PER_GENERAL)
         gbs = bytes_alg / (us * 1e-6) / 1e9
         tops = muls / (us * 1e-6) / 1e12
         per_kernel[name] = dict(us=round(us, 2), alg_bytes=bytes_alg, alg_int32_muls=muls,

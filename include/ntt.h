@@ -94,12 +94,24 @@ int ntt_inverse(const ntt_plan* plan, void* d_data, uint32_t batch, void* stream
 int ntt_pointwise_mul(const ntt_plan* plan, const void* d_a, const void* d_b, void* d_c,
                       uint32_t batch, void* stream);
 
+/* d_c = inverse(d_a * d_b): the pointwise product followed by the inverse
+ * NTT (the usual last two steps of a negacyclic polynomial product). On the
+ * four-step path the product is computed inside the first inverse kernel, so
+ * the product is never written to memory; elsewhere it is the two calls in a
+ * row. d_c may alias d_a or d_b (exactly). Asynchronous. */
+int ntt_pointwise_mul_inverse(const ntt_plan* plan, const void* d_a, const void* d_b, void* d_c,
+                              uint32_t batch, void* stream);
+
 /* One kernel of a four-step transform, for timing and profiling: stage 0 is
  * the first kernel (forward: column pass, data -> scratch; inverse: row pass,
  * data -> scratch), stage 1 the second (scratch -> data). Running stage 0 then
  * stage 1 on the same stream equals ntt_forward / ntt_inverse. Returns
  * NTT_ERR_UNSUPPORTED unless the plan's variant is NTT_PATH_FOURSTEP. */
 int ntt_forward_stage(const ntt_plan* plan, void* d_data, uint32_t batch, int stage, void* stream);
+/* Same for ntt_pointwise_mul_inverse: stage 0 is the fused product + first
+ * inverse kernel (d_a, d_b -> scratch), stage 1 the second (scratch -> d_c). */
+int ntt_pointwise_mul_inverse_stage(const ntt_plan* plan, const void* d_a, const void* d_b, void* d_c,
+                                    uint32_t batch, int stage, void* stream);
 int ntt_inverse_stage(const ntt_plan* plan, void* d_data, uint32_t batch, int stage, void* stream);
 
 /* Plan queries: the root used for each limb (L values) and the variant. */

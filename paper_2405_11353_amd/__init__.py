@@ -28,6 +28,8 @@ from .ntt import (  # noqa: F401
     ntt_plan_set_quotient,
     ntt_plan_set_variant,
     ntt_pointwise_mul,
+    ntt_pointwise_mul_inverse,
+    ntt_pointwise_mul_inverse_stage,
     ntt_strerror,
     ntt_workspace_bytes,
 )

@@ -255,6 +255,9 @@ static int get_scratch(ntt_plan* p, void* stream, size_t bytes, void** out) {
   return NTT_OK;
 }
 
+extern "C" int ntt_pointwise_mul(const ntt_plan* p, const void* a, const void* b, void* c, uint32_t batch,
+                                 void* stream);
+
 static int check_common(const ntt_plan* p, uint32_t batch) {
   if (!p || batch == 0) return NTT_ERR_ARG;
   if ((uint64_t)batch * p->L > 0xFFFFFFFFull / 64) return NTT_ERR_ARG;
@@ -307,6 +310,62 @@ int ntt_inverse_stage(const ntt_plan* p, void* d, uint32_t batch, int stage, voi
   if (stage != 0 && stage != 1) return NTT_ERR_ARG;
   return run_ntt(p, d, batch, stream, false, 1 << stage);
 }
+
+static int run_mul_inverse(const ntt_plan* pc, const void* a, const void* b, void* c, uint32_t batch,
+                           void* stream, int stage_mask);
+
+int ntt_pointwise_mul_inverse(const ntt_plan* pc, const void* a, const void* b, void* c, uint32_t batch,
+                              void* stream) {
+  return run_mul_inverse(pc, a, b, c, batch, stream, 3);
+}
+
+int ntt_pointwise_mul_inverse_stage(const ntt_plan* pc, const void* a, const void* b, void* c, uint32_t batch,
+                                    int stage, void* stream) {
+  if (stage != 0 && stage != 1) return NTT_ERR_ARG;
+  return run_mul_inverse(pc, a, b, c, batch, stream, 1 << stage);
+}
+
+}  // extern "C"
+
+static int run_mul_inverse(const ntt_plan* pc, const void* a, const void* b, void* c, uint32_t batch,
+                           void* stream, int stage_mask) {
+  int rc = check_common(pc, batch);
+  if (rc != NTT_OK) return rc;
+  if (!a || !b || !c) return NTT_ERR_ARG;
+  ntt_plan* p = const_cast<ntt_plan*>(pc);
+  if (p->path != NTT_PATH_FOURSTEP) {
+    if (stage_mask != 3) return NTT_ERR_UNSUPPORTED;
+    // no fused kernel for this shape: the two steps, still on the device
+    rc = ntt_pointwise_mul(p, a, b, c, batch, stream);
+    return rc != NTT_OK ? rc : run_ntt(p, c, batch, stream, false);
+  }
+  nttk::Launch L;
+  L.word = p->word;
+  L.exact = p->exact;
+  L.path = nttk::PATH_TWO;
+  L.logN = (int)p->logN;
+  L.logN1 = p->logN1;
+  L.natural = (p->flags & NTT_ORDER_BITREV) ? 0 : 1;
+  L.data = c;
+  L.mul_a = a;
+  L.mul_b = b;
+  L.tw = p->d_tw_inv;
+  L.mods = p->d_mod;
+  L.L = p->L;
+  L.batch = batch;
+  L.items = batch * p->L;
+  L.stream = (hipStream_t)stream;
+  L.stage_mask = stage_mask;
+  if (L.natural) {
+    rc = get_scratch(p, stream, ntt_workspace_bytes(p, batch), &L.scratch);
+    if (rc != NTT_OK) return rc;
+  }
+  const hipError_t e = nttk::launch_ntt(L, false);
+  if (e == hipErrorNotSupported) return NTT_ERR_UNSUPPORTED;
+  return e == hipSuccess ? NTT_OK : NTT_ERR_HIP;
+}
+
+extern "C" {
 
 int ntt_pointwise_mul(const ntt_plan* p, const void* a, const void* b, void* c, uint32_t batch, void* stream) {
   int rc = check_common(p, batch);

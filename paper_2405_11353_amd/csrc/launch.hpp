@@ -22,6 +22,8 @@ struct Launch {
   uint32_t L = 0, items = 0, batch = 0;  // items = batch * L
   hipStream_t stream = nullptr;
   int stage_mask = 3;       // PATH_TWO: bit 0 runs the first kernel, bit 1 the second
+  const void* mul_a = nullptr;  // PATH_TWO inverse: if set, transform mul_a * mul_b into data
+  const void* mul_b = nullptr;
 };
 
 // Each returns hipErrorNotSupported for a shape it has no kernel for.

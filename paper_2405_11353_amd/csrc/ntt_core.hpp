@@ -242,6 +242,8 @@ k_col(const typename A::word* in, typename A::word* out, const typename A::tw_t*
   const uint32_t c = threadIdx.x % NC, t = threadIdx.x / NC;
   A a;
   a.load(mods[l]);
+  // the column stages use table slots [0, N1) only; every lane of a wave reads
+  // the same slot, so these loads are served by one cache line each
   const typename A::tw_t* tw = tw_all + ((size_t)l << logN);
   const size_t base = ((size_t)item << logN) + tile * NC + c;
   const W* src = in + base;
@@ -291,11 +293,13 @@ k_col(const typename A::word* in, typename A::word* out, const typename A::tw_t*
 // element (r, c) to brv(c) * N1 + brv(r) with rows r = brv(k1), k1 in the tile.
 // Inverse: reads that layout (or rows in place), runs the row stages
 // backwards and writes rows in lazy range for the column pass.
-template <class A, int LOGN2, bool FWD, bool NATURAL>
+// MULIN (inverse only): the input is in * in2 elementwise mod q (the pointwise
+// product fused into the load), read from two buffers.
+template <class A, int LOGN2, bool FWD, bool NATURAL, bool MULIN = false>
 __global__ void __launch_bounds__(16 << (LOGN2 - 4))
 k_row(const typename A::word* in, typename A::word* out, const typename A::tw_t* __restrict__ tw_all,
       const typename ModOf<A>::type* __restrict__ mods, uint32_t L, uint32_t logN, uint32_t items,
-      uint32_t batch) {
+      uint32_t batch, const typename A::word* in2 = nullptr) {
   using W = typename A::word;
   using S = Sched<LOGN2>;
   constexpr uint32_t N2 = 1u << LOGN2, TPR = N2 / 16, RSTR = N2 + N2 / 16 + 1;
@@ -357,19 +361,29 @@ k_row(const typename A::word* in, typename A::word* out, const typename A::tw_t*
       for (int i = 0; i < 16; ++i) dst[i * TPR + t] = sh[pad16(i * TPR + t)];
     }
   } else {
+    const typename ModOf<A>::type* mi = mods + l;
     if constexpr (NATURAL) {
       const uint32_t rr = threadIdx.x % 16, cg = threadIdx.x / 16;
-      const W* src = in + pbase + tile * 16 + rr;
+      const size_t off = pbase + tile * 16 + rr;
+      const W* src = in + off;
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
         const uint32_t cc = cg + TPR * j;
-        lds[rr * RSTR + pad16(cc)] = src[(size_t)brv(cc, LOGN2) * N1];
+        const size_t e = (size_t)brv(cc, LOGN2) * N1;
+        W val = src[e];
+        if constexpr (MULIN) val = mulmod_general(val, in2[off + e], *mi);
+        lds[rr * RSTR + pad16(cc)] = val;
       }
       __syncthreads();
     } else {
-      const W* src = in + pbase + (size_t)r * N2;
+      const size_t off = pbase + (size_t)r * N2;
+      const W* src = in + off;
 #pragma unroll
-      for (int i = 0; i < 16; ++i) sh[pad16(i * TPR + t)] = src[i * TPR + t];
+      for (int i = 0; i < 16; ++i) {
+        W val = src[i * TPR + t];
+        if constexpr (MULIN) val = mulmod_general(val, in2[off + i * TPR + t], *mi);
+        sh[pad16(i * TPR + t)] = val;
+      }
       wave_lds_sync();
     }
 #pragma unroll

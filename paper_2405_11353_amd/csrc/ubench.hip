@@ -116,8 +116,26 @@ static int run_copy(FILE* out) {
   return 0;
 }
 
+// --copy-only: three dispatches of a plain copy of 1 GiB (read 1 GiB, write
+// 1 GiB each), the reference for scaling FETCH_SIZE / WRITE_SIZE counters.
+static int run_copy_only() {
+  const size_t bytes = (size_t)1 << 30, n = bytes / sizeof(uint4);
+  uint4 *a, *b;
+  CHK(hipMalloc(&a, bytes)); CHK(hipMalloc(&b, bytes));
+  CHK(hipMemset(a, 1, bytes)); CHK(hipMemset(b, 0, bytes));
+  CHK(hipDeviceSynchronize());
+  int dev; CHK(hipGetDevice(&dev)); hipDeviceProp_t p; CHK(hipGetDeviceProperties(&p, dev));
+  for (int r = 0; r < 3; ++r) k_copy<<<p.multiProcessorCount * 16, 256>>>(a, b, n);
+  CHK(hipGetLastError());
+  CHK(hipDeviceSynchronize());
+  printf("{\"op\": \"copy_only\", \"dispatches\": 3, \"bytes_read_per_dispatch\": %zu, \"bytes_written_per_dispatch\": %zu}\n", bytes, bytes);
+  CHK(hipFree(a)); CHK(hipFree(b));
+  return 0;
+}
+
 int main(int argc, char** argv) {
   int dev = 0; CHK(hipSetDevice(dev));
+  if (argc > 1 && strcmp(argv[1], "--copy-only") == 0) return run_copy_only() ? 1 : 0;
   hipDeviceProp_t p; CHK(hipGetDeviceProperties(&p, dev));
   printf("{\"device\": \"%s\", \"gcnArchName\": \"%s\", \"cus\": %d, \"clock_khz\": %d, \"lds_per_block\": %zu, \"lds_per_cu\": %zu, \"l2_bytes\": %d, \"regs_per_block\": %d, \"hbm_bytes\": %zu, \"mem_clock_khz\": %d, \"mem_bus_bits\": %d}\n",
          p.name, p.gcnArchName, p.multiProcessorCount, p.clockRate, p.sharedMemPerBlock,

@@ -47,6 +47,8 @@ def lib() -> ctypes.CDLL:
             "ntt_forward": (i32, [vp, vp, u32, vp]),
             "ntt_inverse": (i32, [vp, vp, u32, vp]),
             "ntt_pointwise_mul": (i32, [vp, vp, vp, vp, u32, vp]),
+            "ntt_pointwise_mul_inverse": (i32, [vp, vp, vp, vp, u32, vp]),
+            "ntt_pointwise_mul_inverse_stage": (i32, [vp, vp, vp, vp, u32, i32, vp]),
             "ntt_forward_stage": (i32, [vp, vp, u32, i32, vp]),
             "ntt_inverse_stage": (i32, [vp, vp, u32, i32, vp]),
             "ntt_plan_get_psi": (i32, [vp, u64p]),
@@ -147,6 +149,16 @@ def ntt_inverse_stage(plan: int, data, batch: int, stage: int, stream=None) -> N
 
 def ntt_pointwise_mul(plan: int, a, b, c, batch: int, stream=None) -> None:
     _check(lib().ntt_pointwise_mul(plan, _ptr(a), _ptr(b), _ptr(c), batch, _stream(stream)), "ntt_pointwise_mul")
+
+
+def ntt_pointwise_mul_inverse(plan: int, a, b, c, batch: int, stream=None) -> None:
+    _check(lib().ntt_pointwise_mul_inverse(plan, _ptr(a), _ptr(b), _ptr(c), batch, _stream(stream)),
+           "ntt_pointwise_mul_inverse")
+
+
+def ntt_pointwise_mul_inverse_stage(plan: int, a, b, c, batch: int, stage: int, stream=None) -> None:
+    _check(lib().ntt_pointwise_mul_inverse_stage(plan, _ptr(a), _ptr(b), _ptr(c), batch, stage, _stream(stream)),
+           "ntt_pointwise_mul_inverse_stage")
 
 
 def ntt_plan_get_psi(plan: int, L: int) -> list[int]:
@@ -252,6 +264,20 @@ class Plan:
         self._batch(b, bt)
         self._batch(out, bt)
         ntt_pointwise_mul(self.handle, a, b, out, bt, stream)
+        return out
+
+    def pointwise_inverse(self, a, b, out=None, batch=None, stream=None):
+        """out = inverse(a * b); out defaults to a."""
+        out = a if out is None else out
+        bt = self._batch(a, batch)
+        self._batch(b, bt)
+        self._batch(out, bt)
+        ntt_pointwise_mul_inverse(self.handle, a, b, out, bt, stream)
+        return out
+
+    def pointwise_inverse_stage(self, a, b, out, stage: int, batch=None, stream=None):
+        bt = self._batch(a, batch)
+        ntt_pointwise_mul_inverse_stage(self.handle, a, b, out, bt, stage, stream)
         return out
 
     def workspace_bytes(self, batch: int) -> int:

@@ -288,3 +288,32 @@ def test_stage_entry_points_compose(ntt):
     small = ntt.Plan(1024, moduli)
     with pytest.raises(ntt.NttError):
         small.forward_stage(to_dev(si.poly_batch(1, 1, moduli, 1024)), 0)
+
+
+@pytest.mark.parametrize("logn,bitrev,variant", [(16, False, None), (16, True, None), (15, False, None),
+                                                  (12, False, None), (12, False, (3, 6)), (13, True, (3, 6)),
+                                                  (17, False, None)])
+def test_fused_pointwise_inverse(ntt, logn, bitrev, variant):
+    N, moduli = 1 << logn, P18[:3]
+    log(f"case fused pointwise+inverse N={N} bitrev={bitrev} variant={variant}")
+    plan = ntt.Plan(N, moduli, flags=ntt.NTT_ORDER_BITREV if bitrev else 0)
+    if variant:
+        plan.set_variant(*variant)
+    a = si.poly_batch(31, 2, moduli, N)
+    b = si.poly_batch(32, 2, moduli, N)
+    da, db = to_dev(a), to_dev(b)
+    plan.forward(da)
+    plan.forward(db)
+    dc = to_dev(np.zeros_like(a))
+    plan.pointwise_inverse(da, db, dc)
+    got = from_dev(dc).reshape(a.shape)
+    # reference: the unfused path, itself checked against the oracle elsewhere
+    A = oracle_fwd(a, moduli)
+    B = oracle_fwd(b, moduli)
+    ref = oracle_inv(oracle.pointwise_batch(A, B, moduli)[0], moduli)
+    np.testing.assert_array_equal(got, ref)
+    plan.pointwise_inverse(da, db)          # aliasing: result into a
+    np.testing.assert_array_equal(from_dev(da).reshape(a.shape), ref)
+    if logn <= 12:
+        for l, q in enumerate(moduli):
+            np.testing.assert_array_equal(got[1, l], oracle.negacyclic_mul(a[1, l], b[1, l], q))
