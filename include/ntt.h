@@ -133,10 +133,68 @@ int ntt_plan_set_quotient(ntt_plan* plan, int exact);
  * 0 when the chosen variant works in place). The plan allocates it. */
 size_t ntt_workspace_bytes(const ntt_plan* plan, uint32_t batch);
 
+/* The variant a call with `batch` polynomials would run (after tuning). */
+int ntt_plan_get_variant_for(const ntt_plan* plan, uint32_t batch, int* path, int* log_n1, int* exact);
+
 /* Thread-local code of the last failed call that returns a pointer, and a
  * static description of any code. */
 int ntt_last_error(void);
+void ntt_set_last_error(int code);
 const char* ntt_strerror(int code);
+
+/* ---- autotuner ------------------------------------------------------------
+ * Times every kernel variant the library has for (N, word size, `items`
+ * transforms per call) on the current GPU: the LDS-resident kernel, each
+ * four-step split N1 x N2, and for 64-bit words both quotient flavours;
+ * `reps` timed calls each after two warm-up calls, with HIP events on a
+ * private stream. The fastest goes into a process-wide table that plans in
+ * automatic mode (the default) and batches consult per call, keyed by
+ * (word, log2 N, log2 items). The table is saved and loaded as JSON tagged
+ * with the GPU architecture; a process loads the file named by the
+ * NTT_TUNE_CACHE environment variable at its first plan or batch creation.
+ * Synchronous; allocates items*N words of device memory while it runs. */
+typedef struct {
+  int32_t path;       /* NTT_PATH_* */
+  int32_t log_n1;     /* four-step column length log2 */
+  int32_t exact;      /* 64-bit quotient flavour */
+  float us_per_call;  /* measured time of the winner */
+} ntt_tune_choice;
+int ntt_autotune(uint32_t N, uint32_t flags, uint32_t items, uint32_t reps, ntt_tune_choice* best);
+int ntt_tune_save(const char* path);
+int ntt_tune_load(const char* path);  /* NTT_ERR_STATE if the file is for another arch */
+int ntt_tune_clear(void);
+
+/* ---- batched executor ---------------------------------------------------------
+ * Many polynomials of different N (16 <= N <= 2^17) and limb counts,
+ * transformed by one ntt_batch_run: each job is one polynomial, [L][N]
+ * contiguous 64-bit words at d_data, limb l reduced mod moduli[l] (q < 2^61,
+ * prime, 2N | q-1). Items (polynomial, limb) are bucketed by (N, op); each
+ * bucket runs the tuned (or default) variant; the buckets' kernels are
+ * captured once, at creation, as parallel branches of one hipGraph, so a run
+ * is a single hipGraphLaunch. Twiddle tables come from a process-wide pool
+ * keyed by (device, q, N) and stay resident. The batch owns its descriptor
+ * table, four-step scratch and graph; the caller owns the job buffers, which
+ * must stay valid (the graph holds their addresses). Natural-order spectra. */
+#define NTT_JOB_FORWARD 0u
+#define NTT_JOB_INVERSE 1u
+typedef struct {
+  uint32_t N;                 /* transform length */
+  uint32_t L;                 /* limbs */
+  uint32_t op;                /* NTT_JOB_FORWARD or NTT_JOB_INVERSE */
+  uint32_t reserved;
+  const uint64_t* moduli;     /* L moduli (host; read during create) */
+  void* d_data;               /* [L][N] words on the device, in place */
+} ntt_job_desc;
+typedef struct ntt_batch ntt_batch;
+typedef struct {
+  uint32_t items, buckets, kernels, uses_graph;
+  uint64_t scratch_bytes, twiddle_pool_bytes;
+} ntt_batch_info;
+#define NTT_BATCH_NO_GRAPH 0x1u  /* launch the kernels directly on each run */
+ntt_batch* ntt_batch_create(const ntt_job_desc* jobs, uint32_t n_jobs, uint32_t flags);
+int ntt_batch_run(ntt_batch* batch, void* stream);
+int ntt_batch_get_info(const ntt_batch* batch, ntt_batch_info* info);
+void ntt_batch_destroy(ntt_batch* batch);
 
 #ifdef __cplusplus
 }

@@ -5,6 +5,15 @@ The compute path is libntt.so (hand-written HIP for gfx950, C ABI in
 include/ntt.h); this package only marshals arguments to it.
 """
 from .ntt import (  # noqa: F401
+    NTT_BATCH_NO_GRAPH,
+    NTT_JOB_FORWARD,
+    NTT_JOB_INVERSE,
+    Batch,
+    ntt_autotune,
+    ntt_plan_get_variant_for,
+    ntt_tune_clear,
+    ntt_tune_load,
+    ntt_tune_save,
     NTT_ORDER_BITREV,
     NTT_PATH_AUTO,
     NTT_PATH_FOURSTEP,

@@ -9,6 +9,7 @@
 
 #include "launch.hpp"
 #include "ntt.h"
+#include "ntt_internal.hpp"
 #include "params.hpp"
 
 namespace {
@@ -18,34 +19,9 @@ int fail(int code) {
   g_last_error = code;
   return code;
 }
-
-struct ScratchSlot {
-  void* stream;
-  void* ptr;
-  size_t bytes;
-};
 }  // namespace
 
-struct ntt_plan {
-  uint32_t N = 0, logN = 0, L = 0, flags = 0;
-  int word = 64;
-  int device = 0;
-  std::vector<uint64_t> moduli, psi;
-  void* d_tw_fwd = nullptr;
-  void* d_tw_inv = nullptr;
-  void* d_mod = nullptr;
-  int path = NTT_PATH_LDS;
-  int logN1 = 0;
-  int exact = 0;
-  std::mutex mu;  // guards scratch
-  std::vector<ScratchSlot> scratch;
-};
-
-static int ilog2(uint32_t N) {
-  int l = 0;
-  while ((1u << l) < N) ++l;
-  return l;
-}
+using ntti::ilog2;
 
 static bool variant_ok(const ntt_plan* p, int path, int logN1, int exact) {
   using namespace nttk;
@@ -59,17 +35,32 @@ static bool variant_ok(const ntt_plan* p, int path, int logN1, int exact) {
 }
 
 static void default_variant(ntt_plan* p) {
-  const int lg = (int)p->logN;
+  ntti::default_variant(p->word, (int)p->logN, &p->path, &p->logN1);
   p->exact = 0;
-  if (lg <= 3) {
-    p->path = NTT_PATH_TINY;
-  } else if (lg <= (p->word == 32 ? 14 : 13)) {
-    p->path = NTT_PATH_LDS;
-  } else {
-    p->path = NTT_PATH_FOURSTEP;
-    p->logN1 = lg / 2;
+  p->auto_variant = true;
+}
+
+// the variant a call on `items` transforms runs with
+static void select_variant(const ntt_plan* p, uint32_t items, int* path, int* logN1, int* exact) {
+  *path = p->path;
+  *logN1 = p->logN1;
+  *exact = p->exact;
+  if (!p->auto_variant) return;
+  int tp, tn1, tex;
+  if (ntti::tune_lookup(p->word, (int)p->logN, items, &tp, &tn1, &tex) && variant_ok(p, tp, tn1, tex)) {
+    *path = tp;
+    *logN1 = tn1;
+    *exact = tex;
   }
 }
+
+namespace ntti {
+int check_modulus(uint64_t q, uint32_t N, int word) {
+  const uint64_t qmax = word == 32 ? (1ull << 30) : (1ull << 61);
+  if (q < 3 || q >= qmax || (q - 1) % (2ull * N) || !nttp::is_prime(q)) return NTT_ERR_MODULUS;
+  return NTT_OK;
+}
+}  // namespace ntti
 
 static void release(ntt_plan* p) {
   if (!p) return;
@@ -88,6 +79,7 @@ static void release(ntt_plan* p) {
 extern "C" {
 
 int ntt_last_error(void) { return g_last_error; }
+void ntt_set_last_error(int code) { g_last_error = code; }
 
 const char* ntt_strerror(int code) {
   switch (code) {
@@ -117,11 +109,10 @@ ntt_plan* ntt_plan_create_ex(uint32_t N, const uint64_t* moduli, uint32_t L, uin
     return nullptr;
   }
   const int word = (flags & NTT_WORD32) ? 32 : 64;
-  const uint64_t qmax = word == 32 ? (1ull << 30) : (1ull << 61);
   std::vector<uint64_t> roots(L);
   for (uint32_t l = 0; l < L; ++l) {
     const uint64_t q = moduli[l];
-    if (q < 3 || q >= qmax || (q - 1) % (2ull * N) || !nttp::is_prime(q)) {
+    if (ntti::check_modulus(q, N, word) != NTT_OK) {
       fail(NTT_ERR_MODULUS);
       return nullptr;
     }
@@ -157,6 +148,7 @@ ntt_plan* ntt_plan_create_ex(uint32_t N, const uint64_t* moduli, uint32_t L, uin
     fail(NTT_ERR_HIP);
     return nullptr;
   }
+  ntti::tune_autoload();
   default_variant(p);
 
   const size_t tw_bytes = (size_t)N * nttp::tw_entry_bytes(word);
@@ -202,6 +194,16 @@ int ntt_plan_get_variant(const ntt_plan* p, int* path, int* log_n1) {
   return NTT_OK;
 }
 
+int ntt_plan_get_variant_for(const ntt_plan* p, uint32_t batch, int* path, int* log_n1, int* exact) {
+  if (!p || batch == 0) return NTT_ERR_ARG;
+  int pa, n1, ex;
+  select_variant(p, batch * p->L, &pa, &n1, &ex);
+  if (path) *path = pa;
+  if (log_n1) *log_n1 = pa == NTT_PATH_FOURSTEP ? n1 : 0;
+  if (exact) *exact = ex;
+  return NTT_OK;
+}
+
 int ntt_plan_set_variant(ntt_plan* p, int path, int log_n1) {
   if (!p) return NTT_ERR_ARG;
   if (path == NTT_PATH_AUTO) {
@@ -212,6 +214,7 @@ int ntt_plan_set_variant(ntt_plan* p, int path, int log_n1) {
   p->path = path;
   p->logN1 = path == NTT_PATH_FOURSTEP ? log_n1 : 0;
   p->exact = 0;
+  p->auto_variant = false;
   return NTT_OK;
 }
 
@@ -219,11 +222,15 @@ int ntt_plan_set_quotient(ntt_plan* p, int exact) {
   if (!p || p->word != 64) return NTT_ERR_ARG;
   if (!variant_ok(p, p->path, p->logN1, exact ? 1 : 0)) return NTT_ERR_UNSUPPORTED;
   p->exact = exact ? 1 : 0;
+  p->auto_variant = false;
   return NTT_OK;
 }
 
 size_t ntt_workspace_bytes(const ntt_plan* p, uint32_t batch) {
-  if (!p || p->path != NTT_PATH_FOURSTEP || (p->flags & NTT_ORDER_BITREV)) return 0;
+  if (!p || batch == 0 || (p->flags & NTT_ORDER_BITREV)) return 0;
+  int path, n1, ex;
+  select_variant(p, batch * p->L, &path, &n1, &ex);
+  if (path != NTT_PATH_FOURSTEP) return 0;
   return ((size_t)batch * p->L << p->logN) * (p->word / 8);
 }
 
@@ -272,12 +279,14 @@ static int run_ntt(const ntt_plan* pc, void* data, uint32_t batch, void* stream,
   if (rc != NTT_OK) return rc;
   if (!data) return NTT_ERR_ARG;
   ntt_plan* p = const_cast<ntt_plan*>(pc);
+  int path, logN1, exact;
+  select_variant(p, batch * p->L, &path, &logN1, &exact);
   nttk::Launch c;
   c.word = p->word;
-  c.exact = p->exact;
-  c.path = p->path == NTT_PATH_TINY ? nttk::PATH_TINY : p->path == NTT_PATH_LDS ? nttk::PATH_LDS : nttk::PATH_TWO;
+  c.exact = exact;
+  c.path = path == NTT_PATH_TINY ? nttk::PATH_TINY : path == NTT_PATH_LDS ? nttk::PATH_LDS : nttk::PATH_TWO;
   c.logN = (int)p->logN;
-  c.logN1 = p->logN1;
+  c.logN1 = logN1;
   c.natural = (p->flags & NTT_ORDER_BITREV) ? 0 : 1;
   c.data = data;
   c.tw = fwd ? p->d_tw_fwd : p->d_tw_inv;
@@ -333,7 +342,9 @@ static int run_mul_inverse(const ntt_plan* pc, const void* a, const void* b, voi
   if (rc != NTT_OK) return rc;
   if (!a || !b || !c) return NTT_ERR_ARG;
   ntt_plan* p = const_cast<ntt_plan*>(pc);
-  if (p->path != NTT_PATH_FOURSTEP) {
+  int path, logN1, exact;
+  select_variant(p, batch * p->L, &path, &logN1, &exact);
+  if (path != NTT_PATH_FOURSTEP) {
     if (stage_mask != 3) return NTT_ERR_UNSUPPORTED;
     // no fused kernel for this shape: the two steps, still on the device
     rc = ntt_pointwise_mul(p, a, b, c, batch, stream);
@@ -341,10 +352,10 @@ static int run_mul_inverse(const ntt_plan* pc, const void* a, const void* b, voi
   }
   nttk::Launch L;
   L.word = p->word;
-  L.exact = p->exact;
+  L.exact = exact;
   L.path = nttk::PATH_TWO;
   L.logN = (int)p->logN;
-  L.logN1 = p->logN1;
+  L.logN1 = logN1;
   L.natural = (p->flags & NTT_ORDER_BITREV) ? 0 : 1;
   L.data = c;
   L.mul_a = a;

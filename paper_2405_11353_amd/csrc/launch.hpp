@@ -26,6 +26,18 @@ struct Launch {
   const void* mul_b = nullptr;
 };
 
+// Batched executor launch: items are described by a device table of ItemDesc
+// (64-bit words, natural order); PATH_LDS or PATH_TWO.
+struct ItemDesc;
+struct BatchLaunch {
+  int path = PATH_LDS;
+  int logN = 0, logN1 = 0;
+  const ItemDesc* desc = nullptr;  // device pointer, items entries
+  uint32_t items = 0;
+  hipStream_t stream = nullptr;
+};
+hipError_t launch_batch_u64(const BatchLaunch& c, bool forward);
+
 // Each returns hipErrorNotSupported for a shape it has no kernel for.
 hipError_t launch_u64(const Launch& c, bool forward);
 hipError_t launch_u64x(const Launch& c, bool forward);

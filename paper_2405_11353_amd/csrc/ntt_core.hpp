@@ -56,6 +56,19 @@ template <class A> struct ModOf;
 template <bool E> struct ModOf<Arith64<E>> { using type = ModInfo64; };
 template <> struct ModOf<Arith32> { using type = ModInfo32; };
 
+// One work item of the batched executor: a single (polynomial, limb) transform
+// with its own buffers, twiddle tables and modulus constants.
+struct ItemDesc {
+  void* data;            // N words: input and output of the transform
+  void* scratch;         // N words: four-step intermediate (natural order)
+  const void* tw_fwd;    // N twiddle pairs of the item's modulus and length
+  const void* tw_inv;
+  const void* mod;       // ModInfo64 / ModInfo32 of the item's modulus
+  uint64_t pad[3];
+};
+// io codes for the four-step kernels in indirect mode
+enum { IO_DATA_DATA = 0, IO_DATA_SCRATCH = 1, IO_SCRATCH_DATA = 2 };
+
 __device__ __forceinline__ uint32_t brv(uint32_t x, uint32_t bits) {
   return bits ? (__builtin_bitreverse32(x) >> (32 - bits)) : 0u;
 }
@@ -148,22 +161,37 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 // ============================================================ k_lds
 // P transforms per workgroup, N/16 threads each, whole transform in LDS.
-template <class A, int LOGN, int P, bool FWD, bool NATURAL>
+// IND: items come from a descriptor table (batched executor) instead of the
+// contiguous [batch][L][N] layout.
+template <class A, int LOGN, int P, bool FWD, bool NATURAL, bool IND = false>
 __global__ void __launch_bounds__(P << (LOGN - 4))
 k_lds(typename A::word* __restrict__ data, const typename A::tw_t* __restrict__ tw_all,
-      const typename ModOf<A>::type* __restrict__ mods, uint32_t L, uint32_t items) {
+      const typename ModOf<A>::type* __restrict__ mods, uint32_t L, uint32_t items,
+      const ItemDesc* __restrict__ desc = nullptr) {
   using W = typename A::word;
+  using TW = typename A::tw_t;
+  using M = typename ModOf<A>::type;
   using S = Sched<LOGN>;
   constexpr uint32_t N = 1u << LOGN, T = N / 16, SPAN = N + N / 16;
   __shared__ W lds[P * SPAN];
   const uint32_t g = threadIdx.x / T, t = threadIdx.x % T;
   const uint32_t item = blockIdx.x * P + g;
   const bool valid = item < items;
-  const uint32_t l = valid ? item % L : 0;
+  const uint32_t vi = valid ? item : 0;
   A a;
-  a.load(mods[l]);
-  const typename A::tw_t* tw = tw_all + ((size_t)l << LOGN);
-  W* x = data + ((size_t)(valid ? item : 0) << LOGN);
+  const TW* tw;
+  W* x;
+  if constexpr (IND) {
+    const ItemDesc d = desc[vi];
+    a.load(*(const M*)d.mod);
+    tw = (const TW*)(FWD ? d.tw_fwd : d.tw_inv);
+    x = (W*)d.data;
+  } else {
+    const uint32_t l = vi % L;
+    a.load(mods[l]);
+    tw = tw_all + ((size_t)l << LOGN);
+    x = data + ((size_t)vi << LOGN);
+  }
   W* sh = lds + g * SPAN;
   W v[16];
   if constexpr (FWD) {
@@ -225,11 +253,14 @@ k_lds(typename A::word* __restrict__ data, const typename A::tw_t* __restrict__ 
 // each row segment read or written is NC words (128 bytes).
 // Forward: global stages [0, logN1), out-of-place allowed (in == out is fine).
 // Inverse: global stages [logN1-1 .. 0] with the N^-1 fold, canonical output.
-template <class A, int LOGN1, int NC, bool FWD>
+template <class A, int LOGN1, int NC, bool FWD, bool IND = false>
 __global__ void __launch_bounds__(NC << (LOGN1 - 4))
 k_col(const typename A::word* in, typename A::word* out, const typename A::tw_t* __restrict__ tw_all,
-      const typename ModOf<A>::type* __restrict__ mods, uint32_t L, uint32_t logN, uint32_t items) {
+      const typename ModOf<A>::type* __restrict__ mods, uint32_t L, uint32_t logN, uint32_t items,
+      const ItemDesc* __restrict__ desc = nullptr, int io = 0) {
   using W = typename A::word;
+  using TW = typename A::tw_t;
+  using M = typename ModOf<A>::type;
   using S = Sched<LOGN1>;
   constexpr uint32_t N1 = 1u << LOGN1, TPC = N1 / 16, LD = NC + 1;
   __shared__ W lds[N1 * LD];
@@ -238,16 +269,28 @@ k_col(const typename A::word* in, typename A::word* out, const typename A::tw_t*
   const uint32_t bid = xcd_remap(blockIdx.x, gridDim.x);
   const uint32_t tile = bid % tiles, item = bid / tiles;
   if (item >= items) return;  // whole workgroup leaves together
-  const uint32_t l = item % L;
   const uint32_t c = threadIdx.x % NC, t = threadIdx.x / NC;
   A a;
-  a.load(mods[l]);
   // the column stages use table slots [0, N1) only; every lane of a wave reads
   // the same slot, so these loads are served by one cache line each
-  const typename A::tw_t* tw = tw_all + ((size_t)l << logN);
-  const size_t base = ((size_t)item << logN) + tile * NC + c;
-  const W* src = in + base;
-  W* dst = out + base;
+  const TW* tw;
+  const W* src;
+  W* dst;
+  const size_t off = tile * NC + c;
+  if constexpr (IND) {
+    const ItemDesc d = desc[item];
+    a.load(*(const M*)d.mod);
+    tw = (const TW*)(FWD ? d.tw_fwd : d.tw_inv);
+    src = (const W*)(io == IO_SCRATCH_DATA ? d.scratch : d.data) + off;
+    dst = (W*)(io == IO_DATA_SCRATCH ? d.scratch : d.data) + off;
+  } else {
+    const uint32_t l = item % L;
+    a.load(mods[l]);
+    tw = tw_all + ((size_t)l << logN);
+    const size_t base = ((size_t)item << logN) + off;
+    src = in + base;
+    dst = out + base;
+  }
   W v[16];
   if constexpr (FWD) {
 #pragma unroll
@@ -295,12 +338,15 @@ k_col(const typename A::word* in, typename A::word* out, const typename A::tw_t*
 // backwards and writes rows in lazy range for the column pass.
 // MULIN (inverse only): the input is in * in2 elementwise mod q (the pointwise
 // product fused into the load), read from two buffers.
-template <class A, int LOGN2, bool FWD, bool NATURAL, bool MULIN = false>
+template <class A, int LOGN2, bool FWD, bool NATURAL, bool MULIN = false, bool IND = false>
 __global__ void __launch_bounds__(16 << (LOGN2 - 4))
 k_row(const typename A::word* in, typename A::word* out, const typename A::tw_t* __restrict__ tw_all,
       const typename ModOf<A>::type* __restrict__ mods, uint32_t L, uint32_t logN, uint32_t items,
-      uint32_t batch, const typename A::word* in2 = nullptr) {
+      uint32_t batch, const typename A::word* in2 = nullptr, const ItemDesc* __restrict__ desc = nullptr,
+      int io = 0) {
   using W = typename A::word;
+  using TW = typename A::tw_t;
+  using M = typename ModOf<A>::type;
   using S = Sched<LOGN2>;
   constexpr uint32_t N2 = 1u << LOGN2, TPR = N2 / 16, RSTR = N2 + N2 / 16 + 1;
   static_assert(TPR <= 64, "a row must fit in one wavefront");
@@ -318,9 +364,23 @@ k_row(const typename A::word* in, typename A::word* out, const typename A::tw_t*
   const uint32_t k1 = tile * 16 + rl;
   const uint32_t r = NATURAL ? brv(k1, logN1) : k1;
   A a;
-  a.load(mods[l]);
-  const typename A::tw_t* tw = tw_all + ((size_t)l << logN);
-  const size_t pbase = (size_t)item << logN;
+  const M* mi;
+  const TW* tw;
+  size_t pbase;
+  if constexpr (IND) {
+    // indirect mode: in/out are rebased per item, pbase = 0
+    const ItemDesc d = desc[item];
+    mi = (const M*)d.mod;
+    tw = (const TW*)(FWD ? d.tw_fwd : d.tw_inv);
+    in = (const W*)(io == IO_SCRATCH_DATA ? d.scratch : d.data);
+    out = (W*)(io == IO_DATA_SCRATCH ? d.scratch : d.data);
+    pbase = 0;
+  } else {
+    mi = mods + l;
+    tw = tw_all + ((size_t)l << logN);
+    pbase = (size_t)item << logN;
+  }
+  a.load(*mi);
   W* sh = lds + rl * RSTR;
   W v[16];
   if constexpr (FWD) {
@@ -361,7 +421,6 @@ k_row(const typename A::word* in, typename A::word* out, const typename A::tw_t*
       for (int i = 0; i < 16; ++i) dst[i * TPR + t] = sh[pad16(i * TPR + t)];
     }
   } else {
-    const typename ModOf<A>::type* mi = mods + l;
     if constexpr (NATURAL) {
       const uint32_t rr = threadIdx.x % 16, cg = threadIdx.x / 16;
       const size_t off = pbase + tile * 16 + rr;

@@ -1,0 +1,62 @@
+// Host-side internals shared by the C ABI, the batched executor, the
+// autotuner and the server. Not part of the public header.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <mutex>
+#include <vector>
+
+#include "launch.hpp"
+#include "ntt.h"
+
+struct ScratchSlot {
+  void* stream;
+  void* ptr;
+  size_t bytes;
+};
+
+struct ntt_plan {
+  uint32_t N = 0, logN = 0, L = 0, flags = 0;
+  int word = 64;
+  int device = 0;
+  std::vector<uint64_t> moduli, psi;
+  void* d_tw_fwd = nullptr;
+  void* d_tw_inv = nullptr;
+  void* d_mod = nullptr;
+  bool auto_variant = true;  // choose per call from the tuning table / defaults
+  int path = NTT_PATH_LDS;
+  int logN1 = 0;
+  int exact = 0;
+  std::mutex mu;  // guards scratch
+  std::vector<ScratchSlot> scratch;
+};
+
+namespace ntti {
+
+int ilog2(uint32_t x);
+// library default variant for (word, logN): path, logN1
+void default_variant(int word, int logN, int* path, int* logN1);
+// tuned variant for (word, logN, items) if the tuning table has one
+bool tune_lookup(int word, int logN, uint32_t items, int* path, int* logN1, int* exact);
+void tune_store(int word, int logN, uint32_t items, int path, int logN1, int exact, float us);
+// load the table named by NTT_TUNE_CACHE once per process (no-op if unset)
+void tune_autoload();
+
+// validation shared by plans and batch jobs: 0 or an NTT_ERR_ code
+int check_modulus(uint64_t q, uint32_t N, int word);
+
+// twiddle tables of one (word, q, N) on a device, created on first use and
+// kept for the life of the process
+struct PoolEntry {
+  const void* tw_fwd;
+  const void* tw_inv;
+  const void* mod;
+};
+int pool_get(int word, uint64_t q, uint32_t logN, PoolEntry* out);
+size_t pool_bytes();
+
+// a prime q < 2^bits with q = 1 mod 2N (the largest one), for tuning runs
+uint64_t tuning_prime(uint32_t N, int word);
+
+}  // namespace ntti

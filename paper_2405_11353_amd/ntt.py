@@ -20,6 +20,26 @@ NTT_PATH_AUTO, NTT_PATH_TINY, NTT_PATH_LDS, NTT_PATH_FOURSTEP = 0, 1, 2, 3
 
 _lib = None
 
+NTT_JOB_FORWARD, NTT_JOB_INVERSE = 0, 1
+NTT_BATCH_NO_GRAPH = 0x1
+
+
+class JobDesc(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_uint32), ("L", ctypes.c_uint32), ("op", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("moduli", ctypes.POINTER(ctypes.c_uint64)),
+                ("d_data", ctypes.c_void_p)]
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("items", ctypes.c_uint32), ("buckets", ctypes.c_uint32), ("kernels", ctypes.c_uint32),
+                ("uses_graph", ctypes.c_uint32), ("scratch_bytes", ctypes.c_uint64),
+                ("twiddle_pool_bytes", ctypes.c_uint64)]
+
+
+class TuneChoice(ctypes.Structure):
+    _fields_ = [("path", ctypes.c_int32), ("log_n1", ctypes.c_int32), ("exact", ctypes.c_int32),
+                ("us_per_call", ctypes.c_float)]
+
 
 class NttError(RuntimeError):
     def __init__(self, code: int, what: str = ""):
@@ -57,6 +77,16 @@ def lib() -> ctypes.CDLL:
             "ntt_plan_set_quotient": (i32, [vp, i32]),
             "ntt_workspace_bytes": (sz, [vp, u32]),
             "ntt_last_error": (i32, []),
+            "ntt_set_last_error": (None, [i32]),
+            "ntt_plan_get_variant_for": (i32, [vp, u32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+            "ntt_autotune": (i32, [u32, u32, u32, u32, ctypes.POINTER(TuneChoice)]),
+            "ntt_tune_save": (i32, [ctypes.c_char_p]),
+            "ntt_tune_load": (i32, [ctypes.c_char_p]),
+            "ntt_tune_clear": (i32, []),
+            "ntt_batch_create": (vp, [ctypes.POINTER(JobDesc), u32, u32]),
+            "ntt_batch_run": (i32, [vp, vp]),
+            "ntt_batch_get_info": (i32, [vp, ctypes.POINTER(BatchInfo)]),
+            "ntt_batch_destroy": (None, [vp]),
             "ntt_strerror": (ctypes.c_char_p, [i32]),
         }
         for name, (res, args) in sig.items():
@@ -183,6 +213,80 @@ def ntt_plan_set_quotient(plan: int, exact: bool) -> None:
 
 def ntt_workspace_bytes(plan: int, batch: int) -> int:
     return int(lib().ntt_workspace_bytes(plan, batch))
+
+
+def ntt_plan_get_variant_for(plan: int, batch: int) -> tuple[int, int, int]:
+    p, n1, ex = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(lib().ntt_plan_get_variant_for(plan, batch, ctypes.byref(p), ctypes.byref(n1), ctypes.byref(ex)),
+           "ntt_plan_get_variant_for")
+    return p.value, n1.value, ex.value
+
+
+def ntt_autotune(N: int, items: int, reps: int = 20, flags: int = 0) -> dict:
+    out = TuneChoice()
+    _check(lib().ntt_autotune(N, flags, items, reps, ctypes.byref(out)), "ntt_autotune")
+    return {"path": out.path, "log_n1": out.log_n1, "exact": out.exact, "us_per_call": out.us_per_call}
+
+
+def ntt_tune_save(path: str) -> None:
+    _check(lib().ntt_tune_save(path.encode()), "ntt_tune_save")
+
+
+def ntt_tune_load(path: str) -> None:
+    _check(lib().ntt_tune_load(path.encode()), "ntt_tune_load")
+
+
+def ntt_tune_clear() -> None:
+    _check(lib().ntt_tune_clear(), "ntt_tune_clear")
+
+
+class Batch:
+    """ntt_batch_create / run / destroy over a list of jobs.
+
+    jobs: iterable of (N, moduli, op, tensor) with tensor holding [L][N] 64-bit words
+    on the GPU. The tensors must outlive the batch (the captured graph holds their
+    addresses); the Batch keeps references to them.
+    """
+
+    def __init__(self, jobs, flags: int = 0):
+        jobs = list(jobs)
+        self._keep = []
+        arr = (JobDesc * len(jobs))()
+        for i, (N, moduli, op, t) in enumerate(jobs):
+            mods = _u64_array(moduli)
+            self._keep.append((mods, t))
+            if t.element_size() != 8 or not t.is_cuda or t.numel() < len(moduli) * N:
+                raise ValueError("job tensor must hold [L][N] 64-bit words on the GPU")
+            arr[i] = JobDesc(N, len(moduli), op, 0, mods, _ptr(t))
+        self.handle = lib().ntt_batch_create(arr, len(jobs), flags)
+        if not self.handle:
+            raise NttError(ntt_last_error(), "ntt_batch_create")
+
+    def run(self, stream=None):
+        _check(lib().ntt_batch_run(self.handle, _stream(stream)), "ntt_batch_run")
+
+    @property
+    def info(self) -> dict:
+        i = BatchInfo()
+        _check(lib().ntt_batch_get_info(self.handle, ctypes.byref(i)), "ntt_batch_get_info")
+        return {k: getattr(i, k) for k, _ in BatchInfo._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().ntt_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 # ---- convenience object ------------------------------------------------------

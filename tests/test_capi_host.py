@@ -64,3 +64,24 @@ def test_strerror_covers_codes(lib):
     lib.ntt_strerror.restype = ctypes.c_char_p
     for c in range(0, -10, -1):
         assert lib.ntt_strerror(c) and lib.ntt_strerror(c) != b"unknown error"
+
+
+def test_tune_table_save_load_round_trip(lib, tmp_path):
+    import paper_2405_11353_amd as ntt
+    ntt.ntt_tune_clear()
+    f = tmp_path / "t.json"
+    ntt.ntt_tune_save(str(f))          # empty table
+    assert '"entries"' in f.read_text()
+    with pytest.raises(ntt.NttError):
+        ntt.ntt_tune_load(str(f))      # no entries
+    arch = f.read_text().split('"arch": "')[1].split('"')[0]
+    f.write_text('{"arch": "%s", "entries": [\n {"word": 64, "log_n": 16, "items_log2": 6, "path": 3, '
+                 '"log_n1": 7, "exact": 0, "us": 12.5}]}' % arch)
+    ntt.ntt_tune_load(str(f))
+    ntt.ntt_tune_save(str(f))
+    assert '"log_n1": 7' in f.read_text()
+    f.write_text('{"arch": "gfx000", "entries": [{"word": 64, "log_n": 16, "items_log2": 6, "path": 3, '
+                 '"log_n1": 7, "exact": 0, "us": 1}]}')
+    with pytest.raises(ntt.NttError):
+        ntt.ntt_tune_load(str(f))      # another architecture
+    ntt.ntt_tune_clear()
