@@ -196,6 +196,65 @@ int ntt_batch_run(ntt_batch* batch, void* stream);
 int ntt_batch_get_info(const ntt_batch* batch, ntt_batch_info* info);
 void ntt_batch_destroy(ntt_batch* batch);
 
+/* ---- serving loop ---------------------------------------------------------------
+ * Continuous batching of requests on device-resident polynomials ([L][N]
+ * 64-bit words, 16 <= N <= 2^17, 1 <= L <= 256, natural order):
+ *   NTT_REQ_NTT      d_out = forward(d_a)
+ *   NTT_REQ_INTT     d_out = inverse(d_a)
+ *   NTT_REQ_POLYMUL  d_out = d_a * d_b in Z_q[x]/(x^N + 1) (two forward
+ *                    NTTs, pointwise product, inverse NTT)
+ * d_a and d_b are not modified unless d_out equals one of them (in place);
+ * partial overlaps are not allowed. A scheduler thread admits queued jobs in
+ * arrival order whenever one of n_streams device streams is free and the
+ * job's working memory (an operand copy for POLYMUL, four-step scratch for
+ * N >= 2^14) fits in the server's hbm_budget_bytes arena; jobs admitted
+ * together run as one batch (descriptor table + one launch per (phase, N)),
+ * up to max_batch_items (polynomial, limb) transforms per batch. Latency is
+ * measured from submit to the scheduler observing completion. With
+ * NTT_SERVER_SIMULATE nothing touches a device: each batch completes after
+ * simulate_ns_per_item per item (for testing the scheduler). The caller owns
+ * all request buffers and must keep them valid until the ticket completes.
+ * The server owns its arena, streams and descriptor buffers. submit/wait/
+ * stats are thread-safe; destroy drains queued work first. */
+#define NTT_REQ_NTT 0u
+#define NTT_REQ_INTT 1u
+#define NTT_REQ_POLYMUL 2u
+#define NTT_SERVER_SIMULATE 0x1u
+typedef struct {
+  uint32_t op, N, L, reserved;
+  const uint64_t* moduli;  /* host, L values, read during submit */
+  const void* d_a;
+  const void* d_b;         /* NTT_REQ_POLYMUL only */
+  void* d_out;
+} ntt_request;
+typedef struct {
+  size_t hbm_budget_bytes;
+  uint32_t n_streams;        /* 1..64 */
+  uint32_t max_batch_items;
+  uint32_t flags;
+  uint32_t reserved;
+  double simulate_ns_per_item;
+} ntt_server_config;
+typedef struct {
+  uint64_t submitted, completed, failed, rejected, queued;
+  uint64_t batches, items, ntts;   /* ntts: forward + inverse transforms done */
+  uint64_t admission_stalls;       /* times a free slot waited for arena space */
+  uint64_t peak_bytes;             /* largest arena use */
+  uint32_t max_inflight_batches, reserved;
+  double p50_us, p99_us, mean_us, max_us;
+  double wall_s, busy_s;           /* since creation or reset; busy = a batch in flight */
+} ntt_server_stats;
+typedef struct ntt_server ntt_server;
+ntt_server* ntt_server_create(const ntt_server_config* cfg);
+int ntt_server_submit(ntt_server* server, const ntt_request* req, uint64_t* ticket);
+/* NTT_OK when the job finished (then the ticket is forgotten), the job's
+ * error code if it failed, NTT_ERR_TIMEOUT if still pending after timeout_us
+ * (< 0: wait forever), NTT_ERR_STATE for an unknown ticket. */
+int ntt_server_wait(ntt_server* server, uint64_t ticket, int64_t timeout_us);
+int ntt_server_get_stats(ntt_server* server, ntt_server_stats* stats);
+int ntt_server_reset_stats(ntt_server* server);
+void ntt_server_destroy(ntt_server* server);
+
 #ifdef __cplusplus
 }
 #endif

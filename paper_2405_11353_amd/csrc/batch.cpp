@@ -9,7 +9,6 @@
 #include <new>
 #include <vector>
 
-#include "ntt_core.hpp"
 #include "ntt_internal.hpp"
 
 namespace {

@@ -4,6 +4,39 @@
 #include "ntt_core.hpp"
 
 namespace nttk {
+
+// ============================================================ indirect helpers
+// Gather copy and pointwise product over items of mixed length: item i is
+// split into chunks of CHUNK words; grid.x = items * max_chunks.
+constexpr uint32_t kIndChunk = 4096;
+__global__ void __launch_bounds__(256)
+k_ind_copy(const ItemDesc* __restrict__ desc, uint32_t items, uint32_t max_chunks) {
+  const uint32_t item = blockIdx.x / max_chunks, chunk = blockIdx.x % max_chunks;
+  if (item >= items) return;
+  const ItemDesc d = desc[item];
+  const uint32_t n = 1u << (uint32_t)d.logN;
+  const uint32_t lo = chunk * kIndChunk;
+  if (lo >= n) return;
+  const uint32_t hi = lo + kIndChunk < n ? lo + kIndChunk : n;
+  const uint64_t* src = (const uint64_t*)d.aux;
+  uint64_t* dst = (uint64_t*)d.data;
+  for (uint32_t e = lo + threadIdx.x; e < hi; e += blockDim.x) dst[e] = src[e];
+}
+__global__ void __launch_bounds__(256)
+k_ind_pointwise(const ItemDesc* __restrict__ desc, uint32_t items, uint32_t max_chunks) {
+  const uint32_t item = blockIdx.x / max_chunks, chunk = blockIdx.x % max_chunks;
+  if (item >= items) return;
+  const ItemDesc d = desc[item];
+  const uint32_t n = 1u << (uint32_t)d.logN;
+  const uint32_t lo = chunk * kIndChunk;
+  if (lo >= n) return;
+  const uint32_t hi = lo + kIndChunk < n ? lo + kIndChunk : n;
+  const ModInfo64 m = *(const ModInfo64*)d.mod;
+  const uint64_t* b = (const uint64_t*)d.aux;
+  uint64_t* a = (uint64_t*)d.data;
+  for (uint32_t e = lo + threadIdx.x; e < hi; e += blockDim.x) a[e] = mulmod_general(a[e], b[e], m);
+}
+
 namespace {
 
 using A = Arith64<false>;
@@ -91,6 +124,20 @@ hipError_t launch_batch_u64(const BatchLaunch& c, bool fwd) {
     return col_sw(c.logN1, c, false, IO_SCRATCH_DATA);
   }
   return hipErrorNotSupported;
+}
+
+hipError_t launch_ind_copy(const ItemDesc* desc, uint32_t items, uint32_t max_logn, hipStream_t s) {
+  if (items == 0) return hipSuccess;
+  const uint32_t n = 1u << max_logn, chunks = (n + kIndChunk - 1) / kIndChunk;
+  hipLaunchKernelGGL(k_ind_copy, dim3(items * chunks), dim3(256), 0, s, desc, items, chunks);
+  return hipGetLastError();
+}
+
+hipError_t launch_ind_pointwise(const ItemDesc* desc, uint32_t items, uint32_t max_logn, hipStream_t s) {
+  if (items == 0) return hipSuccess;
+  const uint32_t n = 1u << max_logn, chunks = (n + kIndChunk - 1) / kIndChunk;
+  hipLaunchKernelGGL(k_ind_pointwise, dim3(items * chunks), dim3(256), 0, s, desc, items, chunks);
+  return hipGetLastError();
 }
 
 }  // namespace nttk

@@ -8,6 +8,22 @@ namespace nttk {
 
 enum Path { PATH_TINY = 0, PATH_LDS = 1, PATH_TWO = 2 };
 
+// One work item of the batched executor: a single (polynomial, limb) transform
+// with its own buffers, twiddle tables and modulus constants.
+struct ItemDesc {
+  void* data;            // N words: input and output of the transform
+  void* scratch;         // N words: four-step intermediate (natural order)
+  const void* tw_fwd;    // N twiddle pairs of the item's modulus and length
+  const void* tw_inv;
+  const void* mod;       // ModInfo64 / ModInfo32 of the item's modulus
+  const void* aux;       // copy: source; pointwise: second operand
+  uint64_t logN;         // copy / pointwise: log2 of the item's length
+  uint64_t pad;
+};
+// io codes for the four-step kernels in indirect mode
+enum { IO_DATA_DATA = 0, IO_DATA_SCRATCH = 1, IO_SCRATCH_DATA = 2 };
+
+
 struct Launch {
   int word = 64;      // 32 or 64-bit coefficients
   int exact = 0;      // 64-bit: exact Shoup quotient (lazy bound 2q) instead of approx (4q)
@@ -28,7 +44,6 @@ struct Launch {
 
 // Batched executor launch: items are described by a device table of ItemDesc
 // (64-bit words, natural order); PATH_LDS or PATH_TWO.
-struct ItemDesc;
 struct BatchLaunch {
   int path = PATH_LDS;
   int logN = 0, logN1 = 0;
@@ -37,6 +52,10 @@ struct BatchLaunch {
   hipStream_t stream = nullptr;
 };
 hipError_t launch_batch_u64(const BatchLaunch& c, bool forward);
+// item-wise copy (data <- aux) and product (data <- data * aux mod q) over
+// items of any length up to 2^max_logn
+hipError_t launch_ind_copy(const ItemDesc* desc, uint32_t items, uint32_t max_logn, hipStream_t s);
+hipError_t launch_ind_pointwise(const ItemDesc* desc, uint32_t items, uint32_t max_logn, hipStream_t s);
 
 // Each returns hipErrorNotSupported for a shape it has no kernel for.
 hipError_t launch_u64(const Launch& c, bool forward);

@@ -32,6 +32,7 @@
 
 #include <type_traits>
 
+#include "launch.hpp"
 #include "modarith.hpp"
 
 namespace nttk {
@@ -55,19 +56,6 @@ __device__ __forceinline__ void static_for_down(F&& f) {
 template <class A> struct ModOf;
 template <bool E> struct ModOf<Arith64<E>> { using type = ModInfo64; };
 template <> struct ModOf<Arith32> { using type = ModInfo32; };
-
-// One work item of the batched executor: a single (polynomial, limb) transform
-// with its own buffers, twiddle tables and modulus constants.
-struct ItemDesc {
-  void* data;            // N words: input and output of the transform
-  void* scratch;         // N words: four-step intermediate (natural order)
-  const void* tw_fwd;    // N twiddle pairs of the item's modulus and length
-  const void* tw_inv;
-  const void* mod;       // ModInfo64 / ModInfo32 of the item's modulus
-  uint64_t pad[3];
-};
-// io codes for the four-step kernels in indirect mode
-enum { IO_DATA_DATA = 0, IO_DATA_SCRATCH = 1, IO_SCRATCH_DATA = 2 };
 
 __device__ __forceinline__ uint32_t brv(uint32_t x, uint32_t bits) {
   return bits ? (__builtin_bitreverse32(x) >> (32 - bits)) : 0u;

@@ -36,6 +36,33 @@ class BatchInfo(ctypes.Structure):
                 ("twiddle_pool_bytes", ctypes.c_uint64)]
 
 
+NTT_REQ_NTT, NTT_REQ_INTT, NTT_REQ_POLYMUL = 0, 1, 2
+NTT_SERVER_SIMULATE = 0x1
+NTT_ERR_TIMEOUT = -9
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_uint32), ("N", ctypes.c_uint32), ("L", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("moduli", ctypes.POINTER(ctypes.c_uint64)),
+                ("d_a", ctypes.c_void_p), ("d_b", ctypes.c_void_p), ("d_out", ctypes.c_void_p)]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("n_streams", ctypes.c_uint32),
+                ("max_batch_items", ctypes.c_uint32), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("simulate_ns_per_item", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("failed", ctypes.c_uint64),
+                ("rejected", ctypes.c_uint64), ("queued", ctypes.c_uint64), ("batches", ctypes.c_uint64),
+                ("items", ctypes.c_uint64), ("ntts", ctypes.c_uint64), ("admission_stalls", ctypes.c_uint64),
+                ("peak_bytes", ctypes.c_uint64), ("max_inflight_batches", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("p50_us", ctypes.c_double), ("p99_us", ctypes.c_double),
+                ("mean_us", ctypes.c_double), ("max_us", ctypes.c_double), ("wall_s", ctypes.c_double),
+                ("busy_s", ctypes.c_double)]
+
+
 class TuneChoice(ctypes.Structure):
     _fields_ = [("path", ctypes.c_int32), ("log_n1", ctypes.c_int32), ("exact", ctypes.c_int32),
                 ("us_per_call", ctypes.c_float)]
@@ -87,6 +114,12 @@ def lib() -> ctypes.CDLL:
             "ntt_batch_run": (i32, [vp, vp]),
             "ntt_batch_get_info": (i32, [vp, ctypes.POINTER(BatchInfo)]),
             "ntt_batch_destroy": (None, [vp]),
+            "ntt_server_create": (vp, [ctypes.POINTER(ServerConfig)]),
+            "ntt_server_submit": (i32, [vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),
+            "ntt_server_wait": (i32, [vp, ctypes.c_uint64, ctypes.c_int64]),
+            "ntt_server_get_stats": (i32, [vp, ctypes.POINTER(ServerStats)]),
+            "ntt_server_reset_stats": (i32, [vp]),
+            "ntt_server_destroy": (None, [vp]),
             "ntt_strerror": (ctypes.c_char_p, [i32]),
         }
         for name, (res, args) in sig.items():
@@ -275,6 +308,59 @@ class Batch:
         if getattr(self, "handle", None):
             lib().ntt_batch_destroy(self.handle)
             self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class Server:
+    """ntt_server_* wrapper. submit() takes device tensors (or int addresses)."""
+
+    def __init__(self, hbm_budget_bytes=4 << 30, n_streams=4, max_batch_items=2048, flags=0,
+                 simulate_ns_per_item=0.0):
+        cfg = ServerConfig(hbm_budget_bytes, n_streams, max_batch_items, flags, 0, simulate_ns_per_item)
+        self.handle = lib().ntt_server_create(ctypes.byref(cfg))
+        if not self.handle:
+            raise NttError(ntt_last_error(), "ntt_server_create")
+        self._keep = {}
+
+    def submit(self, op, N, moduli, a, out, b=None) -> int:
+        mods = _u64_array(moduli)
+        req = Request(op, N, len(moduli), 0, mods, _ptr(a), _ptr(b) if b is not None else None, _ptr(out))
+        t = ctypes.c_uint64()
+        _check(lib().ntt_server_submit(self.handle, ctypes.byref(req), ctypes.byref(t)), "ntt_server_submit")
+        self._keep[t.value] = (mods, a, b, out)
+        return t.value
+
+    def wait(self, ticket: int, timeout_us: int = -1) -> int:
+        """Returns NTT_OK or an error code (NTT_ERR_TIMEOUT if still pending)."""
+        rc = lib().ntt_server_wait(self.handle, ticket, timeout_us)
+        if rc != NTT_ERR_TIMEOUT:
+            self._keep.pop(ticket, None)
+        return rc
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib().ntt_server_get_stats(self.handle, ctypes.byref(st)), "ntt_server_get_stats")
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_ if k != "reserved"}
+
+    def reset_stats(self):
+        _check(lib().ntt_server_reset_stats(self.handle), "ntt_server_reset_stats")
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().ntt_server_destroy(self.handle)
+            self.handle = None
+            self._keep.clear()
 
     def __del__(self):
         try:
