@@ -41,7 +41,188 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-per-call", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-jobs", type=int, default=3000)
     return ap.parse_args()
+
+
+def bench_batched(ntt, si, torch, reps=10):
+    """256 polynomials of uneven N (2^12..2^16) and limb count (1..32) in one
+    hipGraph launch, against eager launches and one call per polynomial."""
+    jobs = si.batched_jobs()
+    primes = si.batched_primes()
+    s = si.Stream(si.BASE_SEED + 30)
+    tensors, hosts = [], []
+    for j in jobs:
+        x = np.stack([s.uniform_mod(q, j.N) for q in primes[:j.L]])
+        hosts.append(x)
+        tensors.append(torch.from_numpy(x.view(np.int64)).cuda())
+    n_ntt = sum(j.L for j in jobs)
+    words = sum(j.L * j.N for j in jobs)
+    stream = torch.cuda.current_stream()
+    fwd = ntt.Batch([(j.N, primes[:j.L], ntt.NTT_JOB_FORWARD, t) for j, t in zip(jobs, tensors)])
+    inv = ntt.Batch([(j.N, primes[:j.L], ntt.NTT_JOB_INVERSE, t) for j, t in zip(jobs, tensors)])
+    eager = ntt.Batch([(j.N, primes[:j.L], ntt.NTT_JOB_FORWARD, t) for j, t in zip(jobs, tensors)],
+                      flags=ntt.NTT_BATCH_NO_GRAPH)
+    # exactness of the timed configuration: forward then inverse is the identity
+    fwd.run()
+    inv.run()
+    torch.cuda.synchronize()
+    exact = all(torch.equal(t, torch.from_numpy(h.view(np.int64)).cuda()) for t, h in zip(tensors[:64], hosts[:64]))
+
+    def timed(fn, n):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(n):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n * 1e3
+
+    us_graph = timed(fwd.run, reps)
+    us_eager = timed(eager.run, reps)
+    plans = {}
+    for j in jobs:
+        if (j.N, j.L) not in plans:
+            plans[(j.N, j.L)] = ntt.Plan(j.N, primes[:j.L])
+
+    def per_call():
+        for j, t in zip(jobs, tensors):
+            plans[(j.N, j.L)].forward(t, batch=1)
+
+    us_call = timed(per_call, max(2, reps // 2))
+    info = fwd.info
+    for b in (fwd, inv, eager):
+        b.close()
+    for p_ in plans.values():
+        p_.close()
+    res = {"workload": "batched_uneven_256polys", "polys": len(jobs), "ntts": n_ntt, "coefficients": words,
+           "graph_us": round(us_graph, 1), "graph_ntt_per_s": round(n_ntt / (us_graph * 1e-6), 1),
+           "graph_alg_GBs": round(16 * words / (us_graph * 1e-6) / 1e9, 1),
+           "eager_us": round(us_eager, 1), "per_call_us": round(us_call, 1),
+           "per_call_ntt_per_s": round(n_ntt / (us_call * 1e-6), 1),
+           "graph_speedup_vs_per_call": round(us_call / us_graph, 2),
+           "buckets": info["buckets"], "kernels": info["kernels"], "round_trip_exact": bool(exact)}
+    log(f"batched: {n_ntt} NTTs in {us_graph:.0f} us (graph), {us_eager:.0f} us (eager), "
+        f"{us_call:.0f} us (per-call) -> {res['graph_ntt_per_s'] / 1e6:.2f} M NTT/s")
+    return res
+
+
+def bench_serving(ntt, si, torch, n_jobs=3000, warm=300):
+    """Poisson stream of NTT and poly-mult jobs (N 2^12..2^17, L 1..40) at 70% of
+    the measured saturated rate through the server, against a per-call FIFO."""
+    import threading
+    primes = si.serving_primes()
+    s = si.Stream(si.BASE_SEED + 40)
+    logns = range(12, 18)
+    pool_a = {}
+    pool_b = {}
+    for lg in logns:
+        N = 1 << lg
+        a = np.stack([s.uniform_mod(q, N) for q in primes])
+        b = np.stack([s.uniform_mod(q, N) for q in primes])
+        pool_a[lg] = torch.from_numpy(a.view(np.int64)).cuda()
+        pool_b[lg] = torch.from_numpy(b.view(np.int64)).cuda()
+    ring = [torch.empty(40 << 17, dtype=torch.int64, device="cuda") for _ in range(64)]
+
+    def job_args(i, j):
+        lg = j.N.bit_length() - 1
+        op = ntt.NTT_REQ_POLYMUL if j.op == "polymul" else ntt.NTT_REQ_NTT
+        a = pool_a[lg][:j.L]
+        b = pool_b[lg][:j.L] if op == ntt.NTT_REQ_POLYMUL else None
+        return op, j.N, primes[:j.L], a, ring[i % len(ring)], b
+
+    def ntts_of(j):
+        return j.L * (3 if j.op == "polymul" else 1)
+
+    server = ntt.Server(hbm_budget_bytes=4 << 30, n_streams=4, max_batch_items=4096)
+
+    def prepare(jobs):
+        out = []
+        for i, j in enumerate(jobs):
+            op, N, mods, a, o, b = job_args(i, j)
+            out.append(server.make_request(op, N, mods, a, o, b))
+        return out
+
+    # saturated throughput: a burst of jobs, all queued at once (requests are
+    # prepared beforehand so the submit loop is the C call only)
+    burst = si.serving_trace(seed=si.BASE_SEED + 41, count=2000)
+    reqs = prepare(burst)
+    for r in reqs[:50]:                     # first sight of every (q, N): tables built
+        assert server.wait(server.submit_request(r)) == 0
+    t0 = time.perf_counter()
+    tk = [server.submit_request(r) for r in reqs]
+    for t in tk:
+        assert server.wait(t) == 0
+    sat_jobs_s = len(burst) / (time.perf_counter() - t0)
+    rate = 0.7 * sat_jobs_s
+    trace = si.serving_trace(count=warm + n_jobs, rate_per_s=rate)
+    treqs = prepare(trace)
+    server.reset_stats()
+
+    def replay_server():
+        tickets = []
+        start = time.perf_counter()
+        for i, j in enumerate(trace):
+            while time.perf_counter() - start < j.arrival_s:
+                pass
+            tickets.append(server.submit_request(treqs[i]))
+            if i == warm - 1:
+                server.reset_stats()
+        for t in tickets:
+            assert server.wait(t) == 0
+        return time.perf_counter() - start
+
+    wall = replay_server()
+    st = server.stats()
+    server.close()
+
+    # per-call FIFO: each job run on arrival with plain plan calls, one at a time
+    plans = {}
+    for j in trace:
+        if (j.N, j.L) not in plans:
+            plans[(j.N, j.L)] = ntt.Plan(j.N, primes[:j.L])
+    tmp_b = torch.empty(40 << 17, dtype=torch.int64, device="cuda")
+    fifo_lat = []
+    start = time.perf_counter()
+    for i, j in enumerate(trace):
+        while time.perf_counter() - start < j.arrival_s:
+            pass
+        op, N, mods, a, out, b = job_args(i, j)
+        p_ = plans[(j.N, j.L)]
+        o = out[:j.L * j.N].view(j.L, j.N)
+        o.copy_(a)
+        if op == ntt.NTT_REQ_NTT:
+            p_.forward(o, batch=1)
+        else:
+            bb = tmp_b[:j.L * j.N].view(j.L, j.N)
+            bb.copy_(b)
+            p_.forward(o, batch=1)
+            p_.forward(bb, batch=1)
+            p_.pointwise_inverse(o, bb, o, batch=1)
+        torch.cuda.synchronize()
+        if i >= warm:
+            fifo_lat.append((time.perf_counter() - start - j.arrival_s) * 1e6)
+    fifo_wall = time.perf_counter() - start
+    for p_ in plans.values():
+        p_.close()
+    fl = np.sort(np.array(fifo_lat))
+    res = {"workload": "serving_poisson_ntt_polymul", "jobs": n_jobs, "warmup_jobs": warm,
+           "offered_jobs_per_s": round(rate, 1), "saturated_jobs_per_s": round(sat_jobs_s, 1),
+           "p50_us": round(st["p50_us"], 1), "p99_us": round(st["p99_us"], 1),
+           "ntt_per_s": round(st["ntts"] / st["wall_s"], 1), "batches": st["batches"],
+           "mean_jobs_per_batch": round(st["completed"] / max(1, st["batches"]), 2),
+           "max_inflight_batches": st["max_inflight_batches"], "admission_stalls": st["admission_stalls"],
+           "hbm_budget_GiB": 4,
+           "per_call_fifo": {"p50_us": round(float(fl[len(fl) // 2]), 1),
+                             "p99_us": round(float(fl[int(0.99 * (len(fl) - 1))]), 1),
+                             "ntt_per_s": round(sum(ntts_of(j) for j in trace) / fifo_wall, 1)}}
+    log(f"serving: offered {rate:.0f} jobs/s; server p50 {res['p50_us']} us p99 {res['p99_us']} us; "
+        f"per-call FIFO p50 {res['per_call_fifo']['p50_us']} us p99 {res['per_call_fifo']['p99_us']} us")
+    return res
 
 
 def main():
@@ -215,6 +396,9 @@ def main():
         log(f"cpu oracle: {cpu['value']:.1f} NTT/s on {threads} threads; GPU sample bit-exact: {exact}")
         assert exact, "GPU result differs from the oracle on the CPU sample"
 
+    batched = None if args.no_batched else bench_batched(ntt, si, torch)
+    serving = None if args.no_serving else bench_serving(ntt, si, torch, n_jobs=args.serving_jobs)
+
     res = {
         "metric": "NTT/s at N=2^16 x 24 limbs (forward + inverse NTTs of a batched 2-ciphertext negacyclic product)",
         "value": round(value, 1),
@@ -236,6 +420,8 @@ def main():
         "per_call": per_call,
         "cpu_baseline": cpu,
         "ms_per_step_events": round(ms_event, 5),
+        "batched": batched,
+        "serving": serving,
     }
     print(json.dumps(res), flush=True)
 

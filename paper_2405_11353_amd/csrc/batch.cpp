@@ -81,8 +81,7 @@ static int build(ntt_batch* b, const ntt_job_desc* jobs, uint32_t n_jobs) {
     k.op = (int)J.op;
     for (uint32_t l = 0; l < J.L; ++l) {
       const uint64_t q = J.moduli[l];
-      if ((err = ntti::check_modulus(q, J.N, 64)) != NTT_OK) return err;
-      ntti::PoolEntry e;
+      ntti::PoolEntry e;  // the pool validates (q, N) when it first builds its tables
       if ((err = ntti::pool_get(64, q, (uint32_t)lg, &e)) != NTT_OK) return err;
       nttk::ItemDesc d{};
       d.data = (uint64_t*)J.d_data + ((size_t)l << lg);

@@ -33,6 +33,8 @@ int pool_get(int word, uint64_t q, uint32_t logN, PoolEntry* out) {
     return NTT_OK;
   }
   const uint32_t N = 1u << logN;
+  // validated once, when the tables are first built
+  if (check_modulus(q, N, word) != NTT_OK) return NTT_ERR_MODULUS;
   const uint64_t psi = nttp::default_psi(q, N);
   if (!psi) return NTT_ERR_MODULUS;
   const size_t tb = (size_t)N * nttp::tw_entry_bytes(word), mb = nttp::modinfo_bytes(word);

@@ -325,9 +325,16 @@ static void scheduler(ntt_server* s) {
         s->cv_done.notify_all();
       }
     }
-    // wait: short polls while batches run, otherwise until work arrives
-    if (s->inflight) s->cv_sched.wait_for(lk, std::chrono::microseconds(10));
-    else s->cv_sched.wait_for(lk, std::chrono::milliseconds(2), [s] { return s->stop || !s->pending.empty(); });
+    // while batches run, poll their events in a yield loop (the scheduler owns
+    // a core; a timed wait would add tens of microseconds of timer slack to
+    // every completion); otherwise sleep until work arrives
+    if (s->inflight) {
+      lk.unlock();
+      std::this_thread::yield();
+      lk.lock();
+    } else {
+      s->cv_sched.wait_for(lk, std::chrono::milliseconds(2), [s] { return s->stop || !s->pending.empty(); });
+    }
   }
 }
 
@@ -409,7 +416,10 @@ int ntt_server_submit(ntt_server* s, const ntt_request* r, uint64_t* ticket) {
   const size_t poly = (size_t)j->L * j->N * 8;
   j->ws_bytes = (j->op == NTT_REQ_POLYMUL ? poly : 0) + (j->fourstep ? poly * (j->op == NTT_REQ_POLYMUL ? 2 : 1) : 0);
   int rc = NTT_OK;
-  for (uint32_t l = 0; l < j->L && rc == NTT_OK; ++l) rc = ntti::check_modulus(r->moduli[l], r->N, 64);
+  // simulate mode validates here; otherwise the pool validates a modulus the
+  // first time it sees (q, N) and later submits only look the tables up
+  if (s->simulate)
+    for (uint32_t l = 0; l < j->L && rc == NTT_OK; ++l) rc = ntti::check_modulus(r->moduli[l], r->N, 64);
   if (rc == NTT_OK && j->ws_bytes > s->cfg.hbm_budget_bytes) rc = NTT_ERR_BUDGET;
   if (rc == NTT_OK && !s->simulate) {
     int cur = 0;

@@ -341,6 +341,18 @@ class Server:
         self._keep[t.value] = (mods, a, b, out)
         return t.value
 
+    def make_request(self, op, N, moduli, a, out, b=None):
+        """A prepared request (ctypes struct) for submit_request: builds the
+        moduli array and resolves the device pointers once."""
+        mods = _u64_array(moduli)
+        req = Request(op, N, len(moduli), 0, mods, _ptr(a), _ptr(b) if b is not None else None, _ptr(out))
+        return (req, mods, a, b, out)
+
+    def submit_request(self, prepared) -> int:
+        t = ctypes.c_uint64()
+        _check(lib().ntt_server_submit(self.handle, ctypes.byref(prepared[0]), ctypes.byref(t)), "ntt_server_submit")
+        return t.value
+
     def wait(self, ticket: int, timeout_us: int = -1) -> int:
         """Returns NTT_OK or an error code (NTT_ERR_TIMEOUT if still pending)."""
         rc = lib().ntt_server_wait(self.handle, ticket, timeout_us)
