@@ -32,6 +32,113 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# sources that determine the timed kernels' machine code; counter-derived
+# traffic is reported only while they are unchanged
+KERNEL_SOURCES = ["paper_2405_11353_amd/csrc/ntt_core.hpp", "paper_2405_11353_amd/csrc/modarith.hpp",
+                  "paper_2405_11353_amd/csrc/dispatch.inc", "paper_2405_11353_amd/csrc/k_u64.hip",
+                  "paper_2405_11353_amd/csrc/k_pointwise.hip", "paper_2405_11353_amd/csrc/launch.hpp"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "polymul_n65536_l24_traffic.json")
+# rocprofv3 kernel names -> the names bench.py times them under
+KERNEL_KEYS = [("k_col<nttk::Arith64<false>, 8, 16, true", "fwd_col_pass"),
+               ("k_row<nttk::Arith64<false>, 8, true, true", "fwd_row_pass"),
+               ("k_row<nttk::Arith64<false>, 8, false, true, true", "inv_row_pass_mul"),
+               ("k_col<nttk::Arith64<false>, 8, 16, false", "inv_col_pass"),
+               ("k_pointwise<nttk::ModInfo64", "pointwise")]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def bench_key(name: str):
+    for pat, key in KERNEL_KEYS:
+        if pat in name:
+            return key
+    return None
+
+
+def summarize_counters(d: str):
+    """Reads the rocprofv3 CSVs of one profiling session (kernel trace, FETCH_SIZE
+    and WRITE_SIZE passes on bench.py and on the 1 GiB copy microbenchmark, SQ
+    counters) from directory d and writes the summary files under profiles/."""
+    import csv
+    import collections
+    import glob
+
+    def pmc(sub):
+        agg = collections.defaultdict(lambda: collections.defaultdict(list))
+        for f in glob.glob(os.path.join(d, sub, "*counter_collection.csv")):
+            for r in csv.DictReader(open(f)):
+                agg[r["Kernel_Name"]][r["Counter_Name"]].append(float(r["Counter_Value"]))
+        return {k: {c: sum(v) / len(v) for c, v in cs.items()} for k, cs in agg.items()}
+
+    copy_f = [v["FETCH_SIZE"] for k, v in pmc("pmc_copy_fetch").items() if "k_copy" in k][0]
+    copy_w = [v["WRITE_SIZE"] for k, v in pmc("pmc_copy_write").items() if "k_copy" in k][0]
+    gib_kib = float(1 << 20)
+    f_scale, w_scale = gib_kib / copy_f, gib_kib / copy_w
+    fetch, write, sq = pmc("pmc_fetch"), pmc("pmc_write"), pmc("pmc_sq")
+    stats = {}
+    for f in glob.glob(os.path.join(d, "kt", "*kernel_stats.csv")):
+        for r in csv.DictReader(open(f)):
+            stats[r["Name"]] = r
+    out = {"source_hash": kernel_source_hash(), "fetch_scale": f_scale, "write_scale": w_scale, "kernels": {}}
+    lines = ["# Counters and kernel trace: polymul_n65536_l24 (N=2^16, 24 limbs, 2 ciphertexts), MI355X", "",
+             "Commands (repository root on the GPU box; each pass is its own run):", "",
+             "    B='python3 bench.py --steps 10 --warmup 2 --kernel-reps 5 --no-cpu-baseline --no-per-call --no-batched --no-serving'",
+             "    rocprofv3 --kernel-trace --stats --output-format csv -d <dir>/kt -o kt -- $B",
+             "    rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir>/pmc_fetch -o run -- $B",
+             "    rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir>/pmc_write -o run -- $B",
+             "    rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir>/pmc_copy_fetch -o run -- paper_2405_11353_amd/_build/ubench --copy-only",
+             "    rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir>/pmc_copy_write -o run -- paper_2405_11353_amd/_build/ubench --copy-only",
+             "    rocprofv3 --pmc SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT SQ_WAIT_INST_ANY SQ_WAVES --output-format csv -d <dir>/pmc_sq -o run -- $B",
+             "    python3 bench.py --summarize-counters <dir>", "",
+             f"Scale factors from the plain copy of 1 GiB (read 1 GiB, write 1 GiB per dispatch): "
+             f"FETCH_SIZE reads {copy_f:.0f} KiB -> x{f_scale:.3f}; WRITE_SIZE reads {copy_w:.0f} KiB -> x{w_scale:.3f}.",
+             f"Kernel source hash: {out['source_hash']}", "",
+             "| kernel | rocprof avg us | calls | scaled fetch MiB | scaled write MiB | VALU wave-instr | VALU busy | LDS bank conflicts |",
+             "|---|---|---|---|---|---|---|---|"]
+    for name in sorted(set(fetch) | set(stats)):
+        key = bench_key(name)
+        if key is None:
+            continue
+        avg_us = float(stats[name]["AverageNs"]) / 1e3 if name in stats else float("nan")
+        calls = stats[name]["Calls"] if name in stats else "-"
+        fb = fetch.get(name, {}).get("FETCH_SIZE", float("nan")) * 1024 * f_scale
+        wb = write.get(name, {}).get("WRITE_SIZE", float("nan")) * 1024 * w_scale
+        q = sq.get(name, {})
+        valu = q.get("SQ_INSTS_VALU", float("nan"))
+        busy = valu * 4 / (1024 * avg_us * 1e-6 * 2.4e9) if avg_us == avg_us else float("nan")
+        out["kernels"][key] = {"rocprof_avg_us": avg_us, "fetch_bytes": fb, "write_bytes": wb,
+                               "valu_wave_instr": valu, "lds_bank_conflicts": q.get("SQ_LDS_BANK_CONFLICT")}
+        lines.append(f"| {key} | {avg_us:.2f} | {calls} | {fb / 2**20:.1f} | {wb / 2**20:.1f} | {valu:.3g} | "
+                     f"{busy:.0%} | {q.get('SQ_LDS_BANK_CONFLICT', float('nan')):.3g} |")
+    lines += ["", "VALU busy = SQ_INSTS_VALU x 4 cycles / (1024 SIMDs x avg duration x 2.4 GHz)."]
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(out, fh, indent=1)
+    with open(os.path.join(ROOT, "profiles", "polymul_n65536_l24_counters.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def counter_traffic(key: str):
+    """Scaled HBM bytes of one launch of `key` from the stored counter summary,
+    or None if there is none or the kernel sources changed since."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != kernel_source_hash() or key not in t.get("kernels", {}):
+        return None
+    k = t["kernels"][key]
+    return round(k["fetch_bytes"] + k["write_bytes"])
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -44,6 +151,8 @@ def parse():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-jobs", type=int, default=3000)
+    ap.add_argument("--summarize-counters", metavar="DIR", default=None,
+                    help="write profiles/ summaries from a rocprofv3 session directory and exit")
     return ap.parse_args()
 
 
@@ -227,6 +336,9 @@ def bench_serving(ntt, si, torch, n_jobs=3000, warm=300):
 
 def main():
     args = parse()
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: the NTT batch is independent per (polynomial, limb), "
@@ -334,6 +446,8 @@ def main():
     else:
         roofline = {"bound": "hbm", "achieved": dk["hbm_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": dk["hbm_frac"], "traffic": None}
+    roofline["traffic"] = counter_traffic(dominant)
+    roofline["traffic_unit"] = "bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by a 1 GiB copy)"
     roofline["kernel"] = dominant
     roofline["avg_launch_us"] = dk["us"]
 
