@@ -18,6 +18,18 @@
 
 namespace nttk {
 
+// The arithmetic is __host__ __device__ so that the host build can be unit
+// tested against 128-bit integer arithmetic on the CPU.
+#define NTT_HD __host__ __device__ __forceinline__
+
+NTT_HD uint32_t umulhi32(uint32_t a, uint32_t b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __umulhi(a, b);
+#else
+  return (uint32_t)(((uint64_t)a * b) >> 32);
+#endif
+}
+
 // ---------------------------------------------------------------- 64-bit
 struct ModInfo64 {
   uint64_t q;     // modulus, q < 2^62
@@ -34,30 +46,30 @@ struct Tw64 {
   uint64_t wp;  // floor(w * 2^64 / q)
 };
 
-__device__ __forceinline__ uint32_t lo32(uint64_t x) { return (uint32_t)x; }
-__device__ __forceinline__ uint32_t hi32(uint64_t x) { return (uint32_t)(x >> 32); }
-__device__ __forceinline__ uint64_t mad32(uint32_t a, uint32_t b, uint64_t c) {
+NTT_HD uint32_t lo32(uint64_t x) { return (uint32_t)x; }
+NTT_HD uint32_t hi32(uint64_t x) { return (uint32_t)(x >> 32); }
+NTT_HD uint64_t mad32(uint32_t a, uint32_t b, uint64_t c) {
   return (uint64_t)a * b + c;  // v_mad_u64_u32
 }
 
 // Quotient estimate floor(y * wp / 2^64) minus 0, 1 or 2: drops the low half
 // of the two cross products and the whole low product (each < 2^64 in weight,
 // so the sum dropped is < 3 * 2^64).
-__device__ __forceinline__ uint64_t shoup_q_approx(uint64_t y, uint64_t wp) {
+NTT_HD uint64_t shoup_q_approx(uint64_t y, uint64_t wp) {
   uint32_t y0 = lo32(y), y1 = hi32(y), p0 = lo32(wp), p1 = hi32(wp);
-  uint64_t s = (uint64_t)__umulhi(y1, p0) + __umulhi(y0, p1);
+  uint64_t s = (uint64_t)umulhi32(y1, p0) + umulhi32(y0, p1);
   return mad32(y1, p1, s);
 }
 // Exact high half of y * wp.
-__device__ __forceinline__ uint64_t shoup_q_exact(uint64_t y, uint64_t wp) {
+NTT_HD uint64_t shoup_q_exact(uint64_t y, uint64_t wp) {
   uint32_t y0 = lo32(y), y1 = hi32(y), p0 = lo32(wp), p1 = hi32(wp);
-  uint64_t t = mad32(y1, p0, __umulhi(y0, p0));
+  uint64_t t = mad32(y1, p0, umulhi32(y0, p0));
   uint64_t u = mad32(y0, p1, lo32(t));
   return mad32(y1, p1, (uint64_t)hi32(t) + hi32(u));
 }
 // r = y*w - Q*q mod 2^64, computed as y*w + Q*(2^64 - q): the true value is
 // below 2^64 whenever Q is one of the estimates above.
-__device__ __forceinline__ uint64_t shoup_r(uint64_t y, uint64_t w, uint64_t Q, uint64_t nq) {
+NTT_HD uint64_t shoup_r(uint64_t y, uint64_t w, uint64_t Q, uint64_t nq) {
   uint32_t y0 = lo32(y), y1 = hi32(y), w0 = lo32(w), w1 = hi32(w);
   uint32_t Q0 = lo32(Q), Q1 = hi32(Q), n0 = lo32(nq), n1 = hi32(nq);
   uint64_t lo = mad32(Q0, n0, mad32(y0, w0, 0));
@@ -72,43 +84,43 @@ struct Arith64 {
   static constexpr bool kExact = EXACT;
   uint64_t q, L, nq;
 
-  __device__ __forceinline__ void load(const ModInfo64& m) { q = m.q; L = EXACT ? 2 * m.q : 4 * m.q; nq = m.nq; }
+  NTT_HD void load(const ModInfo64& m) { q = m.q; L = EXACT ? 2 * m.q : 4 * m.q; nq = m.nq; }
 
   // y * w mod q, result in [0, L) (L = 4q approx, 2q exact), any y < 2^64
-  __device__ __forceinline__ uint64_t mul(uint64_t y, const Tw64& t) const {
+  NTT_HD uint64_t mul(uint64_t y, const Tw64& t) const {
     uint64_t Q = EXACT ? shoup_q_exact(y, t.wp) : shoup_q_approx(y, t.wp);
     return shoup_r(y, t.w, Q, nq);
   }
-  __device__ __forceinline__ static uint64_t csub(uint64_t x, uint64_t m) { return x >= m ? x - m : x; }
+  NTT_HD static uint64_t csub(uint64_t x, uint64_t m) { return x >= m ? x - m : x; }
 
   // Cooley-Tukey butterfly (x, y) -> (x + w y, x - w y); values in [0, 2L)
-  __device__ __forceinline__ void ct(uint64_t& x, uint64_t& y, const Tw64& t) const {
+  NTT_HD void ct(uint64_t& x, uint64_t& y, const Tw64& t) const {
     uint64_t xr = csub(x, L);
     uint64_t T = mul(y, t);
     x = xr + T;
     y = xr + L - T;
   }
   // Gentleman-Sande butterfly (x, y) -> (x + y, (x - y) w); values in [0, L)
-  __device__ __forceinline__ void gs(uint64_t& x, uint64_t& y, const Tw64& t) const {
+  NTT_HD void gs(uint64_t& x, uint64_t& y, const Tw64& t) const {
     uint64_t s = x + y;
     uint64_t d = x + L - y;
     x = csub(s, L);
     y = mul(d, t);
   }
   // last inverse stage: both outputs scaled (N^-1 folded into two twiddles)
-  __device__ __forceinline__ void gs_last(uint64_t& x, uint64_t& y, const Tw64& t0, const Tw64& t1) const {
+  NTT_HD void gs_last(uint64_t& x, uint64_t& y, const Tw64& t0, const Tw64& t1) const {
     uint64_t s = x + y;
     uint64_t d = x + L - y;
     x = mul(s, t0);
     y = mul(d, t1);
   }
   // canonical from [0, 2L) (forward) or [0, L) (inverse)
-  __device__ __forceinline__ uint64_t canon_fwd(uint64_t x) const {
+  NTT_HD uint64_t canon_fwd(uint64_t x) const {
     x = csub(x, L);
     if (!EXACT) x = csub(x, 2 * q);
     return csub(x, q);
   }
-  __device__ __forceinline__ uint64_t canon_inv(uint64_t x) const {
+  NTT_HD uint64_t canon_inv(uint64_t x) const {
     if (!EXACT) x = csub(x, 2 * q);
     return csub(x, q);
   }
@@ -117,7 +129,7 @@ struct Arith64 {
 // General product x*y mod q for the pointwise kernel (neither operand known in
 // advance): Montgomery reduction of the 128-bit product gives x*y*2^-64 in
 // (-q, q), then a Shoup product by 2^64 mod q restores the factor.
-__device__ __forceinline__ uint64_t mulmod_general(uint64_t x, uint64_t y, const ModInfo64& m) {
+NTT_HD uint64_t mulmod_general(uint64_t x, uint64_t y, const ModInfo64& m) {
   uint32_t x0 = lo32(x), x1 = hi32(x), y0 = lo32(y), y1 = hi32(y);
   // 128-bit product t = th:tl
   uint64_t p00 = mad32(x0, y0, 0);
@@ -164,43 +176,43 @@ struct Arith32 {
   using tw_t = Tw32;
   static constexpr bool kExact = true;
   uint32_t q, L;
-  __device__ __forceinline__ void load(const ModInfo32& m) { q = m.q; L = 2 * m.q; }
+  NTT_HD void load(const ModInfo32& m) { q = m.q; L = 2 * m.q; }
   // Shoup at w = 32 (Alg. 5 with the paper's word size): result in [0, 2q)
-  __device__ __forceinline__ uint32_t mul(uint32_t y, const Tw32& t) const {
-    uint32_t Q = __umulhi(y, t.wp);
+  NTT_HD uint32_t mul(uint32_t y, const Tw32& t) const {
+    uint32_t Q = umulhi32(y, t.wp);
     return y * t.w - Q * q;
   }
-  __device__ __forceinline__ static uint32_t csub(uint32_t x, uint32_t m) { return x >= m ? x - m : x; }
-  __device__ __forceinline__ void ct(uint32_t& x, uint32_t& y, const Tw32& t) const {
+  NTT_HD static uint32_t csub(uint32_t x, uint32_t m) { return x >= m ? x - m : x; }
+  NTT_HD void ct(uint32_t& x, uint32_t& y, const Tw32& t) const {
     uint32_t xr = csub(x, L);
     uint32_t T = mul(y, t);
     x = xr + T;
     y = xr + L - T;
   }
-  __device__ __forceinline__ void gs(uint32_t& x, uint32_t& y, const Tw32& t) const {
+  NTT_HD void gs(uint32_t& x, uint32_t& y, const Tw32& t) const {
     uint32_t s = x + y;
     uint32_t d = x + L - y;
     x = csub(s, L);
     y = mul(d, t);
   }
-  __device__ __forceinline__ void gs_last(uint32_t& x, uint32_t& y, const Tw32& t0, const Tw32& t1) const {
+  NTT_HD void gs_last(uint32_t& x, uint32_t& y, const Tw32& t0, const Tw32& t1) const {
     uint32_t s = x + y;
     uint32_t d = x + L - y;
     x = mul(s, t0);
     y = mul(d, t1);
   }
-  __device__ __forceinline__ uint32_t canon_fwd(uint32_t x) const { return csub(csub(x, L), q); }
-  __device__ __forceinline__ uint32_t canon_inv(uint32_t x) const { return csub(x, q); }
+  NTT_HD uint32_t canon_fwd(uint32_t x) const { return csub(csub(x, L), q); }
+  NTT_HD uint32_t canon_inv(uint32_t x) const { return csub(x, q); }
 };
 
-__device__ __forceinline__ uint32_t mulmod_general(uint32_t x, uint32_t y, const ModInfo32& m) {
+NTT_HD uint32_t mulmod_general(uint32_t x, uint32_t y, const ModInfo32& m) {
   uint64_t t = (uint64_t)x * y;
   uint32_t u = (uint32_t)t * m.qinv;                 // t - u q = 0 mod 2^32
-  uint32_t uq_hi = __umulhi(u, m.q);
+  uint32_t uq_hi = umulhi32(u, m.q);
   uint32_t th = (uint32_t)(t >> 32);
   uint32_t r = th - uq_hi;
   r = (th < uq_hi) ? r + m.q : r;                    // x y 2^-32 mod q
-  uint32_t Q = __umulhi(r, m.r1p);
+  uint32_t Q = umulhi32(r, m.r1p);
   uint32_t z = r * m.r1 - Q * m.q;                   // [0, 2q)
   return z >= m.q ? z - m.q : z;
 }

@@ -1,0 +1,136 @@
+// Host unit test of the GPU library's modular arithmetic (modarith.hpp, built
+// for the CPU) against exact 128-bit arithmetic: the Shoup quotient estimates,
+// the lazy-range invariants of the butterflies, canonicalisation and the
+// general products. Prints "ok <checks>" or the first failure; exit code 0/1.
+#include <stdint.h>
+#include <stdio.h>
+
+#include "modarith.hpp"
+
+using namespace nttk;
+typedef unsigned __int128 u128;
+
+static uint64_t rng_state = 0x9E3779B97F4A7C15ull;
+static uint64_t rnd() {  // xorshift64*: test-only generator
+  rng_state ^= rng_state >> 12;
+  rng_state ^= rng_state << 25;
+  rng_state ^= rng_state >> 27;
+  return rng_state * 0x2545F4914F6CDD1Dull;
+}
+static long checks = 0;
+#define CHECK(c, ...)                                            \
+  do {                                                           \
+    ++checks;                                                    \
+    if (!(c)) {                                                  \
+      printf("FAIL line %d: ", __LINE__);                        \
+      printf(__VA_ARGS__);                                       \
+      printf("\n");                                              \
+      return 1;                                                  \
+    }                                                            \
+  } while (0)
+
+static uint64_t mulm(uint64_t a, uint64_t b, uint64_t q) { return (uint64_t)((u128)a * b % q); }
+
+static int test64(uint64_t q) {
+  const uint64_t nq = 0 - q;
+  uint64_t inv = q;
+  for (int i = 0; i < 6; ++i) inv *= 2 - q * inv;
+  ModInfo64 m{};
+  m.q = q;
+  m.nq = nq;
+  m.qinv = inv;
+  m.r1 = (uint64_t)(((u128)1 << 64) % q);
+  m.r1p = (uint64_t)(((u128)m.r1 << 64) / q);
+  Arith64<false> A;
+  A.load(m);
+  Arith64<true> X;
+  X.load(m);
+  CHECK(A.L == 4 * q && X.L == 2 * q, "lazy bounds");
+  const uint64_t ys_edge[] = {0, 1, 2, q - 1, q, 2 * q - 1, 4 * q - 1, 8 * q - 1, (1ull << 32) - 1, 1ull << 32,
+                              (1ull << 32) + 1, ~0ull, ~0ull - 1, 1ull << 63, (1ull << 63) - 1};
+  const uint64_t ws_edge[] = {0, 1, 2, q - 1, q - 2, q / 2, (1ull << 32) - 1, 1ull << 32, q / 3};
+  for (int it = 0; it < 300000; ++it) {
+    const uint64_t y = it < 15 * 9 ? ys_edge[it / 9] : (it & 1 ? rnd() : rnd() % (8 * q));
+    const uint64_t w = it < 15 * 9 ? ws_edge[it % 9] % q : rnd() % q;  // twiddles are residues
+    const uint64_t wp = (uint64_t)(((u128)w << 64) / q);
+    const Tw64 t{w, wp};
+    const uint64_t Qt = (uint64_t)(((u128)y * wp) >> 64);
+    const uint64_t Qa = shoup_q_approx(y, wp), Qe = shoup_q_exact(y, wp);
+    CHECK(Qe == Qt, "exact quotient y=%llu w=%llu", (unsigned long long)y, (unsigned long long)w);
+    CHECK(Qa <= Qt && Qt - Qa <= 2, "approx quotient off by %llu", (unsigned long long)(Qt - Qa));
+    const uint64_t ra = A.mul(y, t), re = X.mul(y, t);
+    const uint64_t want = mulm(y % q, w, q);
+    CHECK(ra < 4 * q && ra % q == want, "approx product range/value");
+    CHECK(re < 2 * q && re % q == want, "exact product range/value");
+    // butterflies: forward inputs anywhere in [0, 2L), inverse in [0, L)
+    const uint64_t x8 = rnd() % (8 * q), y8 = rnd() % (8 * q);
+    uint64_t a0 = x8, b0 = y8;
+    A.ct(a0, b0, t);
+    CHECK(a0 < 8 * q && b0 < 8 * q, "ct range");
+    CHECK(a0 % q == (x8 % q + mulm(y8 % q, w, q)) % q, "ct sum");
+    CHECK(b0 % q == (x8 % q + q - mulm(y8 % q, w, q)) % q, "ct difference");
+    const uint64_t x4 = rnd() % (4 * q), y4 = rnd() % (4 * q);
+    a0 = x4;
+    b0 = y4;
+    A.gs(a0, b0, t);
+    CHECK(a0 < 4 * q && b0 < 4 * q, "gs range");
+    CHECK(a0 % q == (x4 % q + y4 % q) % q, "gs sum");
+    CHECK(b0 % q == mulm((x4 % q + q - y4 % q) % q, w, q), "gs difference");
+    const uint64_t x4e = rnd() % (4 * q), y4e = rnd() % (4 * q);
+    a0 = x4e;
+    b0 = y4e;
+    X.ct(a0, b0, t);
+    CHECK(a0 < 4 * q && b0 < 4 * q, "exact ct range");
+    CHECK(A.canon_fwd(x8) == x8 % q && A.canon_inv(x4) == x4 % q, "canonical (approx)");
+    CHECK(X.canon_fwd(x4e) == x4e % q && X.canon_inv(x4e % (2 * q)) == (x4e % (2 * q)) % q, "canonical (exact)");
+    // general product
+    const uint64_t u = rnd() % q, v = it < 9 ? ws_edge[it] % q : rnd() % q;
+    CHECK(mulmod_general(u, v, m) == mulm(u, v, q), "general product");
+  }
+  return 0;
+}
+
+static int test32(uint32_t q) {
+  uint32_t inv = q;
+  for (int i = 0; i < 5; ++i) inv *= 2u - q * inv;
+  ModInfo32 m{};
+  m.q = q;
+  m.qinv = inv;
+  m.r1 = (uint32_t)((1ull << 32) % q);
+  m.r1p = (uint32_t)(((uint64_t)m.r1 << 32) / q);
+  Arith32 A;
+  A.load(m);
+  for (int it = 0; it < 300000; ++it) {
+    const uint32_t y = (uint32_t)rnd(), w = (uint32_t)(rnd() % q);
+    const Tw32 t{w, (uint32_t)(((uint64_t)w << 32) / q)};
+    const uint32_t r = A.mul(y, t);
+    CHECK(r < 2 * q && r % q == (uint32_t)((uint64_t)(y % q) * w % q), "32-bit product");
+    const uint32_t x4 = (uint32_t)(rnd() % (4ull * q)), y4 = (uint32_t)(rnd() % (4ull * q));
+    uint32_t a0 = x4, b0 = y4;
+    A.ct(a0, b0, t);
+    CHECK(a0 < 4 * q && b0 < 4 * q, "32-bit ct range");
+    CHECK(a0 % q == (uint32_t)((x4 % q + (uint64_t)(y4 % q) * w % q) % q), "32-bit ct sum");
+    const uint32_t x2 = (uint32_t)(rnd() % (2ull * q)), y2 = (uint32_t)(rnd() % (2ull * q));
+    a0 = x2;
+    b0 = y2;
+    A.gs(a0, b0, t);
+    CHECK(a0 < 2 * q && b0 < 2 * q, "32-bit gs range");
+    CHECK(A.canon_fwd(x4) == x4 % q && A.canon_inv(x2) == x2 % q, "32-bit canonical");
+    const uint32_t u = (uint32_t)(rnd() % q), v = (uint32_t)(rnd() % q);
+    CHECK(mulmod_general(u, v, m) == (uint32_t)((uint64_t)u * v % q), "32-bit general product");
+  }
+  return 0;
+}
+
+int main() {
+  // largest supported 64-bit size class (just below 2^61) and the workload primes
+  const uint64_t q64[] = {2305843009213693951ull /* 2^61 - 1 (prime) */, 1152921504606584833ull,
+                          1152921504606748673ull, 1152921504605798401ull, 998244353ull, 12289ull};
+  for (uint64_t q : q64)
+    if (test64(q)) return 1;
+  const uint32_t q32[] = {998244353u, 469762049u, 167772161u, 1073479681u /* < 2^30 */, 12289u};
+  for (uint32_t q : q32)
+    if (test32(q)) return 1;
+  printf("ok %ld\n", checks);
+  return 0;
+}
