@@ -89,7 +89,7 @@ def summarize_counters(d: str):
     out = {"source_hash": kernel_source_hash(), "fetch_scale": f_scale, "write_scale": w_scale, "kernels": {}}
     lines = ["# Counters and kernel trace: polymul_n65536_l24 (N=2^16, 24 limbs, 2 ciphertexts), MI355X", "",
              "Commands (repository root on the GPU box; each pass is its own run):", "",
-             "    B='python3 bench.py --steps 10 --warmup 2 --kernel-reps 5 --no-cpu-baseline --no-per-call --no-batched --no-serving'",
+             "    B='python3 bench.py --steps 10 --warmup 2 --kernel-reps 5 --no-cpu-baseline --no-per-call --no-batched --no-serving --no-paper-sizes'",
              "    rocprofv3 --kernel-trace --stats --output-format csv -d <dir>/kt -o kt -- $B",
              "    rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir>/pmc_fetch -o run -- $B",
              "    rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir>/pmc_write -o run -- $B",
@@ -150,6 +150,7 @@ def parse():
     ap.add_argument("--no-per-call", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-paper-sizes", action="store_true")
     ap.add_argument("--serving-jobs", type=int, default=3000)
     ap.add_argument("--summarize-counters", metavar="DIR", default=None,
                     help="write profiles/ summaries from a rocprofv3 session directory and exit")
@@ -218,6 +219,47 @@ def bench_batched(ntt, si, torch, reps=10):
     log(f"batched: {n_ntt} NTTs in {us_graph:.0f} us (graph), {us_eager:.0f} us (eager), "
         f"{us_call:.0f} us (per-call) -> {res['graph_ntt_per_s'] / 1e6:.2f} M NTT/s")
     return res
+
+
+# Table 1 of the paper: best FPGA latency per size (Pease_nc; 16 cores at
+# 1K-16K, 4 cores at 64K), cyclic transform, 32-bit prime -- context only
+PAPER_TABLE1_BEST_FPGA_US = {1024: 2.27, 4096: 8.60, 16384: 37.50, 65536: 669.30}
+
+
+def bench_paper_sizes(ntt, si, torch, reps=100, batch=1024):
+    """The paper's own setting: one cyclic transform with a 32-bit prime at
+    1K/4K/16K/64K, timed as the mean of 100 runs between device-resident
+    input and output (the paper's GPU methodology), plus batched throughput."""
+    q = si.Q_SMALL
+    stream = torch.cuda.current_stream()
+    out = []
+    for N in (1024, 4096, 16384, 65536):
+        plan = ntt.Plan(N, [q], flags=ntt.NTT_CYCLIC | ntt.NTT_WORD32)
+        x = si.Stream(si.BASE_SEED + 50).uniform_mod(q, N).astype(np.uint32)
+        one = torch.from_numpy(x.view(np.int32)).cuda()
+        many = one.repeat(batch)
+        row = {"N": N}
+        for name, buf, b in (("single", one, 1), ("batched", many, batch)):
+            plan.forward(buf, batch=b)
+            plan.inverse(buf, batch=b)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                plan.forward(buf, batch=b)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            us = e0.elapsed_time(e1) / reps * 1e3
+            if name == "single":
+                row["single_us"] = round(us, 3)
+            else:
+                row["batched_ntt_per_s"] = round(b / (us * 1e-6), 1)
+                row["batched_alg_GBs"] = round(8 * N * b / (us * 1e-6) / 1e9, 1)
+        row["paper_table1_best_fpga_us"] = PAPER_TABLE1_BEST_FPGA_US[N]
+        out.append(row)
+        log(f"paper size N={N}: single {row['single_us']} us, batched {row['batched_ntt_per_s'] / 1e6:.1f} M NTT/s")
+        plan.close()
+    return {"workload": "cyclic_u32_q998244353_single_and_batched", "reps": reps, "batch": batch, "sizes": out}
 
 
 def bench_serving(ntt, si, torch, n_jobs=3000, warm=300):
@@ -512,6 +554,7 @@ def main():
 
     batched = None if args.no_batched else bench_batched(ntt, si, torch)
     serving = None if args.no_serving else bench_serving(ntt, si, torch, n_jobs=args.serving_jobs)
+    paper_sizes = None if args.no_paper_sizes else bench_paper_sizes(ntt, si, torch)
 
     res = {
         "metric": "NTT/s at N=2^16 x 24 limbs (forward + inverse NTTs of a batched 2-ciphertext negacyclic product)",
@@ -536,6 +579,7 @@ def main():
         "ms_per_step_events": round(ms_event, 5),
         "batched": batched,
         "serving": serving,
+        "paper_sizes": paper_sizes,
     }
     print(json.dumps(res), flush=True)
 

@@ -58,6 +58,9 @@ extern "C" {
 /* ---- plan flags ---------------------------------------------------------- */
 #define NTT_WORD32 0x1u          /* uint32_t words, every q_l < 2^30            */
 #define NTT_ORDER_BITREV 0x2u    /* spectrum in bit-reversed order              */
+#define NTT_CYCLIC 0x4u          /* the cyclic transform of Eq. 3 instead:      */
+                                 /*   X_k = sum_j x_j omega^(jk), omega = c^((q-1)/N), */
+                                 /*   inverse with N^-1; needs N | q-1          */
 
 /* ---- kernel variants (for tuning and measurement) ------------------------- */
 #define NTT_PATH_AUTO 0          /* library default for (N, word)               */
@@ -76,7 +79,8 @@ ntt_plan* ntt_plan_create(uint32_t N, const uint64_t* moduli, uint32_t L);
 
 /* As ntt_plan_create with NTT_* flags and optional per-limb roots: psi may be
  * NULL (default root above) or L values, each a primitive 2N-th root of unity
- * mod q_l (checked: psi^N == q_l - 1). */
+ * mod q_l (checked: psi^N == q_l - 1), or with NTT_CYCLIC a primitive N-th
+ * root omega (checked: omega^(N/2) == q_l - 1). */
 ntt_plan* ntt_plan_create_ex(uint32_t N, const uint64_t* moduli, uint32_t L, uint32_t flags,
                              const uint64_t* psi);
 
@@ -114,7 +118,8 @@ int ntt_pointwise_mul_inverse_stage(const ntt_plan* plan, const void* d_a, const
                                     uint32_t batch, int stage, void* stream);
 int ntt_inverse_stage(const ntt_plan* plan, void* d_data, uint32_t batch, int stage, void* stream);
 
-/* Plan queries: the root used for each limb (L values) and the variant. */
+/* Plan queries: the root used for each limb (L values: psi, or omega for
+ * NTT_CYCLIC plans) and the variant. */
 int ntt_plan_get_psi(const ntt_plan* plan, uint64_t* psi_out);
 int ntt_plan_get_variant(const ntt_plan* plan, int* path, int* log_n1);
 

@@ -55,6 +55,10 @@ def lib():
             "orc_pointwise": (None, [p64, p64, p64, u32, u64]),
             "orc_negacyclic_mul": (None, [p64, p64, p64, u32, u64]),
             "orc_negacyclic_coeff": (u64, [p64, p64, u32, u64, u32]),
+            "orc_omega": (u64, [u64, u32]),
+            "orc_ntt_cyclic_forward": (None, [p64, u32, u64, u64]),
+            "orc_ntt_cyclic_inverse": (None, [p64, u32, u64, u64]),
+            "orc_ntt_cyclic_direct_coeff": (u64, [p64, u32, u64, u64, u32]),
             "orc_ntt_forward_batch": (ctypes.c_int, [p64, u32, u32, u32, p64, p64, ctypes.c_int]),
             "orc_ntt_inverse_batch": (ctypes.c_int, [p64, u32, u32, u32, p64, p64, ctypes.c_int]),
             "orc_pointwise_batch": (ctypes.c_int, [p64, p64, p64, u32, u32, u32, p64, ctypes.c_int]),
@@ -150,6 +154,28 @@ def negacyclic_mul(a, b, q):
 def negacyclic_coeff(a, b, q, k):
     a, b = _u64(a), _u64(b)
     return int(lib().orc_negacyclic_coeff(_p(a), _p(b), a.size, q, k))
+
+
+# ---- cyclic transform (Eq. 3) ------------------------------------------------------
+def omega(q, N):
+    return int(lib().orc_omega(q, N))
+
+
+def cyclic_forward(x, q, root=None):
+    y = _u64(x).copy()
+    lib().orc_ntt_cyclic_forward(_p(y), y.size, q, root if root is not None else omega(q, y.size))
+    return y
+
+
+def cyclic_inverse(X, q, root=None):
+    y = _u64(X).copy()
+    lib().orc_ntt_cyclic_inverse(_p(y), y.size, q, root if root is not None else omega(q, y.size))
+    return y
+
+
+def cyclic_direct_coeff(x, q, k, root=None):
+    x = _u64(x)
+    return int(lib().orc_ntt_cyclic_direct_coeff(_p(x), x.size, q, root if root is not None else omega(q, x.size), k))
 
 
 # ---- batched [B][L][N] drivers (in place on a copy) ------------------------------

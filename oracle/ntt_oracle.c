@@ -140,6 +140,34 @@ void orc_ntt_inverse(uint64_t* x, uint32_t N, uint64_t q, uint64_t psi) {
   free(P); free(W);
 }
 
+/* ---- cyclic transform (Eq. 3 as printed) ------------------------------ */
+uint64_t orc_omega(uint64_t q, uint32_t N) {
+  if (N == 0 || (q - 1) % N != 0) return 0;
+  uint64_t c = orc_smallest_qnr(q);
+  if (!c) return 0;
+  return orc_powmod(c, (q - 1) / N, q);
+}
+void orc_ntt_cyclic_forward(uint64_t* x, uint32_t N, uint64_t q, uint64_t omega) {
+  uint64_t* W = orc_power_table(omega, N, q);
+  orc_dit_cyclic(x, N, q, W);
+  free(W);
+}
+void orc_ntt_cyclic_inverse(uint64_t* x, uint32_t N, uint64_t q, uint64_t omega) {
+  uint64_t* W = orc_power_table(orc_invmod(omega, q), N, q);
+  uint64_t n_inv = orc_invmod(N % q, q);
+  orc_dif_cyclic(x, N, q, W);
+  for (uint32_t j = 0; j < N; ++j) x[j] = orc_mulmod(x[j], n_inv, q);
+  free(W);
+}
+uint64_t orc_ntt_cyclic_direct_coeff(const uint64_t* x, uint32_t N, uint64_t q, uint64_t omega, uint32_t k) {
+  uint64_t step = orc_powmod(omega, k, q), pw = 1 % q, acc = 0;
+  for (uint32_t j = 0; j < N; ++j) {
+    acc = orc_addmod(acc, orc_mulmod(x[j], pw, q), q);
+    pw = orc_mulmod(pw, step, q);
+  }
+  return acc;
+}
+
 /* Direct evaluation of the definition, X_k = sum_j x_j psi^((2k+1) j), with
  * the exponent reduced mod 2N (psi has order 2N).                          */
 uint64_t orc_ntt_direct_coeff(const uint64_t* x, uint32_t N, uint64_t q, uint64_t psi, uint32_t k) {

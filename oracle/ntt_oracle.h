@@ -60,6 +60,16 @@ void orc_pointwise(const uint64_t* a, const uint64_t* b, uint64_t* c, uint32_t N
 void orc_negacyclic_mul(const uint64_t* a, const uint64_t* b, uint64_t* c, uint32_t N, uint64_t q);
 uint64_t orc_negacyclic_coeff(const uint64_t* a, const uint64_t* b, uint32_t N, uint64_t q, uint32_t k);
 
+/* --- the cyclic transform of Eq. 3, X_k = sum_j x_j W_N^(jk), W_N = omega --- */
+/* omega = c^((q-1)/N), c the smallest quadratic non-residue; 0 if N does not divide q-1 */
+uint64_t orc_omega(uint64_t q, uint32_t N);
+/* the paper's DIT (Alg. 1) as printed (with the loop-bound reading of the
+ * negacyclic version), natural order in and out                              */
+void orc_ntt_cyclic_forward(uint64_t* x, uint32_t N, uint64_t q, uint64_t omega);
+/* DIF (Alg. 2) with omega^-1, bit_reverse, scale by N^-1                     */
+void orc_ntt_cyclic_inverse(uint64_t* x, uint32_t N, uint64_t q, uint64_t omega);
+uint64_t orc_ntt_cyclic_direct_coeff(const uint64_t* x, uint32_t N, uint64_t q, uint64_t omega, uint32_t k);
+
 /* --- batched drivers over a row-major [B][L][N] array (limb l uses q[l]) ---
  * nthreads <= 0 means all OpenMP threads; returns the thread count used.    */
 int orc_ntt_forward_batch(uint64_t* x, uint32_t B, uint32_t L, uint32_t N,

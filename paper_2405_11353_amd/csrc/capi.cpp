@@ -100,7 +100,7 @@ const char* ntt_strerror(int code) {
 ntt_plan* ntt_plan_create_ex(uint32_t N, const uint64_t* moduli, uint32_t L, uint32_t flags,
                              const uint64_t* psi) {
   g_last_error = NTT_OK;
-  if (!moduli || L == 0 || (flags & ~(NTT_WORD32 | NTT_ORDER_BITREV))) {
+  if (!moduli || L == 0 || (flags & ~(NTT_WORD32 | NTT_ORDER_BITREV | NTT_CYCLIC))) {
     fail(NTT_ERR_ARG);
     return nullptr;
   }
@@ -109,22 +109,25 @@ ntt_plan* ntt_plan_create_ex(uint32_t N, const uint64_t* moduli, uint32_t L, uin
     return nullptr;
   }
   const int word = (flags & NTT_WORD32) ? 32 : 64;
+  const bool cyclic = (flags & NTT_CYCLIC) != 0;
   std::vector<uint64_t> roots(L);
   for (uint32_t l = 0; l < L; ++l) {
     const uint64_t q = moduli[l];
-    if (ntti::check_modulus(q, N, word) != NTT_OK) {
+    // the cyclic transform needs N | q-1; the negacyclic one 2N | q-1
+    if (ntti::check_modulus(q, cyclic ? N / 2 : N, word) != NTT_OK) {
       fail(NTT_ERR_MODULUS);
       return nullptr;
     }
     if (psi) {
+      // a primitive 2N-th (negacyclic) or N-th (cyclic) root: r^(order/2) = -1
       const uint64_t r = psi[l];
-      if (r == 0 || r >= q || nttp::powmod(r, N, q) != q - 1) {
+      if (r == 0 || r >= q || nttp::powmod(r, cyclic ? N / 2 : N, q) != q - 1) {
         fail(NTT_ERR_ARG);
         return nullptr;
       }
       roots[l] = r;
     } else {
-      roots[l] = nttp::default_psi(q, N);
+      roots[l] = cyclic ? nttp::default_omega(q, N) : nttp::default_psi(q, N);
       if (!roots[l]) {
         fail(NTT_ERR_MODULUS);
         return nullptr;
@@ -155,8 +158,8 @@ ntt_plan* ntt_plan_create_ex(uint32_t N, const uint64_t* moduli, uint32_t L, uin
   const size_t mod_bytes = nttp::modinfo_bytes(word);
   std::vector<unsigned char> fwd(tw_bytes * L), inv(tw_bytes * L), mod(mod_bytes * L);
   for (uint32_t l = 0; l < L; ++l) {
-    nttp::twiddles(moduli[l], roots[l], p->logN, word, false, fwd.data() + l * tw_bytes);
-    nttp::twiddles(moduli[l], roots[l], p->logN, word, true, inv.data() + l * tw_bytes);
+    nttp::twiddles(moduli[l], roots[l], p->logN, word, false, fwd.data() + l * tw_bytes, cyclic);
+    nttp::twiddles(moduli[l], roots[l], p->logN, word, true, inv.data() + l * tw_bytes, cyclic);
     nttp::modinfo(moduli[l], word, mod.data() + l * mod_bytes);
   }
   if (hipMalloc(&p->d_tw_fwd, fwd.size()) != hipSuccess || hipMalloc(&p->d_tw_inv, inv.size()) != hipSuccess ||

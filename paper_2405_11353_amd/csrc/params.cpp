@@ -52,6 +52,12 @@ uint64_t default_psi(uint64_t q, uint32_t N) {
   return c ? powmod(c, (q - 1) / (2ull * N), q) : 0;
 }
 
+uint64_t default_omega(uint64_t q, uint32_t N) {
+  if ((q - 1) % N) return 0;
+  const uint64_t c = smallest_qnr(q);
+  return c ? powmod(c, (q - 1) / N, q) : 0;
+}
+
 static uint32_t bitrev(uint32_t x, uint32_t bits) {
   uint32_t r = 0;
   for (uint32_t b = 0; b < bits; ++b) r |= ((x >> b) & 1u) << (bits - 1 - b);
@@ -61,16 +67,25 @@ static uint32_t bitrev(uint32_t x, uint32_t bits) {
 size_t tw_entry_bytes(int word) { return word == 32 ? 8 : 16; }
 size_t modinfo_bytes(int word) { return word == 32 ? 32 : 64; }
 
-void twiddles(uint64_t q, uint64_t psi, uint32_t logN, int word, bool inverse, void* out) {
+void twiddles(uint64_t q, uint64_t root, uint32_t logN, int word, bool inverse, void* out, bool cyclic) {
   const uint32_t N = 1u << logN;
-  std::vector<uint64_t> pw(2 * (size_t)N);  // psi^e, e < 2N (psi has order 2N)
+  // powers of the root; the root has order 2N (negacyclic) or N (cyclic)
+  const size_t order = cyclic ? (size_t)N : 2 * (size_t)N;
+  std::vector<uint64_t> pw(order);
   pw[0] = 1;
-  for (size_t e = 1; e < pw.size(); ++e) pw[e] = mulmod(pw[e - 1], psi, q);
+  for (size_t e = 1; e < order; ++e) pw[e] = mulmod(pw[e - 1], root, q);
   const uint64_t n_inv = powmod(N % q, q - 2, q);
+  auto exponent = [&](uint32_t k) -> size_t {  // k >= 1
+    if (!cyclic) return bitrev(k, logN);
+    uint32_t s = 0;
+    while ((2u << s) <= k) ++s;
+    const uint32_t i = k - (1u << s);
+    return (size_t)(N >> (s + 1)) * bitrev(i, s);
+  };
   auto value = [&](uint32_t k) -> uint64_t {
-    if (!inverse) return k == 0 ? 1 : pw[bitrev(k, logN)];
+    if (!inverse) return k == 0 ? 1 : pw[exponent(k)];
     if (k == 0) return n_inv;
-    const uint64_t w = pw[(2 * (size_t)N - bitrev(k, logN)) % (2 * (size_t)N)];
+    const uint64_t w = pw[(order - exponent(k)) % order];
     return k == 1 ? mulmod(w, n_inv, q) : w;
   };
   for (uint32_t k = 0; k < N; ++k) {

@@ -16,12 +16,20 @@ uint64_t smallest_qnr(uint64_t q);
 // psi = c^((q-1)/2N); 0 if 2N does not divide q-1
 uint64_t default_psi(uint64_t q, uint32_t N);
 
-// Twiddle tables, N entries of (w, floor(w * 2^word / q)), word = 64 or 32:
+// omega = c^((q-1)/N) for the cyclic transform; 0 if N does not divide q-1
+uint64_t default_omega(uint64_t q, uint32_t N);
+
+// Twiddle tables, N entries of (w, floor(w * 2^word / q)), word = 64 or 32.
+// Negacyclic (root = psi, a primitive 2N-th root of unity):
 //  forward: slot k >= 1 holds psi^brv(k), the factor of butterfly group k
 //           (stage floor(log2 k)); slot 0 holds 1 (unused)
 //  inverse: slot k >= 2 holds psi^-brv(k); slot 1 holds psi^(-N/2) * N^-1 and
 //           slot 0 holds N^-1 (the last inverse stage scales both outputs)
-void twiddles(uint64_t q, uint64_t psi, uint32_t logN, int word, bool inverse, void* out);
+// Cyclic (root = omega, a primitive N-th root): slot 2^s + i holds
+//  omega^((N >> (s+1)) * brv_s(i)), the root splitting x^(2m) - z into
+//  x^m -+ sqrt(z) for the group's z; the inverse holds the inverses with the
+//  same N^-1 fold in slots 0 and 1.
+void twiddles(uint64_t q, uint64_t root, uint32_t logN, int word, bool inverse, void* out, bool cyclic = false);
 // per-limb constants in the layout of nttk::ModInfo64 / ModInfo32
 void modinfo(uint64_t q, int word, void* out);
 size_t tw_entry_bytes(int word);

@@ -16,6 +16,7 @@ _LIB_PATH = os.path.join(PKG, "libntt.so")
 NTT_OK = 0
 NTT_WORD32 = 0x1
 NTT_ORDER_BITREV = 0x2
+NTT_CYCLIC = 0x4
 NTT_PATH_AUTO, NTT_PATH_TINY, NTT_PATH_LDS, NTT_PATH_FOURSTEP = 0, 1, 2, 3
 
 _lib = None

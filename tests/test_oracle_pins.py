@@ -224,3 +224,35 @@ def test_seeded_example_from_generator():
     x = si.Stream(1).uniform_mod(q, N)
     assert [int(v) for v in x[:4]] == [608340859, 800777064, 477127076, 477025590]
     np.testing.assert_array_equal(oracle.ntt_forward(x, q), oracle.ntt_direct(x, q))
+
+
+# ---------------------------------------------------------------- cyclic (Eq. 3)
+@pytest.mark.parametrize("logn", [1, 3, 6, 9])
+def test_cyclic_against_sympy_ntt(logn):
+    # library pin: sympy's ntt is the cyclic transform with omega = g^((q-1)/N),
+    # g = sympy's primitive root = 3 = the smallest non-residue for this q
+    q, N = Q32, 1 << logn
+    x = rand_vec(200 + logn, q, N)
+    expect = [int(v) for v in sympy_ntt([int(v) for v in x], q)]
+    assert [int(v) for v in oracle.cyclic_forward(x, q)] == expect
+    assert [oracle.cyclic_direct_coeff(x, q, k) for k in range(N)] == expect
+
+
+@pytest.mark.parametrize("q", [Q32, P15[0], P17[2]])
+def test_cyclic_closed_forms_and_round_trip(q):
+    N = 128
+    w = oracle.omega(q, N)
+    assert pow(w, N, q) == 1 and pow(w, N // 2, q) == q - 1
+    d1 = np.zeros(N, np.uint64); d1[1] = 1
+    assert [int(v) for v in oracle.cyclic_forward(d1, q)] == [pow(w, k, q) for k in range(N)]
+    ones = np.ones(N, np.uint64)
+    X = oracle.cyclic_forward(ones, q)
+    assert int(X[0]) == N % q and all(int(v) == 0 for v in X[1:])     # sum of all roots of unity
+    x = rand_vec(300, q, N)
+    np.testing.assert_array_equal(oracle.cyclic_inverse(oracle.cyclic_forward(x, q), q), x)
+    # cyclic convolution theorem against the sympy linear product folded by x^N = 1
+    a, b = rand_vec(301, q, N), rand_vec(302, q, N)
+    lin = list(convolution_ntt([int(v) for v in a], [int(v) for v in b], prime=q)) + [0] * (2 * N)
+    want = [(lin[k] + lin[k + N]) % q for k in range(N)]
+    got = oracle.cyclic_inverse(oracle.pointwise(oracle.cyclic_forward(a, q), oracle.cyclic_forward(b, q), q), q)
+    assert [int(v) for v in got] == want
