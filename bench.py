@@ -194,6 +194,21 @@ def bench_batched(ntt, si, torch, reps=10):
 
     us_graph = timed(fwd.run, reps)
     us_eager = timed(eager.run, reps)
+    # autotuned: every bucket size is tuned at its own item count, then the
+    # batch is rebuilt (buckets pick their variants from the tuning table)
+    ntt.ntt_tune_clear()
+    items_by_n = {}
+    for j in jobs:
+        items_by_n[j.N] = items_by_n.get(j.N, 0) + j.L
+    choices = {}
+    for N, items in sorted(items_by_n.items()):
+        c = ntt.ntt_autotune(N, items=items, reps=5)
+        choices[N] = {"items": items, "path": {2: "lds", 3: "fourstep"}.get(c["path"], c["path"]),
+                      "log_n1": c["log_n1"], "exact": c["exact"], "us": round(c["us_per_call"], 1)}
+    tuned = ntt.Batch([(j.N, primes[:j.L], ntt.NTT_JOB_FORWARD, t) for j, t in zip(jobs, tensors)])
+    us_tuned = timed(tuned.run, reps)
+    tuned.close()
+    ntt.ntt_tune_clear()
     plans = {}
     for j in jobs:
         if (j.N, j.L) not in plans:
@@ -211,11 +226,14 @@ def bench_batched(ntt, si, torch, reps=10):
         p_.close()
     res = {"workload": "batched_uneven_256polys", "polys": len(jobs), "ntts": n_ntt, "coefficients": words,
            "graph_us": round(us_graph, 1), "graph_ntt_per_s": round(n_ntt / (us_graph * 1e-6), 1),
+           "tuned_graph_us": round(us_tuned, 1), "tuned_ntt_per_s": round(n_ntt / (us_tuned * 1e-6), 1),
+           "tuned_choices": choices,
            "graph_alg_GBs": round(16 * words / (us_graph * 1e-6) / 1e9, 1),
            "eager_us": round(us_eager, 1), "per_call_us": round(us_call, 1),
            "per_call_ntt_per_s": round(n_ntt / (us_call * 1e-6), 1),
            "graph_speedup_vs_per_call": round(us_call / us_graph, 2),
            "buckets": info["buckets"], "kernels": info["kernels"], "round_trip_exact": bool(exact)}
+    log(f"batched: autotuned graph {us_tuned:.0f} us; choices {choices}")
     log(f"batched: {n_ntt} NTTs in {us_graph:.0f} us (graph), {us_eager:.0f} us (eager), "
         f"{us_call:.0f} us (per-call) -> {res['graph_ntt_per_s'] / 1e6:.2f} M NTT/s")
     return res

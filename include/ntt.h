@@ -155,8 +155,10 @@ const char* ntt_strerror(int code);
  * private stream. The fastest goes into a process-wide table that plans in
  * automatic mode (the default) and batches consult per call, keyed by
  * (word, log2 N, log2 items). The table is saved and loaded as JSON tagged
- * with the GPU architecture; a process loads the file named by the
- * NTT_TUNE_CACHE environment variable at its first plan or batch creation.
+ * with the GPU architecture. At its first plan, batch or server creation a
+ * process loads the file named by NTT_TUNE_CACHE, or, if that variable is
+ * unset, tune_<arch>.json next to libntt.so (an empty NTT_TUNE_CACHE loads
+ * nothing).
  * Synchronous; allocates items*N words of device memory while it runs. */
 typedef struct {
   int32_t path;       /* NTT_PATH_* */

@@ -1,6 +1,7 @@
 // Autotuner: times every kernel variant the library has for a (word, N,
 // batch size) on the current GPU and keeps the fastest in a table that plans
 // and batches consult; the table persists as JSON keyed by the GPU's arch.
+#include <dlfcn.h>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -101,10 +102,26 @@ uint64_t tuning_prime(uint32_t N, int word) {
   return 0;
 }
 
+// directory of this shared library (for the tuning table shipped next to it)
+static std::string library_dir() {
+  Dl_info info;
+  if (dladdr((void*)&library_dir, &info) && info.dli_fname) {
+    std::string f = info.dli_fname;
+    const size_t slash = f.rfind('/');
+    if (slash != std::string::npos) return f.substr(0, slash);
+  }
+  return ".";
+}
+
 void tune_autoload() {
   std::call_once(g_autoload, [] {
     const char* p = getenv("NTT_TUNE_CACHE");
-    if (p && *p) (void)ntt_tune_load(p);
+    if (p) {
+      if (*p) (void)ntt_tune_load(p);  // an empty value disables loading
+      return;
+    }
+    const std::string f = library_dir() + "/tune_" + arch_name() + ".json";
+    (void)ntt_tune_load(f.c_str());
   });
 }
 
