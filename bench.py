@@ -247,36 +247,46 @@ PAPER_TABLE1_BEST_FPGA_US = {1024: 2.27, 4096: 8.60, 16384: 37.50, 65536: 669.30
 def bench_paper_sizes(ntt, si, torch, reps=100, batch=1024):
     """The paper's own setting: one cyclic transform with a 32-bit prime at
     1K/4K/16K/64K, timed as the mean of 100 runs between device-resident
-    input and output (the paper's GPU methodology), plus batched throughput."""
+    input and output (the paper's GPU methodology), plus batched throughput,
+    for the library's kernels and for the paper's algorithm variants run as
+    one kernel per stage (DIT, DIF, Pease, Pease_nc, Stockham)."""
     q = si.Q_SMALL
     stream = torch.cuda.current_stream()
+    variants = [("fused", None), ("dit", ntt.NTT_PATH_PAPER_DIT), ("dif", ntt.NTT_PATH_PAPER_DIF),
+                ("pease", ntt.NTT_PATH_PAPER_PEASE), ("pease_nc", ntt.NTT_PATH_PAPER_PEASE_NC),
+                ("stockham", ntt.NTT_PATH_PAPER_STOCKHAM)]
     out = []
     for N in (1024, 4096, 16384, 65536):
-        plan = ntt.Plan(N, [q], flags=ntt.NTT_CYCLIC | ntt.NTT_WORD32)
         x = si.Stream(si.BASE_SEED + 50).uniform_mod(q, N).astype(np.uint32)
         one = torch.from_numpy(x.view(np.int32)).cuda()
         many = one.repeat(batch)
-        row = {"N": N}
-        for name, buf, b in (("single", one, 1), ("batched", many, batch)):
-            plan.forward(buf, batch=b)
-            plan.inverse(buf, batch=b)
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            for _ in range(reps):
+        row = {"N": N, "paper_table1_best_fpga_us": PAPER_TABLE1_BEST_FPGA_US[N]}
+        for vname, path in variants:
+            plan = ntt.Plan(N, [q], flags=ntt.NTT_CYCLIC | ntt.NTT_WORD32)
+            if path is not None:
+                plan.set_variant(path)
+            res = {}
+            for name, buf, b in (("single_us", one, 1), ("batched", many, batch)):
                 plan.forward(buf, batch=b)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            us = e0.elapsed_time(e1) / reps * 1e3
-            if name == "single":
-                row["single_us"] = round(us, 3)
-            else:
-                row["batched_ntt_per_s"] = round(b / (us * 1e-6), 1)
-                row["batched_alg_GBs"] = round(8 * N * b / (us * 1e-6) / 1e9, 1)
-        row["paper_table1_best_fpga_us"] = PAPER_TABLE1_BEST_FPGA_US[N]
+                plan.inverse(buf, batch=b)
+                torch.cuda.synchronize()
+                n = reps if b == 1 else max(5, reps // 10)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for _ in range(n):
+                    plan.forward(buf, batch=b)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                us = e0.elapsed_time(e1) / n * 1e3
+                if b == 1:
+                    res["single_us"] = round(us, 3)
+                else:
+                    res["batched_ntt_per_s"] = round(b / (us * 1e-6), 1)
+            row[vname] = res
+            plan.close()
         out.append(row)
-        log(f"paper size N={N}: single {row['single_us']} us, batched {row['batched_ntt_per_s'] / 1e6:.1f} M NTT/s")
-        plan.close()
+        log(f"paper size N={N}: " + ", ".join(f"{v}: {row[v]['single_us']} us / {row[v]['batched_ntt_per_s'] / 1e6:.1f} M/s"
+                                             for v, _ in variants))
     return {"workload": "cyclic_u32_q998244353_single_and_batched", "reps": reps, "batch": batch, "sizes": out}
 
 

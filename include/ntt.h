@@ -67,6 +67,14 @@ extern "C" {
 #define NTT_PATH_TINY 1          /* N < 16: one thread per transform            */
 #define NTT_PATH_LDS 2           /* whole transform in one workgroup's LDS      */
 #define NTT_PATH_FOURSTEP 3      /* column pass + row pass (N = N1 x N2)        */
+/* The paper's algorithm variants (cyclic plans, natural order only): one
+ * kernel launch per stage over global memory, canonical arithmetic (Alg. 4-5),
+ * for comparison with the fused paths. */
+#define NTT_PATH_PAPER_DIT 4      /* Alg. 1: bit_reverse, stages 1..L in place   */
+#define NTT_PATH_PAPER_DIF 5      /* Alg. 2: stages L..1 in place, bit_reverse   */
+#define NTT_PATH_PAPER_PEASE 6    /* Alg. 3: constant geometry, copy per stage   */
+#define NTT_PATH_PAPER_PEASE_NC 7 /* Pease_nc: constant geometry, arrays swapped */
+#define NTT_PATH_PAPER_STOCKHAM 8 /* Stockham autosort: two arrays, no bit_reverse */
 
 typedef struct ntt_plan ntt_plan;
 
@@ -125,7 +133,9 @@ int ntt_plan_get_variant(const ntt_plan* plan, int* path, int* log_n1);
 
 /* Select the kernel variant of a plan: path NTT_PATH_*, and for
  * NTT_PATH_FOURSTEP the column length 2^log_n1 (6 <= log_n1, log2(N)-log_n1
- * <= 9). Not safe while other threads use the plan. */
+ * <= 9). The NTT_PATH_PAPER_* variants need an NTT_CYCLIC plan in natural
+ * order; Pease and Stockham use scratch like the four-step path. Not safe
+ * while other threads use the plan. */
 int ntt_plan_set_variant(ntt_plan* plan, int path, int log_n1);
 
 /* Quotient flavour of the 64-bit Shoup product: 0 (default) estimates

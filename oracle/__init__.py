@@ -59,6 +59,8 @@ def lib():
             "orc_ntt_cyclic_forward": (None, [p64, u32, u64, u64]),
             "orc_ntt_cyclic_inverse": (None, [p64, u32, u64, u64]),
             "orc_ntt_cyclic_direct_coeff": (u64, [p64, u32, u64, u64, u32]),
+            "orc_pease_cyclic_forward": (None, [p64, u32, u64, u64]),
+            "orc_stockham_cyclic_forward": (None, [p64, u32, u64, u64]),
             "orc_ntt_forward_batch": (ctypes.c_int, [p64, u32, u32, u32, p64, p64, ctypes.c_int]),
             "orc_ntt_inverse_batch": (ctypes.c_int, [p64, u32, u32, u32, p64, p64, ctypes.c_int]),
             "orc_pointwise_batch": (ctypes.c_int, [p64, p64, p64, u32, u32, u32, p64, ctypes.c_int]),
@@ -170,6 +172,18 @@ def cyclic_forward(x, q, root=None):
 def cyclic_inverse(X, q, root=None):
     y = _u64(X).copy()
     lib().orc_ntt_cyclic_inverse(_p(y), y.size, q, root if root is not None else omega(q, y.size))
+    return y
+
+
+def pease_forward(x, q, root=None):
+    y = _u64(x).copy()
+    lib().orc_pease_cyclic_forward(_p(y), y.size, q, root if root is not None else omega(q, y.size))
+    return y
+
+
+def stockham_forward(x, q, root=None):
+    y = _u64(x).copy()
+    lib().orc_stockham_cyclic_forward(_p(y), y.size, q, root if root is not None else omega(q, y.size))
     return y
 
 

@@ -168,6 +168,48 @@ uint64_t orc_ntt_cyclic_direct_coeff(const uint64_t* x, uint32_t N, uint64_t q, 
   return acc;
 }
 
+void orc_pease_cyclic_forward(uint64_t* x, uint32_t N, uint64_t q, uint64_t omega) {
+  uint32_t L = 0;
+  while ((1u << L) < N) ++L;
+  uint64_t* W = orc_power_table(omega, N / 2 ? N / 2 : 1, q);
+  uint64_t* y = (uint64_t*)malloc(sizeof(uint64_t) * N);
+  orc_bit_reverse(x, N);
+  for (uint32_t s = L; s >= 1; --s) {
+    uint32_t base = (1u << (s - 1)) - 1;
+    for (uint32_t r = 0; r < N / 2; ++r) {
+      uint64_t f1 = x[2 * r];
+      uint64_t f2 = orc_mulmod(W[r & ~base], x[2 * r + 1], q);
+      y[r] = orc_addmod(f1, f2, q);
+      y[r + N / 2] = orc_submod(f1, f2, q);
+    }
+    memcpy(x, y, sizeof(uint64_t) * N);
+  }
+  free(y);
+  free(W);
+}
+
+void orc_stockham_cyclic_forward(uint64_t* x, uint32_t N, uint64_t q, uint64_t omega) {
+  uint32_t L = 0;
+  while ((1u << L) < N) ++L;
+  uint64_t* W = orc_power_table(omega, N, q);
+  uint64_t* y = (uint64_t*)malloc(sizeof(uint64_t) * N);
+  for (uint32_t t = 1; t <= L; ++t) {
+    uint32_t Lt = 1u << t, h = Lt / 2, r = N / Lt;
+    for (uint32_t j = 0; j < h; ++j) {
+      uint64_t om = W[(size_t)(N / Lt) * j];
+      for (uint32_t k = 0; k < r; ++k) {
+        uint64_t u = x[j + h * k];
+        uint64_t v = orc_mulmod(om, x[j + h * (k + r)], q);
+        y[j + Lt * k] = orc_addmod(u, v, q);
+        y[j + h + Lt * k] = orc_submod(u, v, q);
+      }
+    }
+    memcpy(x, y, sizeof(uint64_t) * N);
+  }
+  free(y);
+  free(W);
+}
+
 /* Direct evaluation of the definition, X_k = sum_j x_j psi^((2k+1) j), with
  * the exponent reduced mod 2N (psi has order 2N).                          */
 uint64_t orc_ntt_direct_coeff(const uint64_t* x, uint32_t N, uint64_t q, uint64_t psi, uint32_t k) {

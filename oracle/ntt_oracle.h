@@ -69,6 +69,14 @@ void orc_ntt_cyclic_forward(uint64_t* x, uint32_t N, uint64_t q, uint64_t omega)
 /* DIF (Alg. 2) with omega^-1, bit_reverse, scale by N^-1                     */
 void orc_ntt_cyclic_inverse(uint64_t* x, uint32_t N, uint64_t q, uint64_t omega);
 uint64_t orc_ntt_cyclic_direct_coeff(const uint64_t* x, uint32_t N, uint64_t q, uint64_t omega, uint32_t k);
+/* Pease constant geometry (Alg. 3): bit_reverse, then for s = L..1 every
+ * stage reads the adjacent pair (x[2r], x[2r+1]) and writes y[r], y[r+N/2];
+ * the twiddle the listing omits is W[r & ~(2^(s-1) - 1)] (reading of Alg. 3) */
+void orc_pease_cyclic_forward(uint64_t* x, uint32_t N, uint64_t q, uint64_t omega);
+/* Stockham autosort (§2 "Stockham"): two arrays and no bit reversal; stage
+ * t (1..L) with Lt = 2^t, half h = Lt/2, r = N/Lt maps x(j + h k) and
+ * x(j + h (k + r)) to y(j + Lt k) and y(j + h + Lt k), twiddle W^((N/Lt) j) */
+void orc_stockham_cyclic_forward(uint64_t* x, uint32_t N, uint64_t q, uint64_t omega);
 
 /* --- batched drivers over a row-major [B][L][N] array (limb l uses q[l]) ---
  * nthreads <= 0 means all OpenMP threads; returns the thread count used.    */

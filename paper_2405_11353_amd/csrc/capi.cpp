@@ -23,9 +23,12 @@ int fail(int code) {
 
 using ntti::ilog2;
 
+static bool is_paper_path(int path) { return path >= NTT_PATH_PAPER_DIT && path <= NTT_PATH_PAPER_STOCKHAM; }
+
 static bool variant_ok(const ntt_plan* p, int path, int logN1, int exact) {
   using namespace nttk;
   const int lg = (int)p->logN;
+  if (is_paper_path(path)) return !exact && (p->flags & NTT_CYCLIC) && !(p->flags & NTT_ORDER_BITREV);
   switch (path) {
     case NTT_PATH_TINY: return shape_supported(p->word, exact, PATH_TINY, lg, 0);
     case NTT_PATH_LDS: return shape_supported(p->word, exact, PATH_LDS, lg, 0);
@@ -72,6 +75,7 @@ static void release(ntt_plan* p) {
   if (p->d_tw_fwd) (void)hipFree(p->d_tw_fwd);
   if (p->d_tw_inv) (void)hipFree(p->d_tw_inv);
   if (p->d_mod) (void)hipFree(p->d_mod);
+  if (p->d_paper) (void)hipFree(p->d_paper);
   (void)hipSetDevice(cur);
   delete p;
 }
@@ -214,6 +218,7 @@ int ntt_plan_set_variant(ntt_plan* p, int path, int log_n1) {
     return NTT_OK;
   }
   if (!variant_ok(p, path, log_n1, 0)) return NTT_ERR_UNSUPPORTED;
+  if (is_paper_path(path) && !(p->N >= 2)) return NTT_ERR_UNSUPPORTED;
   p->path = path;
   p->logN1 = path == NTT_PATH_FOURSTEP ? log_n1 : 0;
   p->exact = 0;
@@ -233,7 +238,9 @@ size_t ntt_workspace_bytes(const ntt_plan* p, uint32_t batch) {
   if (!p || batch == 0 || (p->flags & NTT_ORDER_BITREV)) return 0;
   int path, n1, ex;
   select_variant(p, batch * p->L, &path, &n1, &ex);
-  if (path != NTT_PATH_FOURSTEP) return 0;
+  const bool needs = path == NTT_PATH_FOURSTEP || path == NTT_PATH_PAPER_PEASE || path == NTT_PATH_PAPER_PEASE_NC ||
+                     path == NTT_PATH_PAPER_STOCKHAM;
+  if (!needs) return 0;
   return ((size_t)batch * p->L << p->logN) * (p->word / 8);
 }
 
@@ -268,6 +275,67 @@ static int get_scratch(ntt_plan* p, void* stream, size_t bytes, void** out) {
 extern "C" int ntt_pointwise_mul(const ntt_plan* p, const void* a, const void* b, void* c, uint32_t batch,
                                  void* stream);
 
+// tables for the paper's variants: omega^i and omega^-i for i < N/2 (with
+// Shoup companions) and N^-1 per limb, built and uploaded on first use
+static int paper_tables(ntt_plan* p) {
+  std::lock_guard<std::mutex> g(p->mu);
+  if (p->d_paper) return NTT_OK;
+  const uint32_t half = p->N / 2;
+  const size_t eb = nttp::tw_entry_bytes(p->word);
+  std::vector<unsigned char> host((2 * (size_t)half + 1) * p->L * eb);
+  auto put = [&](size_t slot, uint64_t w, uint64_t q) {
+    if (p->word == 32) {
+      uint32_t* o = (uint32_t*)(host.data() + slot * eb);
+      o[0] = (uint32_t)w;
+      o[1] = (uint32_t)(((uint64_t)w << 32) / q);
+    } else {
+      uint64_t* o = (uint64_t*)(host.data() + slot * eb);
+      o[0] = w;
+      o[1] = (uint64_t)(((unsigned __int128)w << 64) / q);
+    }
+  };
+  for (uint32_t l = 0; l < p->L; ++l) {
+    const uint64_t q = p->moduli[l], w = p->psi[l], wi = nttp::powmod(w, q - 2, q);
+    uint64_t a = 1, b = 1;
+    for (uint32_t i = 0; i < half; ++i) {
+      put((size_t)l * half + i, a, q);
+      put((size_t)(p->L + l) * half + i, b, q);
+      a = nttp::mulmod(a, w, q);
+      b = nttp::mulmod(b, wi, q);
+    }
+    put(2 * (size_t)p->L * half + l, nttp::powmod(p->N % q, q - 2, q), q);
+  }
+  if (hipMalloc(&p->d_paper, host.size()) != hipSuccess) return NTT_ERR_NOMEM;
+  if (hipMemcpy(p->d_paper, host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess) return NTT_ERR_HIP;
+  return NTT_OK;
+}
+
+static int get_scratch(ntt_plan* p, void* stream, size_t bytes, void** out);
+
+static int run_paper(ntt_plan* p, void* data, uint32_t batch, void* stream, bool fwd, int path) {
+  int rc = paper_tables(p);
+  if (rc != NTT_OK) return rc;
+  nttk::PaperLaunch c;
+  c.word = p->word;
+  c.path = path - NTT_PATH_PAPER_DIT;
+  c.logN = (int)p->logN;
+  c.data = data;
+  const size_t eb = nttp::tw_entry_bytes(p->word), half = p->N / 2;
+  c.tw_fwd = p->d_paper;
+  c.tw_inv = (const unsigned char*)p->d_paper + (size_t)p->L * half * eb;
+  c.ninv = (const unsigned char*)p->d_paper + 2 * (size_t)p->L * half * eb;
+  c.mods = p->d_mod;
+  c.L = p->L;
+  c.items = batch * p->L;
+  c.stream = (hipStream_t)stream;
+  if (path != NTT_PATH_PAPER_DIT && path != NTT_PATH_PAPER_DIF) {
+    rc = get_scratch(p, stream, ((size_t)c.items << p->logN) * (p->word / 8), &c.scratch);
+    if (rc != NTT_OK) return rc;
+  }
+  const hipError_t e = nttk::launch_paper(c, fwd);
+  return e == hipSuccess ? NTT_OK : NTT_ERR_HIP;
+}
+
 static int check_common(const ntt_plan* p, uint32_t batch) {
   if (!p || batch == 0) return NTT_ERR_ARG;
   if ((uint64_t)batch * p->L > 0xFFFFFFFFull / 64) return NTT_ERR_ARG;
@@ -284,6 +352,10 @@ static int run_ntt(const ntt_plan* pc, void* data, uint32_t batch, void* stream,
   ntt_plan* p = const_cast<ntt_plan*>(pc);
   int path, logN1, exact;
   select_variant(p, batch * p->L, &path, &logN1, &exact);
+  if (is_paper_path(path)) {
+    if (stage_mask != 3) return NTT_ERR_UNSUPPORTED;
+    return run_paper(p, data, batch, stream, fwd, path);
+  }
   nttk::Launch c;
   c.word = p->word;
   c.exact = exact;

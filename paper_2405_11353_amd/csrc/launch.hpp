@@ -57,6 +57,24 @@ hipError_t launch_batch_u64(const BatchLaunch& c, bool forward);
 hipError_t launch_ind_copy(const ItemDesc* desc, uint32_t items, uint32_t max_logn, hipStream_t s);
 hipError_t launch_ind_pointwise(const ItemDesc* desc, uint32_t items, uint32_t max_logn, hipStream_t s);
 
+// The paper's algorithm variants (cyclic transform, natural order): one
+// launch per stage; tables W[l][N/2] of omega^(+-i) and N^-1 per limb.
+enum PaperPath { PAPER_DIT = 0, PAPER_DIF = 1, PAPER_PEASE = 2, PAPER_PEASE_NC = 3, PAPER_STOCKHAM = 4 };
+struct PaperLaunch {
+  int word = 64;
+  int path = PAPER_DIT;
+  int logN = 0;
+  void* data = nullptr;
+  void* scratch = nullptr;  // PEASE, PEASE_NC, STOCKHAM: items << logN words
+  const void* tw_fwd = nullptr;
+  const void* tw_inv = nullptr;
+  const void* ninv = nullptr;
+  const void* mods = nullptr;
+  uint32_t L = 0, items = 0;
+  hipStream_t stream = nullptr;
+};
+hipError_t launch_paper(const PaperLaunch& c, bool forward);
+
 // Each returns hipErrorNotSupported for a shape it has no kernel for.
 hipError_t launch_u64(const Launch& c, bool forward);
 hipError_t launch_u64x(const Launch& c, bool forward);

@@ -28,8 +28,10 @@ struct ntt_plan {
   int path = NTT_PATH_LDS;
   int logN1 = 0;
   int exact = 0;
-  std::mutex mu;  // guards scratch
+  std::mutex mu;  // guards scratch and the paper-variant tables
   std::vector<ScratchSlot> scratch;
+  // tables of the paper's algorithm variants (cyclic plans), built on first use
+  void* d_paper = nullptr;  // [L][N/2] forward, [L][N/2] inverse, [L] N^-1
 };
 
 namespace ntti {

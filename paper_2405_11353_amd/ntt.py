@@ -18,6 +18,8 @@ NTT_WORD32 = 0x1
 NTT_ORDER_BITREV = 0x2
 NTT_CYCLIC = 0x4
 NTT_PATH_AUTO, NTT_PATH_TINY, NTT_PATH_LDS, NTT_PATH_FOURSTEP = 0, 1, 2, 3
+NTT_PATH_PAPER_DIT, NTT_PATH_PAPER_DIF, NTT_PATH_PAPER_PEASE, NTT_PATH_PAPER_PEASE_NC, NTT_PATH_PAPER_STOCKHAM = \
+    4, 5, 6, 7, 8
 
 _lib = None
 

@@ -77,3 +77,36 @@ def test_cyclic_product_is_cyclic_convolution(ntt):
     got = from_dev(da, 32)
     want = oracle.cyclic_inverse(oracle.pointwise(oracle.cyclic_forward(a, q), oracle.cyclic_forward(b, q), q), q)
     np.testing.assert_array_equal(got, want)
+
+
+PAPER_PATHS = ["PAPER_DIT", "PAPER_DIF", "PAPER_PEASE", "PAPER_PEASE_NC", "PAPER_STOCKHAM"]
+
+
+@pytest.mark.parametrize("path", PAPER_PATHS)
+@pytest.mark.parametrize("word,logn", [(32, 1), (32, 2), (32, 6), (32, 10), (32, 12), (32, 14), (64, 3), (64, 11)])
+def test_paper_variants_match_oracle(ntt, path, word, logn):
+    N = 1 << logn
+    moduli = Q32 if word == 32 else P18[:2]
+    log(f"case paper variant {path} word={word} N={N}")
+    plan = ntt.Plan(N, moduli, flags=ntt.NTT_CYCLIC | (ntt.NTT_WORD32 if word == 32 else 0))
+    plan.set_variant(getattr(ntt, "NTT_PATH_" + path))
+    x = si.poly_batch(logn * 3 + word, 3, moduli, N)
+    d = to_dev(x, word)
+    plan.forward(d)
+    got = from_dev(d, word).reshape(x.shape)
+    for b in range(3):
+        for l, q in enumerate(moduli):
+            ref = {"PAPER_PEASE": oracle.pease_forward, "PAPER_PEASE_NC": oracle.pease_forward,
+                   "PAPER_STOCKHAM": oracle.stockham_forward}.get(path, oracle.cyclic_forward)(x[b, l], q)
+            np.testing.assert_array_equal(got[b, l], ref)
+    plan.inverse(d)
+    np.testing.assert_array_equal(from_dev(d, word).reshape(x.shape), x)
+
+
+def test_paper_variants_need_cyclic_natural_plans(ntt):
+    plan = ntt.Plan(1024, Q32[:1], flags=ntt.NTT_WORD32)          # negacyclic
+    with pytest.raises(ntt.NttError):
+        plan.set_variant(ntt.NTT_PATH_PAPER_DIT)
+    plan = ntt.Plan(1024, Q32[:1], flags=ntt.NTT_WORD32 | ntt.NTT_CYCLIC | ntt.NTT_ORDER_BITREV)
+    with pytest.raises(ntt.NttError):
+        plan.set_variant(ntt.NTT_PATH_PAPER_STOCKHAM)

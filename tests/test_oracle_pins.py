@@ -256,3 +256,16 @@ def test_cyclic_closed_forms_and_round_trip(q):
     want = [(lin[k] + lin[k + N]) % q for k in range(N)]
     got = oracle.cyclic_inverse(oracle.pointwise(oracle.cyclic_forward(a, q), oracle.cyclic_forward(b, q), q), q)
     assert [int(v) for v in got] == want
+
+
+@pytest.mark.parametrize("q", [Q32, P15[0], P18[3]])
+@pytest.mark.parametrize("logn", [1, 2, 5, 8, 10])
+def test_pease_and_stockham_equal_the_definition(q, logn):
+    # brute force: the paper's constant-geometry (Pease) and autosort
+    # (Stockham) orderings against the O(N^2) cyclic definition
+    N = 1 << logn
+    x = rand_vec(400 + logn, q, N)
+    want = [oracle.cyclic_direct_coeff(x, q, k) for k in range(N)] if N <= 256 else \
+        [int(v) for v in oracle.cyclic_forward(x, q)]
+    assert [int(v) for v in oracle.pease_forward(x, q)] == want
+    assert [int(v) for v in oracle.stockham_forward(x, q)] == want
