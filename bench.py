@@ -482,22 +482,25 @@ def main():
     kernels = {}
     if path == ntt.NTT_PATH_FOURSTEP:
         logn2 = int(math.log2(N)) - logn1
+        # twiddle tables read once per limb per launch: the column pass uses the
+        # first N1 entries of each limb's table, the row pass all N (16 B each)
+        tw_col, tw_row = L * 16 * (1 << logn1), L * 16 * N
         kernels["fwd_col_pass"] = dict(fn=lambda b: plan.forward_stage(b, 0, batch=4), items=polys * L,
-                                       stages=logn1, extra_muls=0, words_in=1, words_out=1)
+                                       stages=logn1, extra_muls=0, words_in=1, words_out=1, tw_bytes=tw_col)
         kernels["fwd_row_pass"] = dict(fn=lambda b: plan.forward_stage(b, 1, batch=4), items=polys * L,
-                                       stages=logn2, extra_muls=0, words_in=1, words_out=1)
+                                       stages=logn2, extra_muls=0, words_in=1, words_out=1, tw_bytes=tw_row)
         kernels["inv_row_pass_mul"] = dict(fn=lambda b: plan.pointwise_inverse_stage(b[:2], b[2:], b[:2], 0, batch=2),
                                            items=2 * L, stages=logn2, extra_muls=0, words_in=2, words_out=1,
-                                           general_muls=N)
+                                           general_muls=N, tw_bytes=tw_row)
         kernels["inv_col_pass"] = dict(fn=lambda b: plan.inverse_stage(b[:2], 1, batch=2), items=2 * L,
-                                       stages=logn1, extra_muls=N // 2, words_in=1, words_out=1)
+                                       stages=logn1, extra_muls=N // 2, words_in=1, words_out=1, tw_bytes=tw_col)
     else:
         kernels["pointwise"] = dict(fn=lambda b: plan.pointwise(b[:2], b[2:], b[:2], batch=2), items=2 * L,
                                     stages=0, extra_muls=0, words_in=2, words_out=1)
     per_kernel = {}
     for name, k in kernels.items():
         us = time_kernel(k["fn"], args.kernel_reps)
-        bytes_alg = k["items"] * N * 8 * (k["words_in"] + k["words_out"])
+        bytes_alg = k["items"] * N * 8 * (k["words_in"] + k["words_out"]) + k.get("tw_bytes", 0)
         muls = k["items"] * (((N // 2) * k["stages"] + k["extra_muls"]) * MULS_PER_SHOUP
                              + k.get("general_muls", 0) * MULS_PER_GENERAL)
         gbs = bytes_alg / (us * 1e-6) / 1e9
