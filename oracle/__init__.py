@@ -29,14 +29,29 @@ def build(force: bool = False) -> str:
 
 
 _lib = None
+_lib_path = None  # None: the default build
+
+
+def use_library(path=None):
+    """Load another build of the oracle (the mutation test's planted
+    mistakes); None returns to the default build."""
+    global _lib, _lib_path
+    _lib, _lib_path = None, path
+
+
+def build_variant(out_path: str, defines=()) -> str:
+    """Compile ntt_oracle.c with extra -D definitions into out_path."""
+    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", out_path, _SRC] +
+                          [f"-D{d}" for d in defines])
+    return out_path
 
 
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_SO):
+        if _lib_path is None and not os.path.exists(_SO):
             build()
-        L = ctypes.CDLL(_SO)
+        L = ctypes.CDLL(_lib_path or _SO)
         u64, u32, p64 = ctypes.c_uint64, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint64)
         sig = {
             "orc_addmod": (u64, [u64, u64, u64]),

@@ -16,6 +16,13 @@
 
 typedef unsigned __int128 u128;
 
+/* Planted mistakes for the mutation test of the pins (tests/ builds the
+ * oracle with -DORC_MUTANT=k and checks that the pins reject it); the
+ * default build has ORC_MUTANT = 0 and compiles none of them. */
+#ifndef ORC_MUTANT
+#define ORC_MUTANT 0
+#endif
+
 /* modulo_add (Alg. 4): inputs in [0,q), the sum lies in [0,2q) and needs at
  * most one subtraction of q; the difference lies in (-q,q) and needs at most
  * one addition of q. Written with '%' here, which gives the same value.   */
@@ -75,16 +82,18 @@ void orc_bit_reverse(uint64_t* x, uint32_t N) {
 static void orc_dit_cyclic(uint64_t* x, uint32_t N, uint64_t q, const uint64_t* W) {
   uint32_t L = 0;
   while ((1u << L) < N) ++L;
+#if ORC_MUTANT != 8
   orc_bit_reverse(x, N);
-  for (uint32_t s = 1; s <= L; ++s) {
+#endif
+  for (uint32_t s = 1; s <= L - (ORC_MUTANT == 4 ? 1 : 0); ++s) {
     uint32_t m = 1u << s, h = m >> 1;
     for (uint32_t k = 0; k < h; ++k) {
-      uint64_t tw = W[(size_t)(N / m) * k];
+      uint64_t tw = W[((size_t)(N / m) * k + (ORC_MUTANT == 3 ? 1 : 0)) % N];
       for (uint32_t j = 0; j < N; j += m) {
         uint64_t f1 = x[j + k];
         uint64_t f2 = orc_mulmod(tw, x[j + k + h], q);
-        x[j + k] = orc_addmod(f1, f2, q);
-        x[j + k + h] = orc_submod(f1, f2, q);
+        x[j + k] = ORC_MUTANT == 7 ? orc_submod(f1, f2, q) : orc_addmod(f1, f2, q);
+        x[j + k + h] = ORC_MUTANT == 7 ? orc_addmod(f1, f2, q) : orc_submod(f1, f2, q);
       }
     }
   }
@@ -123,7 +132,9 @@ static uint64_t* orc_power_table(uint64_t base, uint32_t count, uint64_t q) {
 void orc_ntt_forward(uint64_t* x, uint32_t N, uint64_t q, uint64_t psi) {
   uint64_t* P = orc_power_table(psi, N, q);                      /* psi^j   */
   uint64_t* W = orc_power_table(orc_mulmod(psi, psi, q), N, q);  /* omega^i */
-  for (uint32_t j = 0; j < N; ++j) x[j] = orc_mulmod(x[j], P[j], q);
+#if ORC_MUTANT != 1
+  for (uint32_t j = 0; j < N; ++j) x[j] = orc_mulmod(x[j], P[ORC_MUTANT == 2 ? (N - j) % N : j], q);
+#endif
   orc_dit_cyclic(x, N, q, W);
   free(P); free(W);
 }
@@ -136,6 +147,7 @@ void orc_ntt_inverse(uint64_t* x, uint32_t N, uint64_t q, uint64_t psi) {
   uint64_t* P = orc_power_table(psi_inv, N, q);                          /* psi^-j   */
   uint64_t* W = orc_power_table(orc_mulmod(psi_inv, psi_inv, q), N, q);  /* omega^-i */
   orc_dif_cyclic(x, N, q, W);
+  if (ORC_MUTANT == 5) n_inv = 1;
   for (uint32_t j = 0; j < N; ++j) x[j] = orc_mulmod(orc_mulmod(x[j], P[j], q), n_inv, q);
   free(P); free(W);
 }
@@ -226,7 +238,7 @@ void orc_ntt_direct(const uint64_t* x, uint64_t* X, uint32_t N, uint64_t q, uint
   for (uint32_t k = 0; k < N; ++k) {
     uint64_t acc = 0;
     for (uint32_t j = 0; j < N; ++j) {
-      uint64_t e = ((2ull * k + 1) * j) % (2ull * N);
+      uint64_t e = ((2ull * k + (ORC_MUTANT == 6 ? 2 * N - 1 : 1)) * j) % (2ull * N);
       acc = orc_addmod(acc, orc_mulmod(x[j], P[e], q), q);
     }
     X[k] = acc;
@@ -247,7 +259,7 @@ uint64_t orc_intt_direct_coeff(const uint64_t* X, uint32_t N, uint64_t q, uint64
 }
 
 void orc_pointwise(const uint64_t* a, const uint64_t* b, uint64_t* c, uint32_t N, uint64_t q) {
-  for (uint32_t k = 0; k < N; ++k) c[k] = orc_mulmod(a[k], b[k], q);
+  for (uint32_t k = 0; k < N; ++k) c[k] = orc_mulmod(a[k], ORC_MUTANT == 10 ? a[k] : b[k], q);
 }
 
 /* (a*b)_k = sum_{i<=k} a_i b_{k-i} - sum_{i>k} a_i b_{N+k-i}   (x^N = -1) */
@@ -255,7 +267,7 @@ uint64_t orc_negacyclic_coeff(const uint64_t* a, const uint64_t* b, uint32_t N, 
   uint64_t pos = 0, neg = 0;
   for (uint32_t i = 0; i <= k; ++i) pos = orc_addmod(pos, orc_mulmod(a[i], b[k - i], q), q);
   for (uint32_t i = k + 1; i < N; ++i) neg = orc_addmod(neg, orc_mulmod(a[i], b[N + k - i], q), q);
-  return orc_submod(pos, neg, q);
+  return ORC_MUTANT == 9 ? orc_addmod(pos, neg, q) : orc_submod(pos, neg, q);
 }
 void orc_negacyclic_mul(const uint64_t* a, const uint64_t* b, uint64_t* c, uint32_t N, uint64_t q) {
   for (uint32_t k = 0; k < N; ++k) c[k] = orc_negacyclic_coeff(a, b, N, q, k);
