@@ -79,6 +79,9 @@ def lib():
             "orc_ntt_forward_batch": (ctypes.c_int, [p64, u32, u32, u32, p64, p64, ctypes.c_int]),
             "orc_ntt_inverse_batch": (ctypes.c_int, [p64, u32, u32, u32, p64, p64, ctypes.c_int]),
             "orc_pointwise_batch": (ctypes.c_int, [p64, p64, p64, u32, u32, u32, p64, ctypes.c_int]),
+            "orc_tensor_batch": (ctypes.c_int, [p64, p64, p64, u32, u32, u32, p64, ctypes.c_int]),
+            "orc_base_conv_batch": (ctypes.c_int, [p64, p64, u32, u32, p64, u32, p64, u32, ctypes.c_int]),
+            "orc_mod_down_batch": (ctypes.c_int, [p64, p64, p64, u32, u32, p64, u32, p64, u32, ctypes.c_int]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -237,3 +240,34 @@ def pointwise_batch(a, b, moduli, nthreads=0):
     q = _u64(moduli)
     used = lib().orc_pointwise_batch(_p(a), _p(b), _p(c), B, L, N, _p(q), nthreads)
     return c, used
+
+
+# ---- HE steps (definitions in ntt_oracle.h) -----------------------------------------
+def tensor_product(a, b, moduli, nthreads=0):
+    """a, b: [B][2][L][N] ciphertexts in the evaluation domain -> d [B][3][L][N]."""
+    a, b = _u64(a), _u64(b)
+    B, two, L, N = a.shape
+    assert two == 2 and b.shape == a.shape and len(moduli) == L
+    d = np.empty((B, 3, L, N), np.uint64)
+    lib().orc_tensor_batch(_p(a), _p(b), _p(d), B, L, N, _p(_u64(moduli)), nthreads)
+    return d
+
+
+def base_conv(x, src, dst, nthreads=0):
+    """x: [B][L][N] residues over src (L primes) -> [B][K][N] over dst (K primes)."""
+    x = _u64(x)
+    B, L, N = x.shape
+    assert len(src) == L
+    out = np.empty((B, len(dst), N), np.uint64)
+    lib().orc_base_conv_batch(_p(x), _p(out), B, N, _p(_u64(src)), L, _p(_u64(dst)), len(dst), nthreads)
+    return out
+
+
+def mod_down(x, y, src, dst, nthreads=0):
+    """x: [B][L][N] over src, y: [B][K][N] over dst -> (y - conv(x)) * S^-1 over dst."""
+    x, y = _u64(x), _u64(y)
+    B, L, N = x.shape
+    assert len(src) == L and y.shape == (B, len(dst), N)
+    out = np.empty_like(y)
+    lib().orc_mod_down_batch(_p(x), _p(y), _p(out), B, N, _p(_u64(src)), L, _p(_u64(dst)), len(dst), nthreads)
+    return out

@@ -317,3 +317,85 @@ int orc_pointwise_batch(const uint64_t* a, const uint64_t* b, uint64_t* c, uint3
   }
   return nt;
 }
+
+/* ---- HE steps (definitions in ntt_oracle.h) ----------------------------- */
+void orc_tensor_product(const uint64_t* a0, const uint64_t* a1, const uint64_t* b0, const uint64_t* b1,
+                        uint64_t* d0, uint64_t* d1, uint64_t* d2, uint32_t N, uint64_t q) {
+  for (uint32_t k = 0; k < N; ++k) {
+    d0[k] = orc_mulmod(a0[k], b0[k], q);
+    d1[k] = orc_addmod(orc_mulmod(a0[k], b1[k], q), orc_mulmod(a1[k], ORC_MUTANT == 16 ? b1[k] : b0[k], q), q);
+    d2[k] = orc_mulmod(a1[k], b1[k], q);
+  }
+}
+int orc_tensor_batch(const uint64_t* a, const uint64_t* b, uint64_t* d, uint32_t B, uint32_t L, uint32_t N,
+                     const uint64_t* q, int nthreads) {
+  int nt = orc_threads(nthreads);
+  const size_t per = (size_t)L * N;
+  long total = (long)B * L;
+#pragma omp parallel for schedule(static) num_threads(nt)
+  for (long t = 0; t < total; ++t) {
+    const size_t c = (size_t)(t / L), l = (size_t)(t % L);
+    const uint64_t* ac = a + 2 * per * c + l * N;
+    const uint64_t* bc = b + 2 * per * c + l * N;
+    uint64_t* dc = d + 3 * per * c + l * N;
+    orc_tensor_product(ac, ac + per, bc, bc + per, dc, dc + per, dc + 2 * per, N, q[l]);
+  }
+  return nt;
+}
+
+/* shat_i mod m = prod_{k != i} s_k mod m */
+static uint64_t orc_shat_mod(const uint64_t* s, uint32_t L, uint32_t i, uint64_t m) {
+  uint64_t r = 1 % m;
+  for (uint32_t k = 0; k < L; ++k)
+    if (k != i || ORC_MUTANT == 13) r = orc_mulmod(r, s[k] % m, m);
+  return r;
+}
+
+void orc_base_conv(const uint64_t* x, uint64_t* out, uint32_t N, const uint64_t* s, uint32_t L,
+                   const uint64_t* t, uint32_t K) {
+  uint64_t* inv = malloc(sizeof(uint64_t) * (L ? L : 1));
+  for (uint32_t i = 0; i < L; ++i) inv[i] = orc_invmod(orc_shat_mod(s, L, i, s[i]), s[i]);
+  for (uint32_t j = 0; j < K; ++j) {
+    for (uint32_t n = 0; n < N; ++n) {
+      uint64_t acc = 0;
+      for (uint32_t i = 0; i < L - (ORC_MUTANT == 12 ? 1 : 0); ++i) {
+        uint64_t y = ORC_MUTANT == 11 ? x[(size_t)i * N + n]
+                                      : orc_mulmod(x[(size_t)i * N + n], inv[i], s[i]);
+        acc = orc_addmod(acc, orc_mulmod(y % t[j], orc_shat_mod(s, L, i, t[j]), t[j]), t[j]);
+      }
+      out[(size_t)j * N + n] = acc;
+    }
+  }
+  free(inv);
+}
+
+void orc_mod_down(const uint64_t* x, const uint64_t* y, uint64_t* out, uint32_t N, const uint64_t* s,
+                  uint32_t L, const uint64_t* t, uint32_t K) {
+  orc_base_conv(x, out, N, s, L, t, K);
+  for (uint32_t j = 0; j < K; ++j) {
+    uint64_t S_inv = orc_invmod(orc_shat_mod(s, L, L, t[j]), t[j]);  /* k != L: the full product */
+    if (ORC_MUTANT == 15) S_inv = 1;
+    for (uint32_t n = 0; n < N; ++n) {
+      const size_t e = (size_t)j * N + n;
+      uint64_t diff = ORC_MUTANT == 14 ? orc_submod(out[e], y[e], t[j]) : orc_submod(y[e], out[e], t[j]);
+      out[e] = orc_mulmod(diff, S_inv, t[j]);
+    }
+  }
+}
+
+int orc_base_conv_batch(const uint64_t* x, uint64_t* out, uint32_t B, uint32_t N, const uint64_t* s,
+                        uint32_t L, const uint64_t* t, uint32_t K, int nthreads) {
+  int nt = orc_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nt)
+  for (long b = 0; b < (long)B; ++b)
+    orc_base_conv(x + (size_t)b * L * N, out + (size_t)b * K * N, N, s, L, t, K);
+  return nt;
+}
+int orc_mod_down_batch(const uint64_t* x, const uint64_t* y, uint64_t* out, uint32_t B, uint32_t N,
+                       const uint64_t* s, uint32_t L, const uint64_t* t, uint32_t K, int nthreads) {
+  int nt = orc_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nt)
+  for (long b = 0; b < (long)B; ++b)
+    orc_mod_down(x + (size_t)b * L * N, y + (size_t)b * K * N, out + (size_t)b * K * N, N, s, L, t, K);
+  return nt;
+}

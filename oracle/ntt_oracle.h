@@ -87,6 +87,43 @@ int orc_ntt_inverse_batch(uint64_t* x, uint32_t B, uint32_t L, uint32_t N,
 int orc_pointwise_batch(const uint64_t* a, const uint64_t* b, uint64_t* c, uint32_t B,
                         uint32_t L, uint32_t N, const uint64_t* q, int nthreads);
 
+/* --- HE steps on either side of the transform. The paper lists further HE
+ * primitives as future work (Conclusion) and motivates the NTT by HE (§1);
+ * these follow the standard definitions of the RNS HE literature.
+ *
+ * Ciphertext tensor product in the evaluation domain (first step of a
+ * ciphertext-ciphertext product, Fan-Vercauteren / BGV / CKKS): for
+ * ciphertexts a = (a0, a1) and b = (b0, b1),
+ *   d0 = a0 b0,  d1 = a0 b1 + a1 b0,  d2 = a1 b1        (mod q, elementwise)
+ * so that (a0 + a1 s)(b0 + b1 s) = d0 + d1 s + d2 s^2 for any s.
+ * Batched layout: a, b [B][2][L][N], d [B][3][L][N]; limb l uses q[l].
+ * Parity: pinned by the s-identity above (Python integers).                  */
+void orc_tensor_product(const uint64_t* a0, const uint64_t* a1, const uint64_t* b0, const uint64_t* b1,
+                        uint64_t* d0, uint64_t* d1, uint64_t* d2, uint32_t N, uint64_t q);
+int orc_tensor_batch(const uint64_t* a, const uint64_t* b, uint64_t* d, uint32_t B, uint32_t L, uint32_t N,
+                     const uint64_t* q, int nthreads);
+
+/* Fast RNS basis conversion (Bajard, Eynard, Hasan, Zucca, SAC 2016) from
+ * the source basis s_0..s_{L-1} (product S) to the target basis t_0..t_{K-1}
+ * (all primes, pairwise distinct): with shat_i = S / s_i,
+ *   conv(x)_j = sum_i [x_i shat_i^-1 mod s_i] shat_i   mod t_j.
+ * The sum is an integer equal to X + alpha S, X in [0,S) the value with
+ * residues x_i and 0 <= alpha < L; conv gives its residues mod each t_j.
+ * ModDown (the division by S that ends key switching, Cheon-Han-Kim-Kim-Song,
+ * SAC 2018): for y over the target basis and x over the source basis,
+ *   moddown(x, y)_j = (y_j - conv(x)_j) S^-1   mod t_j.
+ * Layouts: x [B][L][N], y and out [B][K][N]; canonical residues.
+ * Parity: pinned through the CRT with Python integers (conv(X) = X + alpha S
+ * for one alpha < L; moddown(X S + E) = X - beta for one beta < L).          */
+void orc_base_conv(const uint64_t* x, uint64_t* out, uint32_t N, const uint64_t* s, uint32_t L,
+                   const uint64_t* t, uint32_t K);
+void orc_mod_down(const uint64_t* x, const uint64_t* y, uint64_t* out, uint32_t N, const uint64_t* s,
+                  uint32_t L, const uint64_t* t, uint32_t K);
+int orc_base_conv_batch(const uint64_t* x, uint64_t* out, uint32_t B, uint32_t N, const uint64_t* s,
+                        uint32_t L, const uint64_t* t, uint32_t K, int nthreads);
+int orc_mod_down_batch(const uint64_t* x, const uint64_t* y, uint64_t* out, uint32_t B, uint32_t N,
+                       const uint64_t* s, uint32_t L, const uint64_t* t, uint32_t K, int nthreads);
+
 #ifdef __cplusplus
 }
 #endif

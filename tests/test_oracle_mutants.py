@@ -2,7 +2,9 @@
 mistake each (a dropped twist, psi instead of psi^-1, an off-by-one twiddle
 index, a skipped stage, a missing N^-1, a swapped butterfly, a missing bit
 reversal, a wrong sign in the definition or in the schoolbook wrap, a
-transposed pointwise operand) must each fail the battery of pins below,
+transposed pointwise operand; in the HE steps: a dropped shat^-1 factor, a
+dropped term, S in place of shat_i, a ModDown sign flip, a missing S^-1, a
+wrong tensor operand) must each fail the battery of pins below,
 which the real oracle passes. The pins compare against sympy, closed forms
 and algebra, never against the oracle itself."""
 import numpy as np
@@ -11,6 +13,7 @@ import sympy
 from sympy.discrete.convolutions import convolution_ntt
 from sympy.discrete.transforms import ntt as sympy_ntt
 
+import he_pins
 import oracle
 import seeded_inputs as si
 
@@ -18,7 +21,9 @@ Q = si.Q_SMALL
 Q60 = si.ntt_primes(60, 17, 1)[0]
 MUTANTS = {1: "dropped twist", 2: "psi^-1 twist", 3: "twiddle index +1", 4: "last stage skipped",
            5: "inverse without N^-1", 6: "definition with 2k-1", 7: "butterfly outputs swapped",
-           8: "no bit reversal", 9: "schoolbook wrap added", 10: "pointwise a*a"}
+           8: "no bit reversal", 9: "schoolbook wrap added", 10: "pointwise a*a",
+           11: "conversion without shat^-1", 12: "conversion drops the last term", 13: "S in place of shat_i",
+           14: "ModDown sign flipped", 15: "ModDown without S^-1", 16: "tensor d1 with a1 b1"}
 
 
 def battery():
@@ -50,7 +55,7 @@ def battery():
     prod = oracle.ntt_inverse(oracle.pointwise(oracle.ntt_forward(a, Q), oracle.ntt_forward(b, Q), Q), Q)
     if [int(v) for v in prod] != neg:
         failed.append("convolution theorem vs sympy")
-    return failed
+    return failed + he_pins.battery()
 
 
 def test_real_oracle_passes_battery():
