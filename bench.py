@@ -46,26 +46,34 @@ KERNEL_KEYS = [("k_col<nttk::Arith64<false>, 8, 16, true", "fwd_col_pass"),
                ("k_pointwise<nttk::ModInfo64", "pointwise")]
 
 
-def kernel_source_hash() -> str:
+HE_SOURCES = ["paper_2405_11353_amd/csrc/k_he.hip", "paper_2405_11353_amd/csrc/he.hpp",
+              "paper_2405_11353_amd/csrc/modarith.hpp"]
+HE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "he_keyswitch_n65536_traffic.json")
+HE_KERNEL_KEYS = [("k_tensor<nttk::ModInfo64", "tensor_product"), ("k_bconv<8, 2, 8, false>", "mod_up"),
+                  ("k_bconv<8, 2, 8, true>", "mod_down")]
+
+
+def kernel_source_hash(files=None) -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in files or KERNEL_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def bench_key(name: str):
-    for pat, key in KERNEL_KEYS:
+def bench_key(name: str, keys=None):
+    for pat, key in keys or KERNEL_KEYS:
         if pat in name:
             return key
     return None
 
 
-def summarize_counters(d: str):
+def summarize_counters(d: str, he: bool = False):
     """Reads the rocprofv3 CSVs of one profiling session (kernel trace, FETCH_SIZE
     and WRITE_SIZE passes on bench.py and on the 1 GiB copy microbenchmark, SQ
-    counters) from directory d and writes the summary files under profiles/."""
+    counters) from directory d and writes the summary files under profiles/
+    (the NTT passes of the headline step, or with he=True the HE steps)."""
     import csv
     import collections
     import glob
@@ -77,6 +85,18 @@ def summarize_counters(d: str):
                 agg[r["Kernel_Name"]][r["Counter_Name"]].append(float(r["Counter_Value"]))
         return {k: {c: sum(v) / len(v) for c, v in cs.items()} for k, cs in agg.items()}
 
+    if he:
+        keys, sources, traffic_file = HE_KERNEL_KEYS, HE_SOURCES, HE_TRAFFIC_FILE
+        md = os.path.join(ROOT, "profiles", "he_keyswitch_n65536_counters.md")
+        title = ("# Counters and kernel trace: HE steps at N=2^16 (tensor product of 24-limb ciphertexts, "
+                 "ModUp 3 x 8 -> 24 limbs, ModDown 2 x 8 -> 24 limbs), MI355X")
+        B = "python3 bench.py --he-only"
+    else:
+        keys, sources, traffic_file = KERNEL_KEYS, KERNEL_SOURCES, TRAFFIC_FILE
+        md = os.path.join(ROOT, "profiles", "polymul_n65536_l24_counters.md")
+        title = "# Counters and kernel trace: polymul_n65536_l24 (N=2^16, 24 limbs, 2 ciphertexts), MI355X"
+        B = ("python3 bench.py --steps 10 --warmup 2 --kernel-reps 5 --no-cpu-baseline --no-per-call "
+             "--no-batched --no-serving --no-paper-sizes --no-he")
     copy_f = [v["FETCH_SIZE"] for k, v in pmc("pmc_copy_fetch").items() if "k_copy" in k][0]
     copy_w = [v["WRITE_SIZE"] for k, v in pmc("pmc_copy_write").items() if "k_copy" in k][0]
     gib_kib = float(1 << 20)
@@ -86,24 +106,25 @@ def summarize_counters(d: str):
     for f in glob.glob(os.path.join(d, "kt", "*kernel_stats.csv")):
         for r in csv.DictReader(open(f)):
             stats[r["Name"]] = r
-    out = {"source_hash": kernel_source_hash(), "fetch_scale": f_scale, "write_scale": w_scale, "kernels": {}}
-    lines = ["# Counters and kernel trace: polymul_n65536_l24 (N=2^16, 24 limbs, 2 ciphertexts), MI355X", "",
+    out = {"source_hash": kernel_source_hash(sources), "fetch_scale": f_scale, "write_scale": w_scale,
+           "kernels": {}}
+    lines = [title, "",
              "Commands (repository root on the GPU box; each pass is its own run):", "",
-             "    B='python3 bench.py --steps 10 --warmup 2 --kernel-reps 5 --no-cpu-baseline --no-per-call --no-batched --no-serving --no-paper-sizes'",
+             f"    B='{B}'",
              "    rocprofv3 --kernel-trace --stats --output-format csv -d <dir>/kt -o kt -- $B",
              "    rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir>/pmc_fetch -o run -- $B",
              "    rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir>/pmc_write -o run -- $B",
              "    rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir>/pmc_copy_fetch -o run -- paper_2405_11353_amd/_build/ubench --copy-only",
              "    rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir>/pmc_copy_write -o run -- paper_2405_11353_amd/_build/ubench --copy-only",
              "    rocprofv3 --pmc SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT SQ_WAIT_INST_ANY SQ_WAVES --output-format csv -d <dir>/pmc_sq -o run -- $B",
-             "    python3 bench.py --summarize-counters <dir>", "",
+             f"    python3 bench.py --summarize-{'he-' if he else ''}counters <dir>", "",
              f"Scale factors from the plain copy of 1 GiB (read 1 GiB, write 1 GiB per dispatch): "
              f"FETCH_SIZE reads {copy_f:.0f} KiB -> x{f_scale:.3f}; WRITE_SIZE reads {copy_w:.0f} KiB -> x{w_scale:.3f}.",
              f"Kernel source hash: {out['source_hash']}", "",
              "| kernel | rocprof avg us | calls | scaled fetch MiB | scaled write MiB | VALU wave-instr | VALU busy | LDS bank conflicts |",
              "|---|---|---|---|---|---|---|---|"]
     for name in sorted(set(fetch) | set(stats)):
-        key = bench_key(name)
+        key = bench_key(name, keys)
         if key is None:
             continue
         avg_us = float(stats[name]["AverageNs"]) / 1e3 if name in stats else float("nan")
@@ -118,22 +139,22 @@ def summarize_counters(d: str):
         lines.append(f"| {key} | {avg_us:.2f} | {calls} | {fb / 2**20:.1f} | {wb / 2**20:.1f} | {valu:.3g} | "
                      f"{busy:.0%} | {q.get('SQ_LDS_BANK_CONFLICT', float('nan')):.3g} |")
     lines += ["", "VALU busy = SQ_INSTS_VALU x 4 cycles / (1024 SIMDs x avg duration x 2.4 GHz)."]
-    with open(TRAFFIC_FILE, "w") as fh:
+    with open(traffic_file, "w") as fh:
         json.dump(out, fh, indent=1)
-    with open(os.path.join(ROOT, "profiles", "polymul_n65536_l24_counters.md"), "w") as fh:
+    with open(md, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))
 
 
-def counter_traffic(key: str):
+def counter_traffic(key: str, he: bool = False):
     """Scaled HBM bytes of one launch of `key` from the stored counter summary,
     or None if there is none or the kernel sources changed since."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(HE_TRAFFIC_FILE if he else TRAFFIC_FILE) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    if t.get("source_hash") != kernel_source_hash() or key not in t.get("kernels", {}):
+    if t.get("source_hash") != kernel_source_hash(HE_SOURCES if he else None) or key not in t.get("kernels", {}):
         return None
     k = t["kernels"][key]
     return round(k["fetch_bytes"] + k["write_bytes"])
@@ -151,6 +172,11 @@ def parse():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-paper-sizes", action="store_true")
+    ap.add_argument("--no-he", action="store_true")
+    ap.add_argument("--he-only", action="store_true",
+                    help="time only the HE steps (tensor product, ModUp, ModDown) and print their JSON")
+    ap.add_argument("--summarize-he-counters", metavar="DIR", default=None,
+                    help="write the HE-step counter summary under profiles/ from a rocprofv3 session")
     ap.add_argument("--serving-jobs", type=int, default=3000)
     ap.add_argument("--summarize-counters", metavar="DIR", default=None,
                     help="write profiles/ summaries from a rocprofv3 session directory and exit")
@@ -290,6 +316,85 @@ def bench_paper_sizes(ntt, si, torch, reps=100, batch=1024):
     return {"workload": "cyclic_u32_q998244353_single_and_batched", "reps": reps, "batch": batch, "sizes": out}
 
 
+def bench_he_steps(ntt, si, torch, reps=50):
+    """The HE steps around the transform at the headline shape (N = 2^16, 24
+    ciphertext limbs of 60 bits) with 8 special primes and 3 key-switching
+    digits of 8 limbs: the tensor product of one ciphertext pair, ModUp of
+    the 3 digits (8 -> 24 limbs: the other 16 ciphertext limbs and the 8
+    special primes) and ModDown of the 2 key-switching outputs (8 special
+    limbs -> 24 limbs). Each kernel rotates over buffer sets larger than the
+    last-level cache and is timed with HIP events on its launch stream."""
+    N, L, K_sp, digit = 1 << 16, 24, 8, 8
+    primes = si.ntt_primes(60, 17, L + K_sp)
+    q, p = primes[:L], primes[L:]
+    stream = torch.cuda.current_stream()
+    plan = ntt.Plan(N, q)
+    modup = ntt.BaseConv(N, q[:digit], q[digit:] + p)      # one digit; the others use their own plan
+    moddown = ntt.BaseConv(N, p, q)
+    words = lambda n: torch.zeros(n, dtype=torch.int64, device="cuda")   # noqa: E731
+
+    def sets_for(nbytes):
+        return max(2, math.ceil((512 << 20) / nbytes))
+
+    def fill(t, moduli, seed):
+        per = N * len(moduli)
+        host = si.poly_batch(seed, t.numel() // per, moduli, N)
+        t.copy_(torch.from_numpy(host.reshape(-1).view(np.int64)))
+        return t
+
+    def timed(fn, n_sets):
+        for r in range(3):
+            fn(r % n_sets)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for r in range(reps):
+            fn(r % n_sets)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e3
+
+    def entry(us, nbytes, muls):
+        gbs = nbytes / (us * 1e-6) / 1e9
+        tops = muls / (us * 1e-6) / 1e12
+        return dict(us=round(us, 2), alg_bytes=nbytes, hbm_GBs=round(gbs, 1), hbm_frac=round(gbs / HBM_PEAK_GBS, 4),
+                    alg_int32_muls=muls, mul_TOPs=round(tops, 3), mul_frac=round(tops / INT32_MUL_PEAK_TOPS, 4))
+
+    out = {"workload": "he_keyswitch_n65536_l24_k8_dnum3", "N": N, "L": L, "special_primes": K_sp, "digits": 3}
+    # tensor product: read 4 words, write 3 per (limb, coefficient); 4 general products
+    tb = 7 * L * N * 8
+    ns = sets_for(tb)
+    A = [fill(words(2 * L * N), q * 2, 700 + i) for i in range(ns)]
+    B = [fill(words(2 * L * N), q * 2, 800 + i) for i in range(ns)]
+    D = [words(3 * L * N) for _ in range(ns)]
+    us = timed(lambda i: plan.tensor_product(A[i], B[i], D[i], batch=1), ns)
+    out["tensor_product"] = entry(us, tb, 4 * L * N * MULS_PER_GENERAL)
+    del A, B, D
+    # ModUp: 3 digits of 8 limbs -> 24 limbs; the dot products take 4
+    # 32x32 multiplies per (source, target) pair and coefficient
+    ub = 3 * (digit + L) * N * 8
+    ns = sets_for(ub)
+    X = [fill(words(3 * digit * N), q[:digit], 900 + i) for i in range(ns)]
+    Y = [words(3 * L * N) for _ in range(ns)]
+    us = timed(lambda i: modup.convert(X[i], Y[i], batch=3), ns)
+    out["mod_up"] = entry(us, ub, 3 * N * digit * L * 4)
+    del X, Y
+    # ModDown: 2 polynomials, read 8 special + 24 limbs, write 24
+    db = 2 * (K_sp + 2 * L) * N * 8
+    ns = sets_for(db)
+    X = [fill(words(2 * K_sp * N), p, 1000 + i) for i in range(ns)]
+    Y = [fill(words(2 * L * N), q, 1100 + i) for i in range(ns)]
+    us = timed(lambda i: moddown.mod_down(X[i], Y[i], Y[i], batch=2), ns)
+    out["mod_down"] = entry(us, db, 2 * N * K_sp * L * 4)
+    del X, Y
+    for k in ("tensor_product", "mod_up", "mod_down"):
+        e = out[k]
+        e["traffic"] = counter_traffic(k, he=True)
+        log(f"he {k}: {e['us']:.1f} us  {e['hbm_GBs']:.0f} GB/s ({e['hbm_frac']:.1%} HBM)  "
+            f"{e['mul_TOPs']:.2f} TOP/s int32 mul ({e['mul_frac']:.1%})")
+    return out
+
+
 def bench_serving(ntt, si, torch, n_jobs=3000, warm=300):
     """Poisson stream of NTT and poly-mult jobs (N 2^12..2^17, L 1..40) at 70% of
     the measured saturated rate through the server, against a per-call FIFO."""
@@ -409,6 +514,9 @@ def main():
     if args.summarize_counters:
         summarize_counters(args.summarize_counters)
         return
+    if args.summarize_he_counters:
+        summarize_counters(args.summarize_he_counters, he=True)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: the NTT batch is independent per (polynomial, limb), "
@@ -421,6 +529,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     torch.cuda.set_device(0)
+    if args.he_only:
+        print(json.dumps(bench_he_steps(ntt, si, torch)), flush=True)
+        return
     w = si.workload_polymul_n16()
     N, moduli, L = w.N, w.moduli, len(w.moduli)
     polys = 4                                       # 2 ciphertexts x 2 components
@@ -586,6 +697,7 @@ def main():
     batched = None if args.no_batched else bench_batched(ntt, si, torch)
     serving = None if args.no_serving else bench_serving(ntt, si, torch, n_jobs=args.serving_jobs)
     paper_sizes = None if args.no_paper_sizes else bench_paper_sizes(ntt, si, torch)
+    he_steps = None if args.no_he else bench_he_steps(ntt, si, torch)
 
     res = {
         "metric": "NTT/s at N=2^16 x 24 limbs (forward + inverse NTTs of a batched 2-ciphertext negacyclic product)",
@@ -611,6 +723,7 @@ def main():
         "batched": batched,
         "serving": serving,
         "paper_sizes": paper_sizes,
+        "he_steps": he_steps,
     }
     print(json.dumps(res), flush=True)
 

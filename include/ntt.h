@@ -272,6 +272,52 @@ int ntt_server_get_stats(ntt_server* server, ntt_server_stats* stats);
 int ntt_server_reset_stats(ntt_server* server);
 void ntt_server_destroy(ntt_server* server);
 
+/* ---- HE steps on either side of the transform ---------------------------------
+ * The paper motivates the NTT by homomorphic encryption (Introduction) and
+ * names further HE primitives as its future work (Conclusion). These are the
+ * two steps that surround the transform in an RNS HE multiplication, with the
+ * standard definitions of that literature. Same ownership, asynchrony and
+ * canonical-input rules as above; 64-bit words only for the conversions.
+ *
+ * Ciphertext tensor product in the NTT domain (the first step of a
+ * ciphertext-ciphertext product): for each of `batch` pairs of two-component
+ * ciphertexts d_a, d_b [batch][2][L][N] (words of the plan's width), writes
+ * d_d [batch][3][L][N] with, elementwise mod q_l,
+ *   d0 = a0*b0,  d1 = a0*b1 + a1*b0,  d2 = a1*b1
+ * so that (a0 + a1 s)(b0 + b1 s) = d0 + d1 s + d2 s^2. d_d must not overlap
+ * d_a or d_b. The plan supplies N, L and the moduli; any spectrum order. */
+int ntt_tensor_product(const ntt_plan* plan, const void* d_a, const void* d_b, void* d_d, uint32_t batch,
+                       void* stream);
+
+/* Fast RNS basis conversion (Bajard, Eynard, Hasan, Zucca, SAC 2016) from a
+ * source basis s_0..s_{L-1} (product S) to a target basis t_0..t_{K-1}, on
+ * coefficient-domain residues. With shat_i = S / s_i,
+ *   conv(x)_j = sum_i [x_i shat_i^-1 mod s_i] shat_i  mod t_j,
+ * the residues mod t_j of X + alpha S, where X in [0, S) has residues x_i and
+ * 0 <= alpha < L (alpha depends on the coefficient). ModUp in key switching
+ * is this conversion; ModDown (Cheon, Han, Kim, Kim, Song, SAC 2018) divides
+ * by S, from y over the target basis and x over the source basis:
+ *   moddown(x, y)_j = (y_j - conv(x)_j) S^-1  mod t_j.
+ * A conversion plan holds the constants (shat_i^-1 mod s_i, the K x L matrix
+ * shat_i mod t_j, S^-1 mod t_j) on the device current at creation.
+ *   N       coefficients per polynomial: even, 2 <= N <= 2^28
+ *   src, L  source primes, 1 <= L <= 64, each < 2^61 (host array, copied)
+ *   dst, K  target primes, 1 <= K <= 4096, each < 2^61; all L + K distinct
+ * Returns NULL and sets ntt_last_error() to NTT_ERR_ARG, NTT_ERR_N,
+ * NTT_ERR_MODULUS (not prime, too large, repeated), NTT_ERR_NOMEM or
+ * NTT_ERR_HIP on failure. */
+typedef struct ntt_bconv ntt_bconv;
+ntt_bconv* ntt_bconv_create(uint32_t N, const uint64_t* src, uint32_t L, const uint64_t* dst, uint32_t K);
+void ntt_bconv_destroy(ntt_bconv* conv);
+int ntt_bconv_get_info(const ntt_bconv* conv, uint32_t* N, uint32_t* L, uint32_t* K);
+/* d_out [batch][K][N] = conv(d_x [batch][L][N]). d_out must not overlap d_x.
+ * Device pointers 16-byte aligned (NTT_ERR_ARG otherwise). */
+int ntt_base_conv(const ntt_bconv* conv, const void* d_x, void* d_out, uint32_t batch, void* stream);
+/* d_out [batch][K][N] = moddown(d_x [batch][L][N], d_y [batch][K][N]).
+ * d_out may be d_y (in place) but must not overlap d_x. 16-byte aligned. */
+int ntt_mod_down(const ntt_bconv* conv, const void* d_x, const void* d_y, void* d_out, uint32_t batch,
+                 void* stream);
+
 #ifdef __cplusplus
 }
 #endif

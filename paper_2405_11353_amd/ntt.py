@@ -98,6 +98,12 @@ def lib() -> ctypes.CDLL:
             "ntt_inverse": (i32, [vp, vp, u32, vp]),
             "ntt_pointwise_mul": (i32, [vp, vp, vp, vp, u32, vp]),
             "ntt_pointwise_mul_inverse": (i32, [vp, vp, vp, vp, u32, vp]),
+            "ntt_tensor_product": (i32, [vp, vp, vp, vp, u32, vp]),
+            "ntt_bconv_create": (vp, [u32, u64p, u32, u64p, u32]),
+            "ntt_bconv_destroy": (None, [vp]),
+            "ntt_bconv_get_info": (i32, [vp, ctypes.POINTER(u32), ctypes.POINTER(u32), ctypes.POINTER(u32)]),
+            "ntt_base_conv": (i32, [vp, vp, vp, u32, vp]),
+            "ntt_mod_down": (i32, [vp, vp, vp, vp, u32, vp]),
             "ntt_pointwise_mul_inverse_stage": (i32, [vp, vp, vp, vp, u32, i32, vp]),
             "ntt_forward_stage": (i32, [vp, vp, u32, i32, vp]),
             "ntt_inverse_stage": (i32, [vp, vp, u32, i32, vp]),
@@ -225,6 +231,29 @@ def ntt_pointwise_mul_inverse(plan: int, a, b, c, batch: int, stream=None) -> No
 def ntt_pointwise_mul_inverse_stage(plan: int, a, b, c, batch: int, stage: int, stream=None) -> None:
     _check(lib().ntt_pointwise_mul_inverse_stage(plan, _ptr(a), _ptr(b), _ptr(c), batch, stage, _stream(stream)),
            "ntt_pointwise_mul_inverse_stage")
+
+
+def ntt_tensor_product(plan: int, a, b, d, batch: int, stream=None) -> None:
+    _check(lib().ntt_tensor_product(plan, _ptr(a), _ptr(b), _ptr(d), batch, _stream(stream)), "ntt_tensor_product")
+
+
+def ntt_bconv_create(N: int, src, dst) -> int:
+    h = lib().ntt_bconv_create(N, _u64_array(src), len(src), _u64_array(dst), len(dst))
+    if not h:
+        raise NttError(ntt_last_error(), "ntt_bconv_create")
+    return h
+
+
+def ntt_bconv_destroy(conv: int) -> None:
+    lib().ntt_bconv_destroy(conv)
+
+
+def ntt_base_conv(conv: int, x, out, batch: int, stream=None) -> None:
+    _check(lib().ntt_base_conv(conv, _ptr(x), _ptr(out), batch, _stream(stream)), "ntt_base_conv")
+
+
+def ntt_mod_down(conv: int, x, y, out, batch: int, stream=None) -> None:
+    _check(lib().ntt_mod_down(conv, _ptr(x), _ptr(y), _ptr(out), batch, _stream(stream)), "ntt_mod_down")
 
 
 def ntt_plan_get_psi(plan: int, L: int) -> list[int]:
@@ -390,6 +419,55 @@ class Server:
         self.close()
 
 
+class BaseConv:
+    """Owns an ntt_bconv*: fast RNS basis conversion from `src` primes to
+    `dst` primes (and ModDown, the division by prod(src)), 64-bit words."""
+
+    def __init__(self, N: int, src, dst):
+        self.N = int(N)
+        self.src = [int(q) for q in src]
+        self.dst = [int(q) for q in dst]
+        self.L, self.K = len(self.src), len(self.dst)
+        self.handle = ntt_bconv_create(self.N, self.src, self.dst)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            ntt_bconv_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _batch(self, t, limbs, batch):
+        per = limbs * self.N
+        if batch is None:
+            if t.numel() % per:
+                raise ValueError("tensor size is not a multiple of limbs*N")
+            batch = t.numel() // per
+        if not t.is_cuda or t.element_size() != 8 or t.numel() < per * batch:
+            raise ValueError("tensor shape/dtype/device mismatch")
+        return batch
+
+    def convert(self, x, out, batch=None, stream=None):
+        """out [batch][K][N] = conv(x [batch][L][N])."""
+        batch = self._batch(x, self.L, batch)
+        self._batch(out, self.K, batch)
+        ntt_base_conv(self.handle, x, out, batch, stream)
+        return out
+
+    def mod_down(self, x, y, out=None, batch=None, stream=None):
+        """out [batch][K][N] = (y - conv(x)) * prod(src)^-1; out defaults to y."""
+        out = y if out is None else out
+        batch = self._batch(x, self.L, batch)
+        self._batch(y, self.K, batch)
+        self._batch(out, self.K, batch)
+        ntt_mod_down(self.handle, x, y, out, batch, stream)
+        return out
+
+
 # ---- convenience object ------------------------------------------------------
 class Plan:
     """Owns an ntt_plan*; methods check tensor shape/dtype/device, then call the C ABI."""
@@ -484,6 +562,17 @@ class Plan:
         bt = self._batch(a, batch)
         ntt_pointwise_mul_inverse_stage(self.handle, a, b, out, bt, stage, stream)
         return out
+
+    def tensor_product(self, a, b, d, batch=None, stream=None):
+        """d [batch][3][L][N] = tensor product of ciphertexts a, b [batch][2][L][N]."""
+        per = self.L * self.N
+        if batch is None:
+            batch = a.numel() // (2 * per)
+        for t, k in ((a, 2), (b, 2), (d, 3)):
+            if not t.is_cuda or t.element_size() * 8 != self.word or t.numel() < k * per * batch:
+                raise ValueError("tensor shape/dtype/device mismatch")
+        ntt_tensor_product(self.handle, a, b, d, batch, stream)
+        return d
 
     def workspace_bytes(self, batch: int) -> int:
         return ntt_workspace_bytes(self.handle, batch)

@@ -85,3 +85,24 @@ def test_tune_table_save_load_round_trip(lib, tmp_path):
     with pytest.raises(ntt.NttError):
         ntt.ntt_tune_load(str(f))      # another architecture
     ntt.ntt_tune_clear()
+
+
+def test_bconv_argument_validation(lib):
+    ps = si.ntt_primes(60, 17, 70)
+    lib.ntt_bconv_create.restype = ctypes.c_void_p
+    lib.ntt_bconv_create.argtypes = [ctypes.c_uint32, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p,
+                                     ctypes.c_uint32]
+    cases = [
+        ((64, None, 1, u64s(ps[1:2]), 1), -1),
+        ((64, u64s(ps[:1]), 0, u64s(ps[1:2]), 1), -1),        # empty source basis
+        ((64, u64s(ps[:1]), 1, u64s(ps[1:2]), 0), -1),        # empty target basis
+        ((64, u64s(ps[:65]), 65, u64s(ps[65:66]), 1), -1),    # source basis above 64 primes
+        ((63, u64s(ps[:2]), 2, u64s(ps[2:3]), 1), -2),        # odd N
+        ((0, u64s(ps[:2]), 2, u64s(ps[2:3]), 1), -2),
+        ((64, u64s([ps[0], ps[0] + 2]), 2, u64s(ps[2:3]), 1), -3),   # not prime
+        ((64, u64s(ps[:2]), 2, u64s([ps[1]]), 1), -3),        # repeated across the bases
+        ((64, u64s([(1 << 61) + 1]), 1, u64s(ps[2:3]), 1), -3),
+    ]
+    for args, code in cases:
+        assert lib.ntt_bconv_create(*args) is None
+        assert lib.ntt_last_error() == code, (args, lib.ntt_last_error())

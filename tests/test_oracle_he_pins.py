@@ -35,3 +35,9 @@ def test_crt_helper_against_definition():
     ms = [5, 7, 9 + 2]
     for X in range(5 * 7 * 11):
         assert he_pins.crt([X % m for m in ms], ms) == X
+
+
+@pytest.mark.parametrize("L,K", [(3, 2), (9, 4)])
+def test_conversions_with_61bit_primes(L, K):
+    assert he_pins.check_base_conv(seed=40 + L, N=16, L=L, K=K, bits=61) == []
+    assert he_pins.check_mod_down(seed=50 + L, N=16, L=L, K=K, bits=61) == []
