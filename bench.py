@@ -95,7 +95,7 @@ def summarize_counters(d: str, he: bool = False):
         keys, sources, traffic_file = KERNEL_KEYS, KERNEL_SOURCES, TRAFFIC_FILE
         md = os.path.join(ROOT, "profiles", "polymul_n65536_l24_counters.md")
         title = "# Counters and kernel trace: polymul_n65536_l24 (N=2^16, 24 limbs, 2 ciphertexts), MI355X"
-        B = ("python3 bench.py --steps 10 --warmup 2 --kernel-reps 5 --no-cpu-baseline --no-per-call "
+        B = ("python3 bench.py --steps 10 --warmup 2 --kernel-reps 5 --streams 1 --no-cpu-baseline --no-per-call "
              "--no-batched --no-serving --no-paper-sizes --no-he")
     copy_f = [v["FETCH_SIZE"] for k, v in pmc("pmc_copy_fetch").items() if "k_copy" in k][0]
     copy_w = [v["WRITE_SIZE"] for k, v in pmc("pmc_copy_write").items() if "k_copy" in k][0]
@@ -166,6 +166,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--streams", type=int, default=2,
+                    help="streams that consecutive steps alternate between (1: all on one stream)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-per-call", action="store_true")
@@ -537,7 +539,10 @@ def main():
     polys = 4                                       # 2 ciphertexts x 2 components
     set_words = polys * L * N
     set_bytes = set_words * 8
-    n_sets = max(2, math.ceil((1 << 30) / set_bytes))
+    # a multiple of the stream count, so that steps in flight on different
+    # streams never share a buffer set
+    n_streams = max(1, args.streams)
+    n_sets = math.ceil(max(2, math.ceil((1 << 30) / set_bytes)) / n_streams) * n_streams
     log(f"workload {w.name}: N={N} L={L} polys={polys}; {n_sets} rotating sets of {set_bytes >> 20} MiB")
 
     host = si.poly_batch(w.seed, polys, moduli, N)  # [4][24][N]: polys 0,1 = ciphertext A, 2,3 = B
@@ -547,10 +552,10 @@ def main():
     path, logn1 = plan.variant
     stream = torch.cuda.current_stream()
 
-    def step(buf):
-        plan.forward(buf, batch=4)
+    def step(buf, st=None):
+        plan.forward(buf, batch=4, stream=st)
         a, b = buf[:2], buf[2:]
-        plan.pointwise_inverse(a, b, a, batch=2)   # pointwise product fused into the inverse
+        plan.pointwise_inverse(a, b, a, batch=2, stream=st)   # pointwise product fused into the inverse
 
     # ---- correctness of the timed configuration on one set (vs. an independent
     # GPU check: forward then inverse must return the input exactly)
@@ -560,22 +565,40 @@ def main():
     torch.cuda.synchronize()
     assert torch.equal(chk, base), "round trip in the bench configuration is not exact"
 
-    for s in range(args.warmup):
-        step(sets[s % n_sets])
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    e0.record(stream)
-    for s in range(args.steps):
-        step(sets[s % n_sets])
-    e1.record(stream)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_wall = (t1 - t0) * 1e3 / args.steps
-    ms_event = e0.elapsed_time(e1) / args.steps
+    # Consecutive steps alternate between `streams` streams (default priority);
+    # each step works on its own buffer set, so a step's inverse passes (48
+    # transforms, too few to fill the GPU) overlap the next step's forward
+    # passes. With one stream every launch pays its own ramp-up and drain.
+    streams = [stream] + [torch.cuda.Stream() for _ in range(n_streams - 1)]
+
+    def timed_steps(n_streams):
+        sts = streams[:n_streams]
+        for s in range(args.warmup):
+            step(sets[s % n_sets], sts[s % n_streams])
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        for st in sts[1:]:
+            st.wait_event(e0)
+        for s in range(args.steps):
+            step(sets[s % n_sets], sts[s % n_streams])
+        for st in sts[1:]:
+            done = torch.cuda.Event()
+            done.record(st)
+            stream.wait_event(done)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        return (t1 - t0) * 1e3 / args.steps, e0.elapsed_time(e1) / args.steps
+
+    ms_wall_1, ms_event_1 = timed_steps(1)
+    ms_wall, ms_event = timed_steps(len(streams)) if len(streams) > 1 else (ms_wall_1, ms_event_1)
     ntts_per_step = polys * L + 2 * L               # 96 forward + 48 inverse
     value = ntts_per_step / (ms_wall / 1e3)
-    log(f"step: {ms_wall * 1e3:.1f} us wall, {ms_event * 1e3:.1f} us events; {value / 1e6:.3f} M NTT/s")
+    log(f"step: {ms_wall * 1e3:.1f} us wall, {ms_event * 1e3:.1f} us events on {len(streams)} streams; "
+        f"{value / 1e6:.3f} M NTT/s (one stream: {ms_wall_1 * 1e3:.1f} us, "
+        f"{ntts_per_step / (ms_wall_1 / 1e3) / 1e6:.3f} M NTT/s)")
 
     # ---- per-kernel durations with HIP events on the launch stream
     def time_kernel(fn, reps):
@@ -714,12 +737,15 @@ def main():
         "data": "synthetic: seeded uniform residues mod 24 primes q < 2^60, q = 1 mod 2^17",
         "config": {"workload": w.name, "N": N, "L": L, "polys": polys, "ntts_per_step": ntts_per_step,
                    "variant": {"path": "fourstep" if path == ntt.NTT_PATH_FOURSTEP else "lds", "log_n1": logn1},
-                   "rotating_sets": n_sets, "footprint_MiB": n_sets * set_bytes >> 20},
+                   "rotating_sets": n_sets, "footprint_MiB": n_sets * set_bytes >> 20,
+                   "streams": len(streams)},
         "roofline": roofline,
         "kernels": per_kernel,
         "per_call": per_call,
         "cpu_baseline": cpu,
         "ms_per_step_events": round(ms_event, 5),
+        "one_stream": {"ms_per_step": round(ms_wall_1, 5), "ms_per_step_events": round(ms_event_1, 5),
+                       "value": round(ntts_per_step / (ms_wall_1 / 1e3), 1)},
         "batched": batched,
         "serving": serving,
         "paper_sizes": paper_sizes,

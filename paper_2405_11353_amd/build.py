@@ -22,8 +22,9 @@ ARCH = os.environ.get("NTT_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 # packed-fp32 instructions are disabled for all device code
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# NTT_HIPCC_FLAGS: extra flags for tuning builds (e.g. -DNTT_NT_OUT=1)
 COMMON = [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",
-          "-I", os.path.join(ROOT, "include"), "-I", CSRC] + DEVICE_FLAGS
+          "-I", os.path.join(ROOT, "include"), "-I", CSRC] + DEVICE_FLAGS + os.environ.get("NTT_HIPCC_FLAGS", "").split()
 
 KERNEL_UNITS = ["k_u64.hip", "k_u64x.hip", "k_u32.hip", "k_pointwise.hip", "k_batch.hip", "k_paper.hip", "k_he.hip"]
 HOST_UNITS = ["params.cpp", "capi.cpp", "pool.cpp", "tune.cpp", "batch.cpp", "serve.cpp", "he.cpp"]

@@ -236,6 +236,38 @@ k_lds(typename A::word* __restrict__ data, const typename A::tw_t* __restrict__ 
   }
 }
 
+// ============================================================ data access
+// Loads and stores of polynomial data, by role: IN (first read of a
+// transform's input), MID (the four-step intermediate, written by one pass
+// and re-read by the next while it is still in the last-level cache) and OUT
+// (a transform's final output). Each access kind can carry the nontemporal
+// (streaming) hint.
+#ifndef NTT_NT_LD_IN
+#define NTT_NT_LD_IN 0
+#endif
+#ifndef NTT_NT_ST_MID
+#define NTT_NT_ST_MID 0
+#endif
+#ifndef NTT_NT_LD_MID
+#define NTT_NT_LD_MID 0
+#endif
+#ifndef NTT_NT_ST_OUT
+#define NTT_NT_ST_OUT 0
+#endif
+constexpr bool NT_LD_IN = NTT_NT_LD_IN, NT_ST_MID = NTT_NT_ST_MID, NT_LD_MID = NTT_NT_LD_MID,
+               NT_ST_OUT = NTT_NT_ST_OUT;
+
+template <bool NT, class T>
+__device__ __forceinline__ T ld_data(const T* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+template <bool NT, class T>
+__device__ __forceinline__ void st_data(T* p, T v) {
+  if constexpr (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
 // ============================================================ column pass
 // NC columns per workgroup, N1/16 threads per column; columns are adjacent so
 // each row segment read or written is NC words (128 bytes).
@@ -282,7 +314,7 @@ k_col(const typename A::word* in, typename A::word* out, const typename A::tw_t*
   W v[16];
   if constexpr (FWD) {
 #pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = src[(size_t)(i * TPC + t) * N2];
+    for (int i = 0; i < 16; ++i) v[i] = ld_data<NT_LD_IN>(src + (size_t)(i * TPC + t) * N2);
     static_for<0, S::NPH>([&](auto P_) {
       constexpr int p = decltype(P_)::value;
       if constexpr (p > 0) {
@@ -296,10 +328,10 @@ k_col(const typename A::word* in, typename A::word* out, const typename A::tw_t*
       ct_phase<A, S::rs(p)>(a, v, tw, S::s0(p), grp<LOGN1>(p, t));
     });
 #pragma unroll
-    for (int i = 0; i < 16; ++i) dst[(size_t)pos<LOGN1>(S::NPH - 1, t, i) * N2] = v[i];
+    for (int i = 0; i < 16; ++i) st_data<NT_ST_MID>(dst + (size_t)pos<LOGN1>(S::NPH - 1, t, i) * N2, v[i]);
   } else {
 #pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = src[(size_t)pos<LOGN1>(S::NPH - 1, t, i) * N2];
+    for (int i = 0; i < 16; ++i) v[i] = ld_data<NT_LD_MID>(src + (size_t)pos<LOGN1>(S::NPH - 1, t, i) * N2);
     static_for_down<S::NPH - 1, 0>([&](auto P_) {
       constexpr int p = decltype(P_)::value;
       if constexpr (p < S::NPH - 1) {
@@ -313,7 +345,7 @@ k_col(const typename A::word* in, typename A::word* out, const typename A::tw_t*
       gs_phase<A, S::rs(p), p == 0>(a, v, tw, S::s0(p), grp<LOGN1>(p, t));
     });
 #pragma unroll
-    for (int i = 0; i < 16; ++i) dst[(size_t)(i * TPC + t) * N2] = a.canon_inv(v[i]);
+    for (int i = 0; i < 16; ++i) st_data<NT_ST_OUT>(dst + (size_t)(i * TPC + t) * N2, a.canon_inv(v[i]));
   }
 }
 
@@ -374,7 +406,7 @@ k_row(const typename A::word* in, typename A::word* out, const typename A::tw_t*
   if constexpr (FWD) {
     const W* src = in + pbase + (size_t)r * N2;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = src[i * TPR + t];
+    for (int i = 0; i < 16; ++i) v[i] = ld_data<NT_LD_MID>(src + i * TPR + t);
     static_for<0, S::NPH>([&](auto P_) {
       constexpr int p = decltype(P_)::value;
       if constexpr (p > 0) {
@@ -397,7 +429,7 @@ k_row(const typename A::word* in, typename A::word* out, const typename A::tw_t*
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
         const uint32_t cc = cg + TPR * j;
-        dst[(size_t)brv(cc, LOGN2) * N1] = lds[rr * RSTR + pad16(cc)];
+        st_data<NT_ST_OUT>(dst + (size_t)brv(cc, LOGN2) * N1, lds[rr * RSTR + pad16(cc)]);
       }
     } else {
       if (S::NPH > 1) wave_lds_sync();
@@ -406,7 +438,7 @@ k_row(const typename A::word* in, typename A::word* out, const typename A::tw_t*
       wave_lds_sync();
       W* dst = out + pbase + (size_t)r * N2;
 #pragma unroll
-      for (int i = 0; i < 16; ++i) dst[i * TPR + t] = sh[pad16(i * TPR + t)];
+      for (int i = 0; i < 16; ++i) st_data<NT_ST_OUT>(dst + i * TPR + t, sh[pad16(i * TPR + t)]);
     }
   } else {
     if constexpr (NATURAL) {
@@ -417,8 +449,8 @@ k_row(const typename A::word* in, typename A::word* out, const typename A::tw_t*
       for (int j = 0; j < 16; ++j) {
         const uint32_t cc = cg + TPR * j;
         const size_t e = (size_t)brv(cc, LOGN2) * N1;
-        W val = src[e];
-        if constexpr (MULIN) val = mulmod_general(val, in2[off + e], *mi);
+        W val = ld_data<NT_LD_IN>(src + e);
+        if constexpr (MULIN) val = mulmod_general(val, ld_data<NT_LD_IN>(in2 + off + e), *mi);
         lds[rr * RSTR + pad16(cc)] = val;
       }
       __syncthreads();
@@ -427,8 +459,8 @@ k_row(const typename A::word* in, typename A::word* out, const typename A::tw_t*
       const W* src = in + off;
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
-        W val = src[i * TPR + t];
-        if constexpr (MULIN) val = mulmod_general(val, in2[off + i * TPR + t], *mi);
+        W val = ld_data<NT_LD_IN>(src + i * TPR + t);
+        if constexpr (MULIN) val = mulmod_general(val, ld_data<NT_LD_IN>(in2 + off + i * TPR + t), *mi);
         sh[pad16(i * TPR + t)] = val;
       }
       wave_lds_sync();
@@ -449,7 +481,7 @@ k_row(const typename A::word* in, typename A::word* out, const typename A::tw_t*
     });
     W* dst = out + pbase + (size_t)r * N2;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) dst[i * TPR + t] = v[i];
+    for (int i = 0; i < 16; ++i) st_data<NT_ST_MID>(dst + i * TPR + t, v[i]);
   }
 }
 
