@@ -61,6 +61,30 @@ __global__ void __launch_bounds__(256) k_copy(const uint4* __restrict__ src, uin
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
 }
 
+// One 16-byte vector per thread, no loop (the grid covers the buffer), with
+// or without the nontemporal hint; and the read-only / write-only halves.
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+template <bool NT>
+__global__ void __launch_bounds__(256) k_copy1(const uint4* __restrict__ src, uint4* __restrict__ dst, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    if (NT) __builtin_nontemporal_store(__builtin_nontemporal_load((const v4u*)src + i), (v4u*)dst + i);
+    else dst[i] = src[i];
+  }
+}
+__global__ void __launch_bounds__(256) k_read1(const uint4* __restrict__ src, uint32_t* sink, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const v4u v = __builtin_nontemporal_load((const v4u*)src + i);
+    if ((v.x ^ v.y ^ v.z ^ v.w) == 0x9e3779b9u) sink[0] = v.x;
+  }
+}
+__global__ void __launch_bounds__(256) k_write1(uint4* __restrict__ dst, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const v4u v = {(uint32_t)i, 1u, 2u, 3u};
+  if (i < n) __builtin_nontemporal_store(v, (v4u*)dst + i);
+}
+
 template <int OP>
 static int run_issue(int ncu, FILE* out) {
   const int blocks = ncu * 8, threads = 256, iters = 4096;
@@ -112,6 +136,29 @@ static int run_copy(FILE* out) {
   CHK(hipEventElapsedTime(&ms, e0, e1));
   gbps = 2.0 * bytes * reps / (ms * 1e-3) / 1e9;
   fprintf(out, "{\"op\": \"hipMemcpy_d2d_2GiB\", \"ms_per_copy\": %.4f, \"GBps_read_plus_write\": %.1f}\n", ms / reps, gbps);
+  // one vector per thread over the whole buffer
+  const size_t blocks1 = (n + 255) / 256;
+  uint32_t* sink;
+  CHK(hipMalloc(&sink, 64));
+  auto time_it = [&](auto launch) -> float {
+    launch(0);
+    CHK(hipGetLastError());
+    CHK(hipDeviceSynchronize());
+    CHK(hipEventRecord(e0));
+    for (int r = 0; r < reps; ++r) launch(r);
+    CHK(hipEventRecord(e1)); CHK(hipEventSynchronize(e1));
+    float t = 0; CHK(hipEventElapsedTime(&t, e0, e1));
+    return t / reps;
+  };
+  ms = time_it([&](int r) { k_copy1<false><<<blocks1, 256>>>((r & 1) ? b : a, (r & 1) ? a : b, n); });
+  fprintf(out, "{\"op\": \"copy_one_vector_per_thread_2GiB\", \"ms_per_copy\": %.4f, \"GBps_read_plus_write\": %.1f}\n", ms, 2.0 * bytes / (ms * 1e-3) / 1e9);
+  ms = time_it([&](int r) { k_copy1<true><<<blocks1, 256>>>((r & 1) ? b : a, (r & 1) ? a : b, n); });
+  fprintf(out, "{\"op\": \"copy_one_vector_per_thread_nontemporal_2GiB\", \"ms_per_copy\": %.4f, \"GBps_read_plus_write\": %.1f}\n", ms, 2.0 * bytes / (ms * 1e-3) / 1e9);
+  ms = time_it([&](int r) { k_read1<<<blocks1, 256>>>((r & 1) ? b : a, sink, n); });
+  fprintf(out, "{\"op\": \"read_one_vector_per_thread_nontemporal_2GiB\", \"ms\": %.4f, \"GBps\": %.1f}\n", ms, 1.0 * bytes / (ms * 1e-3) / 1e9);
+  ms = time_it([&](int r) { k_write1<<<blocks1, 256>>>((r & 1) ? b : a, n); });
+  fprintf(out, "{\"op\": \"write_one_vector_per_thread_nontemporal_2GiB\", \"ms\": %.4f, \"GBps\": %.1f}\n", ms, 1.0 * bytes / (ms * 1e-3) / 1e9);
+  CHK(hipFree(sink));
   CHK(hipFree(a)); CHK(hipFree(b));
   return 0;
 }
