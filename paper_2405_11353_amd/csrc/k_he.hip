@@ -116,7 +116,11 @@ k_bconv(const uint64_t* __restrict__ x, const uint64_t* yin, uint64_t* out, cons
   };
   __shared__ Split ys[LMAX][64];
   constexpr uint32_t M30 = (1u << 30) - 1;
-  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6, W = blockDim.x >> 6;
+  // the wave index is uniform across the wave; saying so keeps the matrix
+  // rows and per-prime constants on scalar loads (vector loads here would
+  // need waits that also drain this wave's outstanding stores)
+  const uint32_t lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t W = blockDim.x >> 6;
   const uint32_t slots = N / CPT, tiles = (slots + 63) / 64;
   const uint32_t b = blockIdx.x / tiles;
   const uint32_t slot = (blockIdx.x - b * tiles) * 64 + lane;

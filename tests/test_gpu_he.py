@@ -172,3 +172,14 @@ def test_conversion_rejects_bad_arguments(ntt):
     assert lib.ntt_base_conv(conv.handle, p, p, 0, None) == -1            # empty batch
     assert lib.ntt_mod_down(conv.handle, p, None, p, 1, None) == -1       # no y
     assert lib.ntt_base_conv(None, p, p, 1, None) == -1
+
+
+def test_conversion_plan_info(ntt):
+    import ctypes
+    conv = ntt.BaseConv(96, P17[:5], P17[5:12])
+    n, l, k = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+    assert ntt.lib().ntt_bconv_get_info(conv.handle, ctypes.byref(n), ctypes.byref(l), ctypes.byref(k)) == 0
+    assert (n.value, l.value, k.value) == (96, 5, 7)
+    assert ntt.lib().ntt_bconv_get_info(None, None, None, None) == -1
+    conv.close()
+    conv.close()          # closing twice is harmless
