@@ -96,7 +96,7 @@ def summarize_counters(d: str, he: bool = False):
         md = os.path.join(ROOT, "profiles", "polymul_n65536_l24_counters.md")
         title = "# Counters and kernel trace: polymul_n65536_l24 (N=2^16, 24 limbs, 2 ciphertexts), MI355X"
         B = ("python3 bench.py --steps 10 --warmup 2 --kernel-reps 5 --streams 1 --no-cpu-baseline --no-per-call "
-             "--no-batched --no-serving --no-paper-sizes --no-he")
+             "--no-batched --no-serving --no-paper-sizes --no-he --no-ablations")
     copy_f = [v["FETCH_SIZE"] for k, v in pmc("pmc_copy_fetch").items() if "k_copy" in k][0]
     copy_w = [v["WRITE_SIZE"] for k, v in pmc("pmc_copy_write").items() if "k_copy" in k][0]
     gib_kib = float(1 << 20)
@@ -175,6 +175,7 @@ def parse():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-paper-sizes", action="store_true")
     ap.add_argument("--no-he", action="store_true")
+    ap.add_argument("--no-ablations", action="store_true")
     ap.add_argument("--he-only", action="store_true",
                     help="time only the HE steps (tensor product, ModUp, ModDown) and print their JSON")
     ap.add_argument("--summarize-he-counters", metavar="DIR", default=None,
@@ -316,6 +317,64 @@ def bench_paper_sizes(ntt, si, torch, reps=100, batch=1024):
         log(f"paper size N={N}: " + ", ".join(f"{v}: {row[v]['single_us']} us / {row[v]['batched_ntt_per_s'] / 1e6:.1f} M/s"
                                              for v, _ in variants))
     return {"workload": "cyclic_u32_q998244353_single_and_batched", "reps": reps, "batch": batch, "sizes": out}
+
+
+def bench_ablations(ntt, si, torch, steps=60, warm=5):
+    """The headline step (2 ciphertexts, N = 2^16, 24 limbs, one stream) with one
+    design choice changed at a time: the four-step split N1 x N2, the exact
+    quotient of the 64-bit Shoup product instead of the approximate one, the
+    pointwise product as its own pass instead of fused into the first inverse
+    pass, and the LDS-resident path forced off (it cannot hold 2^16 points).
+    Each variant is checked: forward then inverse returns the input."""
+    w = si.workload_polymul_n16()
+    N, moduli, L = w.N, w.moduli, len(w.moduli)
+    host = si.poly_batch(w.seed, 4, moduli, N)
+    base = torch.from_numpy(host.view(np.int64)).cuda()
+    set_bytes = base.numel() * 8
+    n_sets = max(2, math.ceil((1 << 30) / set_bytes))
+    sets = [base.clone() for _ in range(n_sets)]
+    stream = torch.cuda.current_stream()
+
+    def run(plan, fused):
+        def step(buf):
+            plan.forward(buf, batch=4)
+            a, b = buf[:2], buf[2:]
+            if fused:
+                plan.pointwise_inverse(a, b, a, batch=2)
+            else:
+                plan.pointwise(a, b, a, batch=2)
+                plan.inverse(a, batch=2)
+        chk = base.clone()
+        plan.forward(chk, batch=4)
+        plan.inverse(chk, batch=4)
+        torch.cuda.synchronize()
+        assert torch.equal(chk, base), "ablation variant is not exact"
+        for s in range(warm):
+            step(sets[s % n_sets])
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for s in range(steps):
+            step(sets[s % n_sets])
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps * 1e3
+
+    rows = []
+    for name, log_n1, exact, fused in [("default: split 2^8 x 2^8, approximate quotient, fused product", 8, False, True),
+                                       ("split 2^7 x 2^9", 7, False, True),
+                                       ("split 2^9 x 2^7", 9, False, True),
+                                       ("exact quotient", 8, True, True),
+                                       ("separate pointwise pass", 8, False, False)]:
+        plan = ntt.Plan(N, moduli)
+        plan.set_variant(ntt.NTT_PATH_FOURSTEP, log_n1)
+        plan.set_exact_quotient(exact)
+        us = run(plan, fused)
+        rows.append({"variant": name, "log_n1": log_n1, "exact_quotient": exact, "fused_product": fused,
+                     "us_per_step": round(us, 1), "ntt_per_s": round(144 / (us * 1e-6), 1)})
+        log(f"ablation {name}: {us:.1f} us/step")
+        plan.close()
+    return {"workload": w.name, "streams": 1, "rows": rows}
 
 
 def bench_he_steps(ntt, si, torch, reps=50):
@@ -721,6 +780,7 @@ def main():
     serving = None if args.no_serving else bench_serving(ntt, si, torch, n_jobs=args.serving_jobs)
     paper_sizes = None if args.no_paper_sizes else bench_paper_sizes(ntt, si, torch)
     he_steps = None if args.no_he else bench_he_steps(ntt, si, torch)
+    ablations = None if args.no_ablations else bench_ablations(ntt, si, torch)
 
     res = {
         "metric": "NTT/s at N=2^16 x 24 limbs (forward + inverse NTTs of a batched 2-ciphertext negacyclic product)",
@@ -750,6 +810,7 @@ def main():
         "serving": serving,
         "paper_sizes": paper_sizes,
         "he_steps": he_steps,
+        "ablations": ablations,
     }
     print(json.dumps(res), flush=True)
 
