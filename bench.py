@@ -96,7 +96,7 @@ def summarize_counters(d: str, he: bool = False):
         md = os.path.join(ROOT, "profiles", "polymul_n65536_l24_counters.md")
         title = "# Counters and kernel trace: polymul_n65536_l24 (N=2^16, 24 limbs, 2 ciphertexts), MI355X"
         B = ("python3 bench.py --steps 10 --warmup 2 --kernel-reps 5 --streams 1 --no-cpu-baseline --no-per-call "
-             "--no-batched --no-serving --no-paper-sizes --no-he --no-ablations")
+             "--no-batched --no-serving --no-paper-sizes --no-he --no-ablations --no-polymul")
     copy_f = [v["FETCH_SIZE"] for k, v in pmc("pmc_copy_fetch").items() if "k_copy" in k][0]
     copy_w = [v["WRITE_SIZE"] for k, v in pmc("pmc_copy_write").items() if "k_copy" in k][0]
     gib_kib = float(1 << 20)
@@ -176,6 +176,7 @@ def parse():
     ap.add_argument("--no-paper-sizes", action="store_true")
     ap.add_argument("--no-he", action="store_true")
     ap.add_argument("--no-ablations", action="store_true")
+    ap.add_argument("--no-polymul", action="store_true")
     ap.add_argument("--he-only", action="store_true",
                     help="time only the HE steps (tensor product, ModUp, ModDown) and print their JSON")
     ap.add_argument("--summarize-he-counters", metavar="DIR", default=None,
@@ -317,6 +318,57 @@ def bench_paper_sizes(ntt, si, torch, reps=100, batch=1024):
         log(f"paper size N={N}: " + ", ".join(f"{v}: {row[v]['single_us']} us / {row[v]['batched_ntt_per_s'] / 1e6:.1f} M/s"
                                              for v, _ in variants))
     return {"workload": "cyclic_u32_q998244353_single_and_batched", "reps": reps, "batch": batch, "sizes": out}
+
+
+def bench_polymul(ntt, si, torch, steps=100, warm=10):
+    """The headline product (2 ciphertexts, N = 2^16, 24 limbs) through
+    ntt_polymul, which keeps the spectra on chip: c = a * b for the 2 pairs of
+    components, coefficients in and out. Reported per step and as the
+    equivalent NTT rate (the same 96 forward and 48 inverse transforms), on one
+    and on two streams, beside the headline step that hands the spectra back."""
+    w = si.workload_polymul_n16()
+    N, moduli, L = w.N, w.moduli, len(w.moduli)
+    host = si.poly_batch(w.seed, 4, moduli, N)
+    base = torch.from_numpy(host.view(np.int64)).cuda()
+    n_sets = max(2, math.ceil((1 << 30) / (base.numel() * 8 * 3 // 2)))
+    n_sets += n_sets % 2
+    sets = [(base.clone(), torch.zeros_like(base[:2])) for _ in range(n_sets)]
+    plan = ntt.Plan(N, moduli)
+    stream = torch.cuda.current_stream()
+    # check: equal to the unfused product
+    ref = base.clone()
+    plan.forward(ref, batch=4)
+    plan.pointwise_inverse(ref[:2], ref[2:], ref[:2], batch=2)
+    out = torch.zeros_like(base[:2])
+    plan.polymul(base[:2], base[2:], out, batch=2)
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref[:2]), "fused product differs from the unfused one"
+    res = {"workload": w.name, "products_per_step": 2 * L, "ntt_equivalent_per_step": 144}
+    for n_streams in (1, 2):
+        sts = [stream] + [torch.cuda.Stream() for _ in range(n_streams - 1)]
+        for s in range(warm):
+            x, c = sets[s % n_sets]
+            plan.polymul(x[:2], x[2:], c, batch=2, stream=sts[s % n_streams])
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        for st in sts[1:]:
+            st.wait_event(e0)
+        for s in range(steps):
+            x, c = sets[s % n_sets]
+            plan.polymul(x[:2], x[2:], c, batch=2, stream=sts[s % n_streams])
+        for st in sts[1:]:
+            done = torch.cuda.Event()
+            done.record(st)
+            stream.wait_event(done)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        us = (time.perf_counter() - t0) * 1e6 / steps
+        res[f"streams_{n_streams}"] = {"us_per_step": round(us, 1), "ntt_equivalent_per_s": round(144 / (us * 1e-6), 1)}
+        log(f"polymul (spectra on chip), {n_streams} stream(s): {us:.1f} us/step, "
+            f"{144 / (us * 1e-6) / 1e6:.3f} M NTT-equivalent/s")
+    return res
 
 
 def bench_ablations(ntt, si, torch, steps=60, warm=5):
@@ -781,6 +833,7 @@ def main():
     paper_sizes = None if args.no_paper_sizes else bench_paper_sizes(ntt, si, torch)
     he_steps = None if args.no_he else bench_he_steps(ntt, si, torch)
     ablations = None if args.no_ablations else bench_ablations(ntt, si, torch)
+    polymul = None if args.no_polymul else bench_polymul(ntt, si, torch)
 
     res = {
         "metric": "NTT/s at N=2^16 x 24 limbs (forward + inverse NTTs of a batched 2-ciphertext negacyclic product)",
@@ -811,6 +864,7 @@ def main():
         "paper_sizes": paper_sizes,
         "he_steps": he_steps,
         "ablations": ablations,
+        "polymul": polymul,
     }
     print(json.dumps(res), flush=True)
 

@@ -114,6 +114,18 @@ int ntt_pointwise_mul(const ntt_plan* plan, const void* d_a, const void* d_b, vo
 int ntt_pointwise_mul_inverse(const ntt_plan* plan, const void* d_a, const void* d_b, void* d_c,
                               uint32_t batch, void* stream);
 
+/* Product of coefficient-domain polynomials, for `batch` pairs of [L][N]
+ * polynomials d_a, d_b: d_c = a * b in Z_q[x]/(x^N + 1) per limb (mod
+ * x^N - 1 for NTT_CYCLIC plans), i.e. inverse(pointwise(forward(a),
+ * forward(b))) without handing the spectra back. At four-step sizes the two
+ * forward row passes, the product and the first inverse pass are one kernel,
+ * so the spectra never reach HBM. d_a and d_b are not modified; d_c may be
+ * d_a or d_b. The plan keeps a workspace of 2 * batch * L * N words per
+ * stream. The spectrum-order flag of the plan does not apply (inputs and
+ * output are coefficients); a paper-variant plan uses the library's default
+ * variant. Asynchronous. */
+int ntt_polymul(const ntt_plan* plan, const void* d_a, const void* d_b, void* d_c, uint32_t batch, void* stream);
+
 /* One kernel of a four-step transform, for timing and profiling: stage 0 is
  * the first kernel (forward: column pass, data -> scratch; inverse: row pass,
  * data -> scratch), stage 1 the second (scratch -> data). Running stage 0 then

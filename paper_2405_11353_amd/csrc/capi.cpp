@@ -11,6 +11,7 @@
 #include "ntt.h"
 #include "ntt_internal.hpp"
 #include "params.hpp"
+#include "polymul.hpp"
 
 namespace {
 thread_local int g_last_error = NTT_OK;
@@ -463,3 +464,84 @@ int ntt_pointwise_mul(const ntt_plan* p, const void* a, const void* b, void* c, 
 }
 
 }  // extern "C"
+
+static int run_polymul(const ntt_plan* pc, const void* a, const void* b, void* c, uint32_t batch, void* stream) {
+  int rc = check_common(pc, batch);
+  if (rc != NTT_OK) return rc;
+  if (!a || !b || !c) return NTT_ERR_ARG;
+  ntt_plan* p = const_cast<ntt_plan*>(pc);
+  int path, logN1, exact;
+  select_variant(p, 2 * batch * p->L, &path, &logN1, &exact);
+  if (is_paper_path(path)) ntti::default_variant(p->word, (int)p->logN, &path, &logN1);
+  const size_t bytes = (((size_t)batch * p->L) << p->logN) * (p->word / 8);
+  void* ws = nullptr;
+  rc = get_scratch(p, stream, 2 * bytes, &ws);
+  if (rc != NTT_OK) return rc;
+  void* sa = ws;
+  void* sb = (unsigned char*)ws + bytes;
+  const hipStream_t s = (hipStream_t)stream;
+  nttk::Launch L;
+  L.word = p->word;
+  L.exact = 0;  // one quotient flavour for every pass, so the lazy ranges agree
+  L.logN = (int)p->logN;
+  L.logN1 = logN1;
+  L.natural = 1;
+  L.mods = p->d_mod;
+  L.L = p->L;
+  L.batch = batch;
+  L.items = batch * p->L;
+  L.stream = s;
+  hipError_t e;
+  if (path == NTT_PATH_FOURSTEP) {
+    // column passes of a and b into the workspace, the fused row kernel, and
+    // the inverse column pass into c
+    L.path = nttk::PATH_TWO;
+    L.tw = p->d_tw_fwd;
+    L.stage_mask = 1;
+    L.data = const_cast<void*>(a);
+    L.scratch = sa;
+    if ((const unsigned char*)b == (const unsigned char*)a + bytes) {
+      // b follows a: one column-pass launch over both
+      L.batch = 2 * batch;
+      L.items = 2 * batch * p->L;
+      e = nttk::launch_ntt(L, true);
+      L.batch = batch;
+      L.items = batch * p->L;
+      if (e != hipSuccess) return e == hipErrorNotSupported ? NTT_ERR_UNSUPPORTED : NTT_ERR_HIP;
+    } else {
+      if ((e = nttk::launch_ntt(L, true)) != hipSuccess) return e == hipErrorNotSupported ? NTT_ERR_UNSUPPORTED : NTT_ERR_HIP;
+      L.data = const_cast<void*>(b);
+      L.scratch = sb;
+      if ((e = nttk::launch_ntt(L, true)) != hipSuccess) return NTT_ERR_HIP;
+    }
+    if ((e = nttk::launch_row_polymul(p->word, (int)p->logN, logN1, sa, sb, p->d_tw_fwd, p->d_tw_inv, p->d_mod,
+                                      p->L, batch, s)) != hipSuccess)
+      return e == hipErrorNotSupported ? NTT_ERR_UNSUPPORTED : NTT_ERR_HIP;
+    L.tw = p->d_tw_inv;
+    L.stage_mask = 2;
+    L.data = c;
+    L.scratch = sa;
+    return nttk::launch_ntt(L, false) == hipSuccess ? NTT_OK : NTT_ERR_HIP;
+  }
+  // LDS-resident shapes: the operands are copied into the workspace and
+  // transformed in place; the product goes to c, which is transformed back
+  if (hipMemcpyAsync(sa, a, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(sb, b, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return NTT_ERR_HIP;
+  L.path = path == NTT_PATH_TINY ? nttk::PATH_TINY : nttk::PATH_LDS;
+  L.stage_mask = 3;
+  L.tw = p->d_tw_fwd;
+  L.data = sa;
+  if ((e = nttk::launch_ntt(L, true)) != hipSuccess) return e == hipErrorNotSupported ? NTT_ERR_UNSUPPORTED : NTT_ERR_HIP;
+  L.data = sb;
+  if (nttk::launch_ntt(L, true) != hipSuccess) return NTT_ERR_HIP;
+  if (nttk::launch_pointwise(p->word, sa, sb, c, p->d_mod, p->L, p->logN, batch * p->L, s) != hipSuccess)
+    return NTT_ERR_HIP;
+  L.tw = p->d_tw_inv;
+  L.data = c;
+  return nttk::launch_ntt(L, false) == hipSuccess ? NTT_OK : NTT_ERR_HIP;
+}
+
+extern "C" int ntt_polymul(const ntt_plan* p, const void* a, const void* b, void* c, uint32_t batch, void* stream) {
+  return run_polymul(p, a, b, c, batch, stream);
+}

@@ -1,0 +1,129 @@
+// Polynomial product, four-step shapes: the forward row passes of both
+// operands, their elementwise product and the first inverse pass, fused into
+// one kernel per row tile. Between the column passes the spectra never reach
+// HBM.
+#include "polymul.hpp"
+#include "ntt_core.hpp"
+
+namespace nttk {
+
+// 16 rows per workgroup, N2/16 threads per row (a row lies inside one wave,
+// so every exchange is wave-local). The forward phases leave thread t holding
+// positions pos(last phase, t, i) of each row, which is the layout the
+// inverse phases start from, so the product needs no exchange.
+template <class A, int LOGN2>
+__global__ void __launch_bounds__(16 << (LOGN2 - 4))
+k_row_polymul(typename A::word* sa, const typename A::word* __restrict__ sb,
+              const typename A::tw_t* __restrict__ twf_all, const typename A::tw_t* __restrict__ twi_all,
+              const typename ModOf<A>::type* __restrict__ mods, uint32_t L, uint32_t logN, uint32_t batch) {
+  using W = typename A::word;
+  using TW = typename A::tw_t;
+  using M = typename ModOf<A>::type;
+  using S = Sched<LOGN2>;
+  constexpr uint32_t N2 = 1u << LOGN2, TPR = N2 / 16, RSTR = N2 + N2 / 16 + 1;
+  static_assert(TPR <= 64, "a row must fit in one wavefront");
+  __shared__ W lds[16 * RSTR];
+  const uint32_t logN1 = logN - LOGN2, N1 = 1u << logN1;
+  const uint32_t tiles = N1 / 16;
+  // logical order (limb, tile, pair): the pairs sharing a limb's twiddles run
+  // back to back on one XCD
+  const uint32_t bid = xcd_remap(blockIdx.x, gridDim.x);
+  const uint32_t b = bid % batch, rest = bid / batch;
+  const uint32_t tile = rest % tiles, l = rest / tiles;
+  if (l >= L) return;
+  const uint32_t t = threadIdx.x % TPR, rl = threadIdx.x / TPR;
+  const uint32_t r = tile * 16 + rl;
+  const M m = mods[l];
+  A a;
+  a.load(m);
+  const TW* twf = twf_all + ((size_t)l << logN);
+  const TW* twi = twi_all + ((size_t)l << logN);
+  const size_t off = (((size_t)b * L + l) << logN) + (size_t)r * N2;
+  W* rowa = sa + off;
+  const W* rowb = sb + off;
+  W* sh = lds + rl * RSTR;
+
+  W va[16], vb[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) va[i] = rowa[i * TPR + t];
+
+  auto forward = [&](W (&v)[16], const TW* twf) {
+    static_for<0, S::NPH>([&](auto P_) {
+      constexpr int p = decltype(P_)::value;
+      if constexpr (p > 0) {
+        wave_lds_sync();
+#pragma unroll
+        for (int i = 0; i < 16; ++i) sh[pad16(pos<LOGN2>(p - 1, t, i))] = v[i];
+        wave_lds_sync();
+#pragma unroll
+        for (int i = 0; i < 16; ++i) v[i] = sh[pad16(pos<LOGN2>(p, t, i))];
+      }
+      ct_phase<A, S::rs(p)>(a, v, twf, logN1 + S::s0(p), (r << S::s0(p)) + grp<LOGN2>(p, t));
+    });
+  };
+  // one operand at a time, so that only one row's working set is live: a's
+  // transform is made canonical (the general product needs operands below q)
+  // before b's row is loaded
+  forward(va, twf);
+#pragma unroll
+  for (int i = 0; i < 16; ++i) va[i] = a.canon_fwd(va[i]);
+#pragma unroll
+  for (int i = 0; i < 16; ++i) vb[i] = rowb[i * TPR + t];
+  // b's transform reads the same twiddles; an opaque copy of the table
+  // pointer makes the compiler load them again (cache hits) instead of
+  // keeping all of a's twiddles live across both transforms
+  const TW* twf_b = twf;
+  asm volatile("" : "+v"(twf_b));
+  forward(vb, twf_b);
+#pragma unroll
+  for (int i = 0; i < 16; ++i) va[i] = mulmod_general(va[i], a.canon_fwd(vb[i]), m);
+  static_for_down<S::NPH - 1, 0>([&](auto P_) {
+    constexpr int p = decltype(P_)::value;
+    if constexpr (p < S::NPH - 1) {
+      wave_lds_sync();
+#pragma unroll
+      for (int i = 0; i < 16; ++i) sh[pad16(pos<LOGN2>(p + 1, t, i))] = va[i];
+      wave_lds_sync();
+#pragma unroll
+      for (int i = 0; i < 16; ++i) va[i] = sh[pad16(pos<LOGN2>(p, t, i))];
+    }
+    gs_phase<A, S::rs(p), false>(a, va, twi, logN1 + S::s0(p), (r << S::s0(p)) + grp<LOGN2>(p, t));
+  });
+  // phase 0 leaves thread t with positions i * TPR + t
+#pragma unroll
+  for (int i = 0; i < 16; ++i) rowa[i * TPR + t] = va[i];
+}
+
+template <class A>
+static hipError_t go(int logN, int logN1, void* sa, const void* sb, const void* twf, const void* twi,
+                     const void* mods, uint32_t L, uint32_t batch, hipStream_t s) {
+  using W = typename A::word;
+  using TW = typename A::tw_t;
+  using M = typename ModOf<A>::type;
+  const int lg2 = logN - logN1;
+  if (logN1 < 6 || logN1 > 9 || lg2 < 6 || lg2 > 9) return hipErrorNotSupported;
+  const uint32_t tiles = (1u << logN1) / 16;
+  const dim3 grid(batch * L * tiles), block(16u << (lg2 - 4));
+#define POLYMUL_CASE(LG2)                                                                                  \
+  case LG2:                                                                                                \
+    hipLaunchKernelGGL((k_row_polymul<A, LG2>), grid, block, 0, s, (W*)sa, (const W*)sb, (const TW*)twf, \
+                       (const TW*)twi, (const M*)mods, L, (uint32_t)logN, batch);                          \
+    break;
+  switch (lg2) {
+    POLYMUL_CASE(6)
+    POLYMUL_CASE(7)
+    POLYMUL_CASE(8)
+    POLYMUL_CASE(9)
+    default: return hipErrorNotSupported;
+  }
+#undef POLYMUL_CASE
+  return hipGetLastError();
+}
+
+hipError_t launch_row_polymul(int word, int logN, int logN1, void* sa, const void* sb, const void* tw_fwd,
+                              const void* tw_inv, const void* mods, uint32_t L, uint32_t batch, hipStream_t s) {
+  if (word == 32) return go<Arith32>(logN, logN1, sa, sb, tw_fwd, tw_inv, mods, L, batch, s);
+  return go<Arith64<false>>(logN, logN1, sa, sb, tw_fwd, tw_inv, mods, L, batch, s);
+}
+
+}  // namespace nttk

@@ -99,6 +99,7 @@ def lib() -> ctypes.CDLL:
             "ntt_pointwise_mul": (i32, [vp, vp, vp, vp, u32, vp]),
             "ntt_pointwise_mul_inverse": (i32, [vp, vp, vp, vp, u32, vp]),
             "ntt_tensor_product": (i32, [vp, vp, vp, vp, u32, vp]),
+            "ntt_polymul": (i32, [vp, vp, vp, vp, u32, vp]),
             "ntt_bconv_create": (vp, [u32, u64p, u32, u64p, u32]),
             "ntt_bconv_destroy": (None, [vp]),
             "ntt_bconv_get_info": (i32, [vp, ctypes.POINTER(u32), ctypes.POINTER(u32), ctypes.POINTER(u32)]),
@@ -231,6 +232,10 @@ def ntt_pointwise_mul_inverse(plan: int, a, b, c, batch: int, stream=None) -> No
 def ntt_pointwise_mul_inverse_stage(plan: int, a, b, c, batch: int, stage: int, stream=None) -> None:
     _check(lib().ntt_pointwise_mul_inverse_stage(plan, _ptr(a), _ptr(b), _ptr(c), batch, stage, _stream(stream)),
            "ntt_pointwise_mul_inverse_stage")
+
+
+def ntt_polymul(plan: int, a, b, c, batch: int, stream=None) -> None:
+    _check(lib().ntt_polymul(plan, _ptr(a), _ptr(b), _ptr(c), batch, _stream(stream)), "ntt_polymul")
 
 
 def ntt_tensor_product(plan: int, a, b, d, batch: int, stream=None) -> None:
@@ -561,6 +566,15 @@ class Plan:
     def pointwise_inverse_stage(self, a, b, out, stage: int, batch=None, stream=None):
         bt = self._batch(a, batch)
         ntt_pointwise_mul_inverse_stage(self.handle, a, b, out, bt, stage, stream)
+        return out
+
+    def polymul(self, a, b, out, batch=None, stream=None):
+        """out = a * b (negacyclic, or cyclic for NTT_CYCLIC plans) for batch
+        pairs of [L][N] coefficient-domain polynomials; a and b are kept."""
+        bt = self._batch(a, batch)
+        self._batch(b, bt)
+        self._batch(out, bt)
+        ntt_polymul(self.handle, a, b, out, bt, stream)
         return out
 
     def tensor_product(self, a, b, d, batch=None, stream=None):
