@@ -146,6 +146,20 @@ def summarize_counters(d: str, he: bool = False):
     print("\n".join(lines))
 
 
+def counter_valu_busy(key: str):
+    """VALU busy fraction of `key` from the stored counter summary
+    (SQ_INSTS_VALU x 4 cycles over SIMDs x duration x 2.4 GHz), or None."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    k = t.get("kernels", {}).get(key)
+    if t.get("source_hash") != kernel_source_hash() or not k or not k.get("rocprof_avg_us"):
+        return None
+    return round(k["valu_wave_instr"] * 4 / (1024 * k["rocprof_avg_us"] * 1e-6 * 2.4e9), 3)
+
+
 def counter_traffic(key: str, he: bool = False):
     """Scaled HBM bytes of one launch of `key` from the stored counter summary,
     or None if there is none or the kernel sources changed since."""
@@ -768,6 +782,7 @@ def main():
     roofline["traffic_unit"] = "bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by a 1 GiB copy)"
     roofline["kernel"] = dominant
     roofline["avg_launch_us"] = dk["us"]
+    roofline["valu_busy"] = counter_valu_busy(dominant)
 
     # ---- per-call baseline: the same step as one call per (polynomial, limb)
     per_call = None
