@@ -288,12 +288,45 @@ def bench_batched(ntt, si, torch, reps=10):
 PAPER_TABLE1_BEST_FPGA_US = {1024: 2.27, 4096: 8.60, 16384: 37.50, 65536: 669.30}
 
 
+def graph_single(ntt, torch, plan, one, reps):
+    """Mean time of one transform when `reps` dependent transforms are replayed
+    from one captured HIP graph (launch overhead amortised), checked against
+    the same transforms run eagerly, on two replays."""
+    x0 = one.clone()
+    buf = one.clone()
+    cs = torch.cuda.Stream()
+    with torch.cuda.stream(cs):
+        plan.forward(buf, batch=1)     # any per-stream workspace exists before capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=cs):
+        for _ in range(reps):
+            plan.forward(buf, batch=1)
+    ref = x0.clone()
+    for rep in range(2):
+        buf.copy_(x0) if rep == 0 else None
+        g.replay()
+        for _ in range(reps):
+            plan.forward(ref, batch=1)
+        torch.cuda.synchronize()
+        assert torch.equal(buf, ref), "graph replay differs from the eager transforms"
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    g.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return round(e0.elapsed_time(e1) / reps * 1e3, 3)
+
+
 def bench_paper_sizes(ntt, si, torch, reps=100, batch=1024):
     """The paper's own setting: one cyclic transform with a 32-bit prime at
     1K/4K/16K/64K, timed as the mean of 100 runs between device-resident
     input and output (the paper's GPU methodology), plus batched throughput,
     for the library's kernels and for the paper's algorithm variants run as
-    one kernel per stage (DIT, DIF, Pease, Pease_nc, Stockham)."""
+    one kernel per stage (DIT, DIF, Pease, Pease_nc, Stockham). For the
+    library's kernels the 100 runs are also replayed from one HIP graph
+    (single_us_graph), which removes the per-launch overhead."""
     q = si.Q_SMALL
     stream = torch.cuda.current_stream()
     variants = [("fused", None), ("dit", ntt.NTT_PATH_PAPER_DIT), ("dif", ntt.NTT_PATH_PAPER_DIF),
@@ -326,11 +359,13 @@ def bench_paper_sizes(ntt, si, torch, reps=100, batch=1024):
                     res["single_us"] = round(us, 3)
                 else:
                     res["batched_ntt_per_s"] = round(b / (us * 1e-6), 1)
+            if path is None:
+                res["single_us_graph"] = graph_single(ntt, torch, plan, one, reps)
             row[vname] = res
             plan.close()
         out.append(row)
         log(f"paper size N={N}: " + ", ".join(f"{v}: {row[v]['single_us']} us / {row[v]['batched_ntt_per_s'] / 1e6:.1f} M/s"
-                                             for v, _ in variants))
+                                             for v, _ in variants) + f"; fused from a graph: {row['fused']['single_us_graph']} us")
     return {"workload": "cyclic_u32_q998244353_single_and_batched", "reps": reps, "batch": batch, "sizes": out}
 
 
