@@ -135,3 +135,15 @@ def test_polymul_adjacent_operands(ntt):
     np.testing.assert_array_equal(from_dev(dx).reshape(x.shape), x)
     got = from_dev(dc).reshape(2, len(moduli), N)
     np.testing.assert_array_equal(got, composed(ntt, plan, x[:2], x[2:], 64))
+
+
+@pytest.mark.parametrize("N,L,batch", [(2, 1, 1), (4, 2, 3), (8, 1, 2), (4096, 1, 1), (4096, 4, 5)])
+def test_polymul_small_and_default_shapes(ntt, N, L, batch):
+    # tiny transforms (one thread each), one limb and one pair, odd batch
+    moduli = P18[:L]
+    plan, a, b, got = case(ntt, N, moduli, batch, seed=N + L)
+    for p in range(batch):
+        for l, q in enumerate(moduli):
+            if N <= 8 or (p == 0 and l == 0):
+                np.testing.assert_array_equal(got[p, l], oracle.negacyclic_mul(a[p, l], b[p, l], q))
+    np.testing.assert_array_equal(got, composed(ntt, plan, a, b, 64))
