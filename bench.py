@@ -95,7 +95,7 @@ def summarize_counters(d: str, he: bool = False):
         keys, sources, traffic_file = KERNEL_KEYS, KERNEL_SOURCES, TRAFFIC_FILE
         md = os.path.join(ROOT, "profiles", "polymul_n65536_l24_counters.md")
         title = "# Counters and kernel trace: polymul_n65536_l24 (N=2^16, 24 limbs, 2 ciphertexts), MI355X"
-        B = ("python3 bench.py --steps 10 --warmup 2 --kernel-reps 5 --streams 1 --no-cpu-baseline --no-per-call "
+        B = ("python3 bench.py --steps 2 --warmup 1 --kernel-reps 40 --streams 1 --no-cpu-baseline --no-per-call "
              "--no-batched --no-serving --no-paper-sizes --no-he --no-ablations --no-polymul")
     copy_f = [v["FETCH_SIZE"] for k, v in pmc("pmc_copy_fetch").items() if "k_copy" in k][0]
     copy_w = [v["WRITE_SIZE"] for k, v in pmc("pmc_copy_write").items() if "k_copy" in k][0]
