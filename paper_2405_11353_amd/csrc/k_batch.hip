@@ -2,6 +2,7 @@
 // 64-bit words, approximate quotient, natural order, forward and inverse.
 #include "launch.hpp"
 #include "ntt_core.hpp"
+#include "polymul.hpp"
 
 namespace nttk {
 
@@ -124,6 +125,12 @@ hipError_t launch_batch_u64(const BatchLaunch& c, bool fwd) {
     return col_sw(c.logN1, c, false, IO_SCRATCH_DATA);
   }
   return hipErrorNotSupported;
+}
+
+hipError_t launch_batch_col_u64(const BatchLaunch& c, bool fwd, int io) {
+  if (c.items == 0) return hipSuccess;
+  if (c.path != PATH_TWO || !shape_supported(64, 0, PATH_TWO, c.logN, c.logN1)) return hipErrorNotSupported;
+  return col_sw(c.logN1, c, fwd, io);
 }
 
 hipError_t launch_ind_copy(const ItemDesc* desc, uint32_t items, uint32_t max_logn, hipStream_t s) {

@@ -3,6 +3,7 @@
 // one kernel per row tile. Between the column passes the spectra never reach
 // HBM.
 #include "polymul.hpp"
+#include "launch.hpp"
 #include "ntt_core.hpp"
 
 namespace nttk {
@@ -11,11 +12,15 @@ namespace nttk {
 // so every exchange is wave-local). The forward phases leave thread t holding
 // positions pos(last phase, t, i) of each row, which is the layout the
 // inverse phases start from, so the product needs no exchange.
-template <class A, int LOGN2>
+// IND: items come from a descriptor table (data: a's column-pass output,
+// overwritten with the product; aux: b's; twiddles and modulus per item), as
+// in the server's batches.
+template <class A, int LOGN2, bool IND = false>
 __global__ void __launch_bounds__(16 << (LOGN2 - 4))
 k_row_polymul(typename A::word* sa, const typename A::word* __restrict__ sb,
               const typename A::tw_t* __restrict__ twf_all, const typename A::tw_t* __restrict__ twi_all,
-              const typename ModOf<A>::type* __restrict__ mods, uint32_t L, uint32_t logN, uint32_t batch) {
+              const typename ModOf<A>::type* __restrict__ mods, uint32_t L, uint32_t logN, uint32_t batch,
+              const ItemDesc* __restrict__ desc = nullptr) {
   using W = typename A::word;
   using TW = typename A::tw_t;
   using M = typename ModOf<A>::type;
@@ -25,22 +30,42 @@ k_row_polymul(typename A::word* sa, const typename A::word* __restrict__ sb,
   __shared__ W lds[16 * RSTR];
   const uint32_t logN1 = logN - LOGN2, N1 = 1u << logN1;
   const uint32_t tiles = N1 / 16;
-  // logical order (limb, tile, pair): the pairs sharing a limb's twiddles run
-  // back to back on one XCD
   const uint32_t bid = xcd_remap(blockIdx.x, gridDim.x);
-  const uint32_t b = bid % batch, rest = bid / batch;
-  const uint32_t tile = rest % tiles, l = rest / tiles;
-  if (l >= L) return;
   const uint32_t t = threadIdx.x % TPR, rl = threadIdx.x / TPR;
+  uint32_t tile;
+  M m;
+  const TW* twf;
+  const TW* twi;
+  W* rowa;
+  const W* rowb;
+  if constexpr (IND) {
+    // logical order (item, tile): an item's tiles run back to back on one XCD
+    const uint32_t item = bid / tiles;
+    tile = bid % tiles;
+    if (item >= batch) return;
+    const ItemDesc d = desc[item];
+    m = *(const M*)d.mod;
+    twf = (const TW*)d.tw_fwd;
+    twi = (const TW*)d.tw_inv;
+    rowa = (W*)d.data + (size_t)(tile * 16 + rl) * N2;
+    rowb = (const W*)d.aux + (size_t)(tile * 16 + rl) * N2;
+  } else {
+    // logical order (limb, tile, pair): the pairs sharing a limb's twiddles
+    // run back to back on one XCD
+    const uint32_t b = bid % batch, rest = bid / batch;
+    tile = rest % tiles;
+    const uint32_t l = rest / tiles;
+    if (l >= L) return;
+    m = mods[l];
+    twf = twf_all + ((size_t)l << logN);
+    twi = twi_all + ((size_t)l << logN);
+    const size_t off = (((size_t)b * L + l) << logN) + (size_t)(tile * 16 + rl) * N2;
+    rowa = sa + off;
+    rowb = sb + off;
+  }
   const uint32_t r = tile * 16 + rl;
-  const M m = mods[l];
   A a;
   a.load(m);
-  const TW* twf = twf_all + ((size_t)l << logN);
-  const TW* twi = twi_all + ((size_t)l << logN);
-  const size_t off = (((size_t)b * L + l) << logN) + (size_t)r * N2;
-  W* rowa = sa + off;
-  const W* rowb = sb + off;
   W* sh = lds + rl * RSTR;
 
   W va[16], vb[16];
@@ -124,6 +149,28 @@ hipError_t launch_row_polymul(int word, int logN, int logN1, void* sa, const voi
                               const void* tw_inv, const void* mods, uint32_t L, uint32_t batch, hipStream_t s) {
   if (word == 32) return go<Arith32>(logN, logN1, sa, sb, tw_fwd, tw_inv, mods, L, batch, s);
   return go<Arith64<false>>(logN, logN1, sa, sb, tw_fwd, tw_inv, mods, L, batch, s);
+}
+
+hipError_t launch_ind_row_polymul(const ItemDesc* desc, uint32_t items, int logN, int logN1, hipStream_t s) {
+  using A = Arith64<false>;
+  const int lg2 = logN - logN1;
+  if (items == 0) return hipSuccess;
+  if (logN1 < 6 || logN1 > 9 || lg2 < 6 || lg2 > 9) return hipErrorNotSupported;
+  const dim3 grid(items * ((1u << logN1) / 16)), block(16u << (lg2 - 4));
+#define IND_CASE(LG2)                                                                                      \
+  case LG2:                                                                                                \
+    hipLaunchKernelGGL((k_row_polymul<A, LG2, true>), grid, block, 0, s, nullptr, nullptr, nullptr, nullptr, \
+                       nullptr, 1u, (uint32_t)logN, items, desc);                                          \
+    break;
+  switch (lg2) {
+    IND_CASE(6)
+    IND_CASE(7)
+    IND_CASE(8)
+    IND_CASE(9)
+    default: return hipErrorNotSupported;
+  }
+#undef IND_CASE
+  return hipGetLastError();
 }
 
 }  // namespace nttk

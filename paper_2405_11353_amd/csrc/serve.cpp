@@ -24,6 +24,7 @@
 #include <vector>
 
 #include "ntt_internal.hpp"
+#include "polymul.hpp"
 
 namespace {
 
@@ -155,6 +156,10 @@ static int launch_batch(ntt_server* s, Slot& slot) {
   using nttk::ItemDesc;
   std::vector<ItemDesc> copy, pw;
   std::map<uint32_t, std::vector<ItemDesc>> fwd, inv;
+  // four-step products: column passes of a and b into the workspace, the
+  // fused row kernel (both forward row passes, the product, the first
+  // inverse pass), the inverse column pass into the output
+  std::map<uint32_t, std::vector<ItemDesc>> pm_col, pm_row, pm_inv;
   uint32_t max_logn = 0;
   for (Job* j : slot.jobs) {
     const size_t n = (size_t)j->N;
@@ -169,6 +174,24 @@ static int launch_batch(ntt_server* s, Slot& slot) {
       d.tw_inv = j->tw[l].tw_inv;
       d.mod = j->tw[l].mod;
       uint64_t* out_l = j->out + l * n;
+      if (j->op == NTT_REQ_POLYMUL && j->fourstep) {
+        uint64_t* sa = ws + l * n;
+        uint64_t* sb = ws + (j->L + l) * n;
+        ItemDesc ca = d, cb = d, r = d, v = d;
+        ca.data = const_cast<uint64_t*>(j->a + l * n);  // read only (data -> scratch)
+        ca.scratch = sa;
+        cb.data = const_cast<uint64_t*>(j->b + l * n);
+        cb.scratch = sb;
+        r.data = sa;
+        r.aux = sb;
+        v.data = out_l;
+        v.scratch = sa;
+        pm_col[j->logN].push_back(ca);
+        pm_col[j->logN].push_back(cb);
+        pm_row[j->logN].push_back(r);
+        pm_inv[j->logN].push_back(v);
+        continue;
+      }
       if (j->a != j->out) {
         ItemDesc c = d;
         c.data = out_l;
@@ -207,6 +230,15 @@ static int launch_batch(ntt_server* s, Slot& slot) {
     uint32_t logN;
     size_t off, n;
   };
+  auto append = [&all](std::map<uint32_t, std::vector<ItemDesc>>& m, std::vector<Run>& out, bool f) {
+    for (auto& kv : m) {
+      out.push_back({f, kv.first, all.size(), kv.second.size()});
+      all.insert(all.end(), kv.second.begin(), kv.second.end());
+    }
+  };
+  std::vector<Run> pm_col_runs, pm_row_runs, pm_inv_runs;
+  append(pm_col, pm_col_runs, true);
+  append(pm_row, pm_row_runs, true);
   std::vector<Run> runs;
   for (auto& kv : fwd) {
     runs.push_back({true, kv.first, all.size(), kv.second.size()});
@@ -218,11 +250,31 @@ static int launch_batch(ntt_server* s, Slot& slot) {
     runs.push_back({false, kv.first, all.size(), kv.second.size()});
     all.insert(all.end(), kv.second.begin(), kv.second.end());
   }
+  append(pm_inv, pm_inv_runs, false);
   if (all.size() > slot.cap) return NTT_ERR_ARG;
   std::copy(all.begin(), all.end(), slot.h_desc);
   hipError_t e = hipMemcpyAsync(slot.d_desc, slot.h_desc, all.size() * sizeof(ItemDesc), hipMemcpyHostToDevice,
                                 slot.stream);
   if (e == hipSuccess) e = nttk::launch_ind_copy(slot.d_desc, (uint32_t)copy.size(), max_logn, slot.stream);
+  auto col_launch = [&](const Run& r, bool f, int io) {
+    nttk::BatchLaunch c;
+    int path, n1;
+    ntti::default_variant(64, (int)r.logN, &path, &n1);
+    c.path = nttk::PATH_TWO;
+    c.logN = (int)r.logN;
+    c.logN1 = n1;
+    c.desc = slot.d_desc + r.off;
+    c.items = (uint32_t)r.n;
+    c.stream = slot.stream;
+    return nttk::launch_batch_col_u64(c, f, io);
+  };
+  for (const Run& r : pm_col_runs)
+    if (e == hipSuccess) e = col_launch(r, true, nttk::IO_DATA_SCRATCH);
+  for (const Run& r : pm_row_runs) {
+    int path, n1;
+    ntti::default_variant(64, (int)r.logN, &path, &n1);
+    if (e == hipSuccess) e = nttk::launch_ind_row_polymul(slot.d_desc + r.off, (uint32_t)r.n, (int)r.logN, n1, slot.stream);
+  }
   bool pw_done = false;
   for (const Run& r : runs) {
     if (!r.fwd && !pw_done) {
@@ -242,6 +294,8 @@ static int launch_batch(ntt_server* s, Slot& slot) {
   }
   if (!pw_done && e == hipSuccess)
     e = nttk::launch_ind_pointwise(slot.d_desc + pw_off, (uint32_t)pw.size(), max_logn, slot.stream);
+  for (const Run& r : pm_inv_runs)
+    if (e == hipSuccess) e = col_launch(r, false, nttk::IO_SCRATCH_DATA);
   if (e == hipSuccess) e = hipEventRecord(slot.done, slot.stream);
   return e == hipSuccess ? NTT_OK : NTT_ERR_HIP;
 }
@@ -414,7 +468,9 @@ int ntt_server_submit(ntt_server* s, const ntt_request* r, uint64_t* ticket) {
   if (j->op == NTT_REQ_POLYMUL && j->out == j->b && j->out != j->a) std::swap(j->a, j->b);  // a*b = b*a
   j->fourstep = server_fourstep(j->logN);
   const size_t poly = (size_t)j->L * j->N * 8;
-  j->ws_bytes = (j->op == NTT_REQ_POLYMUL ? poly : 0) + (j->fourstep ? poly * (j->op == NTT_REQ_POLYMUL ? 2 : 1) : 0);
+  // products: an operand copy (LDS sizes) or the two column-pass outputs
+  // (four-step sizes); transforms: the four-step intermediate
+  j->ws_bytes = j->op == NTT_REQ_POLYMUL ? poly * (j->fourstep ? 2 : 1) : (j->fourstep ? poly : 0);
   int rc = NTT_OK;
   // simulate mode validates here; otherwise the pool validates a modulus the
   // first time it sees (q, N) and later submits only look the tables up

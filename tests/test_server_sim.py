@@ -50,8 +50,8 @@ def test_overlapping_batches_use_several_streams(ntt):
 def test_budget_admission_and_rejection(ntt):
     N, L = 1 << 16, 4
     poly = L * N * 8
-    # a POLYMUL at N = 2^16 holds an operand copy + two four-step scratch copies
-    budget = 3 * poly
+    # a POLYMUL at N = 2^16 holds the column-pass outputs of both operands
+    budget = 2 * poly
     with sim(ntt, hbm_budget_bytes=budget, n_streams=4, simulate_ns_per_item=50000.0) as s:
         with pytest.raises(ntt.NttError) as e:
             s.submit(ntt.NTT_REQ_POLYMUL, N, P18[:L + 1], FAKE, FAKE, b=FAKE)   # > budget
