@@ -232,15 +232,22 @@ int ntt_tune_load(const char* path) {
   fclose(f);
   const size_t ap = text.find("\"arch\"");
   if (ap == std::string::npos) return NTT_ERR_ARG;
-  const size_t q1 = text.find('"', text.find(':', ap) + 1), q2 = text.find('"', q1 + 1);
-  if (q1 == std::string::npos || q2 == std::string::npos) return NTT_ERR_ARG;
+  const size_t colon = text.find(':', ap);
+  if (colon == std::string::npos) return NTT_ERR_ARG;
+  const size_t q1 = text.find('"', colon + 1);
+  if (q1 == std::string::npos) return NTT_ERR_ARG;
+  const size_t q2 = text.find('"', q1 + 1);
+  if (q2 == std::string::npos) return NTT_ERR_ARG;
   if (text.substr(q1 + 1, q2 - q1 - 1) != arch_name()) return NTT_ERR_STATE;
   auto field = [&](size_t from, size_t to, const char* name, double* v) {
     const std::string key = std::string("\"") + name + "\"";
     const size_t k = text.find(key, from);
     if (k == std::string::npos || k > to) return false;
-    *v = strtod(text.c_str() + text.find(':', k) + 1, nullptr);
-    return true;
+    const size_t c = text.find(':', k);
+    if (c == std::string::npos || c > to) return false;
+    char* end = nullptr;
+    *v = strtod(text.c_str() + c + 1, &end);
+    return end != text.c_str() + c + 1;
   };
   size_t pos = text.find('[', q2);
   int count = 0;
@@ -248,8 +255,13 @@ int ntt_tune_load(const char* path) {
     const size_t b = text.find('{', pos), e = text.find('}', b == std::string::npos ? pos : b);
     if (b == std::string::npos || e == std::string::npos) break;
     double w, lg, il, pa, n1, ex, us;
+    // every field present and in range before any conversion to int (a
+    // damaged file then loses entries instead of reaching undefined casts)
+    auto in = [](double v, double lo, double hi) { return v >= lo && v <= hi; };
     if (field(b, e, "word", &w) && field(b, e, "log_n", &lg) && field(b, e, "items_log2", &il) &&
-        field(b, e, "path", &pa) && field(b, e, "log_n1", &n1) && field(b, e, "exact", &ex) && field(b, e, "us", &us)) {
+        field(b, e, "path", &pa) && field(b, e, "log_n1", &n1) && field(b, e, "exact", &ex) &&
+        field(b, e, "us", &us) && (w == 32 || w == 64) && in(lg, 1, 17) && in(il, 0, 40) &&
+        in(pa, NTT_PATH_TINY, NTT_PATH_FOURSTEP) && in(n1, 0, 9) && in(ex, 0, 1) && in(us, 0, 1e9)) {
       std::lock_guard<std::mutex> g(g_mu);
       g_table[TKey{(int)w, (int)lg, (int)il}] = TVal{(int)pa, (int)n1, (int)ex, (float)us};
       ++count;

@@ -106,3 +106,70 @@ def test_bconv_argument_validation(lib):
     for args, code in cases:
         assert lib.ntt_bconv_create(*args) is None
         assert lib.ntt_last_error() == code, (args, lib.ntt_last_error())
+
+
+def _local_table(tmp_path):
+    """The shipped gfx950 tuning table, relabelled with this machine's arch so the loader parses it."""
+    import paper_2405_11353_amd as ntt
+    f = tmp_path / "arch.json"
+    ntt.ntt_tune_clear()
+    ntt.ntt_tune_save(str(f))
+    arch = f.read_text().split('"arch": "')[1].split('"')[0]
+    src = open(os.path.join(ROOT, "paper_2405_11353_amd", "tune_gfx950.json")).read()
+    return src.replace('"arch": "gfx950"', '"arch": "%s"' % arch)
+
+
+def test_tune_load_rejects_out_of_range_fields(lib, tmp_path):
+    import paper_2405_11353_amd as ntt
+    good = _local_table(tmp_path)
+    f = tmp_path / "t.json"
+    f.write_text(good)
+    ntt.ntt_tune_load(str(f))
+    entry = '{"word": 64, "log_n": 16, "items_log2": 6, "path": 3, "log_n1": 8, "exact": 0, "us": 12.5}'
+    head = good.split('"entries"')[0] + '"entries": ['
+    bad = [("64", "48"), ('"log_n": 16', '"log_n": 40'), ('"log_n": 16', '"log_n": -1'),
+           ('"items_log2": 6', '"items_log2": 1e300'), ('"path": 3', '"path": 9'),
+           ('"log_n1": 8', '"log_n1": 12'), ('"exact": 0', '"exact": 2'), ('12.5', 'nan'),
+           ('12.5', '-3'), ('"us": 12.5', '"us" 12.5'), ('"log_n": 16', '"log_n": x')]
+    for old, new in bad:
+        f.write_text(head + entry.replace(old, new, 1) + "]}")
+        with pytest.raises(ntt.NttError):
+            ntt.ntt_tune_load(str(f))
+    for broken in ['{"arch": ', '{"arch"', '{"arch": "x', '']:
+        f.write_text(broken)
+        with pytest.raises(ntt.NttError):
+            ntt.ntt_tune_load(str(f))
+    ntt.ntt_tune_clear()
+
+
+def test_tune_load_survives_damaged_tables(lib, tmp_path):
+    """Truncated, byte-flipped and spliced copies of a valid table either load or
+    raise; none may crash the loader."""
+    import paper_2405_11353_amd as ntt
+    good = _local_table(tmp_path).encode()
+    f = tmp_path / "t.json"
+    rng = si.Stream(2024)
+    loaded = rejected = 0
+    for it in range(400):
+        v = bytearray(good)
+        pos = [rng.uniform_int(0, len(v) - 1) for _ in range(8)]
+        kind = it % 4
+        if kind == 0:
+            del v[pos[0]:]
+        elif kind == 1:
+            for p, b in zip(pos[:4], pos[4:]):
+                v[p] = b & 0xFF
+        elif kind == 2:
+            for p, b in zip(pos[:4], pos[4:]):
+                v[p] = b'{}[],:"0123456789-eE.x '[b % 23]
+        else:
+            a, b = sorted(pos[:2])
+            del v[a:b]
+        f.write_bytes(bytes(v))
+        try:
+            ntt.ntt_tune_load(str(f))
+            loaded += 1
+        except ntt.NttError:
+            rejected += 1
+        ntt.ntt_tune_clear()
+    assert loaded + rejected == 400 and loaded > 0 and rejected > 0
