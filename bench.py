@@ -422,10 +422,11 @@ def bench_polymul(ntt, si, torch, steps=100, warm=10):
 
 def bench_ablations(ntt, si, torch, steps=60, warm=5):
     """The headline step (2 ciphertexts, N = 2^16, 24 limbs, one stream) with one
-    design choice changed at a time: the four-step split N1 x N2, the exact
-    quotient of the 64-bit Shoup product instead of the approximate one, the
-    pointwise product as its own pass instead of fused into the first inverse
-    pass, and the LDS-resident path forced off (it cannot hold 2^16 points).
+    design choice changed at a time: the row pass with the merged per-row
+    twiddles instead of the twisted one, the four-step split N1 x N2, the
+    exact quotient of the 64-bit Shoup product instead of the approximate one,
+    and the pointwise product as its own pass instead of fused into the first
+    inverse pass.
     Each variant is checked: forward then inverse returns the input."""
     w = si.workload_polymul_n16()
     N, moduli, L = w.N, w.moduli, len(w.moduli)
@@ -462,17 +463,22 @@ def bench_ablations(ntt, si, torch, steps=60, warm=5):
         return e0.elapsed_time(e1) / steps * 1e3
 
     rows = []
-    for name, log_n1, exact, fused in [("default: split 2^8 x 2^8, approximate quotient, fused product", 8, False, True),
-                                       ("split 2^7 x 2^9", 7, False, True),
-                                       ("split 2^9 x 2^7", 9, False, True),
-                                       ("exact quotient", 8, True, True),
-                                       ("separate pointwise pass", 8, False, False)]:
+    for name, log_n1, exact, fused, twist in [
+            ("default: split 2^8 x 2^8, approximate quotient, fused product, twisted inverse rows", 8, False, True,
+             ntt.NTT_ROW_TWIST_INV),
+            ("merged-twiddle row passes", 8, False, True, 0),
+            ("twisted row passes in both directions", 8, False, True, ntt.NTT_ROW_TWIST_FWD | ntt.NTT_ROW_TWIST_INV),
+            ("split 2^7 x 2^9", 7, False, True, ntt.NTT_ROW_TWIST_INV),
+            ("split 2^9 x 2^7", 9, False, True, ntt.NTT_ROW_TWIST_INV),
+            ("exact quotient", 8, True, True, ntt.NTT_ROW_TWIST_INV),
+            ("separate pointwise pass", 8, False, False, ntt.NTT_ROW_TWIST_INV)]:
         plan = ntt.Plan(N, moduli)
         plan.set_variant(ntt.NTT_PATH_FOURSTEP, log_n1)
         plan.set_exact_quotient(exact)
+        plan.set_row_twist(twist)
         us = run(plan, fused)
         rows.append({"variant": name, "log_n1": log_n1, "exact_quotient": exact, "fused_product": fused,
-                     "us_per_step": round(us, 1), "ntt_per_s": round(144 / (us * 1e-6), 1)})
+                     "row_twist_mask": twist, "us_per_step": round(us, 1), "ntt_per_s": round(144 / (us * 1e-6), 1)})
         log(f"ablation {name}: {us:.1f} us/step")
         plan.close()
     return {"workload": w.name, "streams": 1, "rows": rows}

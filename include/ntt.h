@@ -156,6 +156,30 @@ int ntt_plan_set_variant(ntt_plan* plan, int path, int log_n1);
  * available on NTT_PATH_FOURSTEP only; kept for measurement. */
 int ntt_plan_set_quotient(ntt_plan* plan, int exact);
 
+/* Row passes of NTT_PATH_FOURSTEP; every setting computes the same transform
+ * (the negacyclic NTT of Sec. 2, or the cyclic one of NTT_CYCLIC plans).
+ * A twisted row pass: after the column stages, row r of the N1 x N2 matrix
+ * is the residue of the input modulo x^N2 - b_r^N2, with b_r = psi^(2 brv(r)
+ * + 1) (omega^brv(r) for cyclic plans). The forward row pass multiplies
+ * element j by b_r^j and runs a cyclic NTT of length N2 whose twiddles are the
+ * same for every row and are kept in LDS; the inverse runs the cyclic inverse
+ * and then multiplies by b_r^-j. Its tables (2 N + 2 N2 twiddle entries per
+ * limb and split) are built on the first call that needs them. A merged row
+ * pass runs the row stages of the merged-twiddle transform, whose twiddles
+ * differ from row to row and are read from global memory.
+ * mask: NTT_ROW_TWIST_FWD and/or NTT_ROW_TWIST_INV select the twisted form
+ * for that direction, the rest are merged; the default is NTT_ROW_TWIST_INV
+ * (the faster setting on MI355X). Applies to ntt_forward, ntt_inverse,
+ * ntt_pointwise_mul_inverse and their _stage forms; a stage run in one setting
+ * composes with the other stage run in another (the forward intermediate is
+ * the same column pass output, and the inverse intermediates agree modulo q
+ * within the range the column pass accepts). ntt_polymul, batches and the
+ * server use the merged form. Returns NTT_ERR_ARG for other mask bits. Not
+ * safe while other threads use the plan. */
+#define NTT_ROW_TWIST_FWD 1
+#define NTT_ROW_TWIST_INV 2
+int ntt_plan_set_row_twist(ntt_plan* plan, int mask);
+
 /* Scratch a natural-order four-step call of `batch` polynomials needs (bytes;
  * 0 when the chosen variant works in place). The plan allocates it. */
 size_t ntt_workspace_bytes(const ntt_plan* plan, uint32_t batch);

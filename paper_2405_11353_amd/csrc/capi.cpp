@@ -77,6 +77,8 @@ static void release(ntt_plan* p) {
   if (p->d_tw_inv) (void)hipFree(p->d_tw_inv);
   if (p->d_mod) (void)hipFree(p->d_mod);
   if (p->d_paper) (void)hipFree(p->d_paper);
+  for (void* t : p->d_rowtw)
+    if (t) (void)hipFree(t);
   (void)hipSetDevice(cur);
   delete p;
 }
@@ -235,6 +237,12 @@ int ntt_plan_set_quotient(ntt_plan* p, int exact) {
   return NTT_OK;
 }
 
+int ntt_plan_set_row_twist(ntt_plan* p, int mask) {
+  if (!p || (mask & ~(NTT_ROW_TWIST_FWD | NTT_ROW_TWIST_INV))) return NTT_ERR_ARG;
+  p->row_twist = mask;
+  return NTT_OK;
+}
+
 size_t ntt_workspace_bytes(const ntt_plan* p, uint32_t batch) {
   if (!p || batch == 0 || (p->flags & NTT_ORDER_BITREV)) return 0;
   int path, n1, ex;
@@ -313,6 +321,47 @@ static int paper_tables(ntt_plan* p) {
 
 static int get_scratch(ntt_plan* p, void* stream, size_t bytes, void** out);
 
+// tables of the twisted row pass for the split N1 = 2^logN1, built and
+// uploaded on first use: [L][N] twist forward, [L][N] twist inverse, then
+// [L][N2] cyclic twiddles forward and inverse. Sets the launch's pointers for
+// the direction being run.
+static int row_tables(ntt_plan* p, int logN1, bool fwd, nttk::Launch* c) {
+  if (logN1 < 0 || logN1 >= (int)(sizeof p->d_rowtw / sizeof p->d_rowtw[0])) return NTT_ERR_UNSUPPORTED;
+  const uint32_t N = p->N, logN2 = p->logN - (uint32_t)logN1, N2 = 1u << logN2, L = p->L;
+  const size_t eb = nttp::tw_entry_bytes(p->word);
+  const size_t twist_bytes = (size_t)N * eb, cyc_bytes = (size_t)N2 * eb;
+  {
+    std::lock_guard<std::mutex> g(p->mu);
+    if (!p->d_rowtw[logN1]) {
+      const bool cyclic = (p->flags & NTT_CYCLIC) != 0;
+      std::vector<unsigned char> host(2 * L * (twist_bytes + cyc_bytes));
+      unsigned char* tf = host.data();
+      unsigned char* ti = tf + L * twist_bytes;
+      unsigned char* cf = ti + L * twist_bytes;
+      unsigned char* ci = cf + L * cyc_bytes;
+      for (uint32_t l = 0; l < L; ++l) {
+        const uint64_t q = p->moduli[l], root = p->psi[l];
+        nttp::twist(q, root, p->logN, (uint32_t)logN1, p->word, false, cyclic, tf + l * twist_bytes);
+        nttp::twist(q, root, p->logN, (uint32_t)logN1, p->word, true, cyclic, ti + l * twist_bytes);
+        const uint64_t w2 = nttp::row_root(q, root, (uint32_t)logN1, cyclic);
+        nttp::twiddles(q, w2, logN2, p->word, false, cf + l * cyc_bytes, true);
+        nttp::twiddles(q, w2, logN2, p->word, true, ci + l * cyc_bytes, true);
+      }
+      void* d = nullptr;
+      if (hipMalloc(&d, host.size()) != hipSuccess) return NTT_ERR_NOMEM;
+      if (hipMemcpy(d, host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(d);
+        return NTT_ERR_HIP;
+      }
+      p->d_rowtw[logN1] = d;
+    }
+  }
+  const unsigned char* base = (const unsigned char*)p->d_rowtw[logN1];
+  c->twist = base + (fwd ? 0 : L * twist_bytes);
+  c->cyc = base + 2 * L * twist_bytes + (fwd ? 0 : L * cyc_bytes);
+  return NTT_OK;
+}
+
 static int run_paper(ntt_plan* p, void* data, uint32_t batch, void* stream, bool fwd, int path) {
   int rc = paper_tables(p);
   if (rc != NTT_OK) return rc;
@@ -377,6 +426,9 @@ static int run_ntt(const ntt_plan* pc, void* data, uint32_t batch, void* stream,
     rc = get_scratch(p, stream, ntt_workspace_bytes(p, batch), &c.scratch);
     if (rc != NTT_OK) return rc;
   }
+  if (c.path == nttk::PATH_TWO && (p->row_twist & (fwd ? NTT_ROW_TWIST_FWD : NTT_ROW_TWIST_INV)) &&
+      (rc = row_tables(p, logN1, fwd, &c)) != NTT_OK)
+    return rc;
   const hipError_t e = nttk::launch_ntt(c, fwd);
   if (e == hipErrorNotSupported) return NTT_ERR_UNSUPPORTED;
   return e == hipSuccess ? NTT_OK : NTT_ERR_HIP;
@@ -447,6 +499,7 @@ static int run_mul_inverse(const ntt_plan* pc, const void* a, const void* b, voi
     rc = get_scratch(p, stream, ntt_workspace_bytes(p, batch), &L.scratch);
     if (rc != NTT_OK) return rc;
   }
+  if ((p->row_twist & NTT_ROW_TWIST_INV) && (rc = row_tables(p, logN1, false, &L)) != NTT_OK) return rc;
   const hipError_t e = nttk::launch_ntt(L, false);
   if (e == hipErrorNotSupported) return NTT_ERR_UNSUPPORTED;
   return e == hipSuccess ? NTT_OK : NTT_ERR_HIP;

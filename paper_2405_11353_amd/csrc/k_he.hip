@@ -35,7 +35,7 @@ hipError_t launch_tensor(int word, const void* a, const void* b, void* d, const 
                          uint32_t logN, uint32_t batch, hipStream_t s) {
   const size_t total = ((size_t)L << logN) * batch;
   int dev = 0, cus = 256;
-  if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   const size_t want = (total + 255) / 256, cap = (size_t)cus * 16;
   const dim3 grid((unsigned)(want < cap ? want : cap)), block(256);
   if (word == 32)

@@ -8,7 +8,7 @@ hipError_t launch_pointwise(int word, const void* a, const void* b, void* out, c
                             uint32_t L, uint32_t logN, uint32_t items, hipStream_t s) {
   const size_t n_pairs = ((size_t)items << logN) / 2;
   int dev = 0, cus = 256;
-  if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   const size_t want = (n_pairs + 255) / 256;
   const size_t cap = (size_t)cus * 16;
   const dim3 grid((unsigned)(want < cap ? (want ? want : 1) : cap)), block(256);

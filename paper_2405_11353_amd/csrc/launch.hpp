@@ -40,6 +40,10 @@ struct Launch {
   int stage_mask = 3;       // PATH_TWO: bit 0 runs the first kernel, bit 1 the second
   const void* mul_a = nullptr;  // PATH_TWO inverse: if set, transform mul_a * mul_b into data
   const void* mul_b = nullptr;
+  // PATH_TWO: if set, the row pass is the twisted one (k_row_tw) with these
+  // tables of the direction being run: [L][N] twist, [L][N2] cyclic twiddles
+  const void* twist = nullptr;
+  const void* cyc = nullptr;
 };
 
 // Batched executor launch: items are described by a device table of ItemDesc

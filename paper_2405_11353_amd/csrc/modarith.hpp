@@ -107,6 +107,19 @@ struct Arith64 {
     x = csub(s, L);
     y = mul(d, t);
   }
+  // butterflies whose twiddle is 1 (group 0 of a cyclic transform): both
+  // inputs are reduced instead of multiplied, same ranges as ct / gs
+  NTT_HD void ct1(uint64_t& x, uint64_t& y) const {
+    uint64_t xr = csub(x, L), yr = csub(y, L);
+    x = xr + yr;
+    y = xr + L - yr;
+  }
+  NTT_HD void gs1(uint64_t& x, uint64_t& y) const {
+    uint64_t s = x + y;
+    uint64_t d = x + L - y;
+    x = csub(s, L);
+    y = csub(d, L);
+  }
   // last inverse stage: both outputs scaled (N^-1 folded into two twiddles)
   NTT_HD void gs_last(uint64_t& x, uint64_t& y, const Tw64& t0, const Tw64& t1) const {
     uint64_t s = x + y;
@@ -194,6 +207,17 @@ struct Arith32 {
     uint32_t d = x + L - y;
     x = csub(s, L);
     y = mul(d, t);
+  }
+  NTT_HD void ct1(uint32_t& x, uint32_t& y) const {
+    uint32_t xr = csub(x, L), yr = csub(y, L);
+    x = xr + yr;
+    y = xr + L - yr;
+  }
+  NTT_HD void gs1(uint32_t& x, uint32_t& y) const {
+    uint32_t s = x + y;
+    uint32_t d = x + L - y;
+    x = csub(s, L);
+    y = csub(d, L);
   }
   NTT_HD void gs_last(uint32_t& x, uint32_t& y, const Tw32& t0, const Tw32& t1) const {
     uint32_t s = x + y;

@@ -273,11 +273,15 @@ __device__ __forceinline__ void st_data(T* p, T v) {
 // each row segment read or written is NC words (128 bytes).
 // Forward: global stages [0, logN1), out-of-place allowed (in == out is fine).
 // Inverse: global stages [logN1-1 .. 0] with the N^-1 fold, canonical output.
-template <class A, int LOGN1, int NC, bool FWD, bool IND = false>
+// TWIST (forward, contiguous layout): the output element (row k, column j) is
+// multiplied by twist[l][k * N2 + j] before the store, for the twisted row pass
+// that follows (k_row_tw); its loads overlap the last phase.
+template <class A, int LOGN1, int NC, bool FWD, bool IND = false, bool TWIST = false>
 __global__ void __launch_bounds__(NC << (LOGN1 - 4))
 k_col(const typename A::word* in, typename A::word* out, const typename A::tw_t* __restrict__ tw_all,
       const typename ModOf<A>::type* __restrict__ mods, uint32_t L, uint32_t logN, uint32_t items,
-      const ItemDesc* __restrict__ desc = nullptr, int io = 0) {
+      const ItemDesc* __restrict__ desc = nullptr, int io = 0,
+      const typename A::tw_t* __restrict__ twist_all = nullptr) {
   using W = typename A::word;
   using TW = typename A::tw_t;
   using M = typename ModOf<A>::type;
@@ -311,6 +315,11 @@ k_col(const typename A::word* in, typename A::word* out, const typename A::tw_t*
     src = in + base;
     dst = out + base;
   }
+  const TW* twist = nullptr;
+  if constexpr (TWIST) {
+    static_assert(FWD && !IND, "the twist applies to the contiguous forward pass");
+    twist = twist_all + ((size_t)(item % L) << logN) + off;
+  }
   W v[16];
   if constexpr (FWD) {
 #pragma unroll
@@ -328,7 +337,12 @@ k_col(const typename A::word* in, typename A::word* out, const typename A::tw_t*
       ct_phase<A, S::rs(p)>(a, v, tw, S::s0(p), grp<LOGN1>(p, t));
     });
 #pragma unroll
-    for (int i = 0; i < 16; ++i) st_data<NT_ST_MID>(dst + (size_t)pos<LOGN1>(S::NPH - 1, t, i) * N2, v[i]);
+    for (int i = 0; i < 16; ++i) {
+      const size_t e = (size_t)pos<LOGN1>(S::NPH - 1, t, i) * N2;
+      W o = v[i];
+      if constexpr (TWIST) o = a.mul(o, twist[e]);
+      st_data<NT_ST_MID>(dst + e, o);
+    }
   } else {
 #pragma unroll
     for (int i = 0; i < 16; ++i) v[i] = ld_data<NT_LD_MID>(src + (size_t)pos<LOGN1>(S::NPH - 1, t, i) * N2);
@@ -482,6 +496,188 @@ k_row(const typename A::word* in, typename A::word* out, const typename A::tw_t*
     W* dst = out + pbase + (size_t)r * N2;
 #pragma unroll
     for (int i = 0; i < 16; ++i) st_data<NT_ST_MID>(dst + i * TPR + t, v[i]);
+  }
+}
+
+// ============================================================ twisted row pass
+// The rows of k_row by another factorisation. After the column stages, row r
+// holds the input reduced modulo x^N2 - beta_r^N2 with beta_r =
+// psi^(2 brv(r) + 1), and its outputs are the values at beta_r * omega^brv(c),
+// omega = psi^(2 N1). So the row is multiplied elementwise by beta_r^j (the
+// twist: one table entry per element, read together with the data) and then
+// transformed by a cyclic NTT of length N2 whose twiddles are the same for
+// every row. Those N2 entries are staged once per workgroup in LDS, so no
+// twiddle is fetched from global memory between butterflies (the merged-
+// twiddle row pass reads a different subtree of twiddles for every row, too
+// many for LDS). In the first phase every group 0 has twiddle 1 and takes the
+// unit butterfly, which pays for the twist's products.
+// Tables: twist[l][N], entry r * N2 + j = beta_r^j (forward) or beta_r^-j
+// (inverse); cyc[l][N2], the cyclic table of length N2 for omega (forward) or
+// its inverse (slots 0 and 1 are never read). The inverse runs the cyclic
+// inverse and multiplies by beta_r^-j before the store; the factor N^-1 stays
+// with the column pass.
+template <class A, int RS, bool FIRST>
+__device__ __forceinline__ void ct_phase_cyc(const A& a, typename A::word (&v)[16], const typename A::tw_t* tw,
+                                             uint32_t S0, uint32_t Hg) {
+#pragma unroll
+  for (int k = 0; k < RS; ++k) {
+#pragma unroll
+    for (int j = 0; j < (1 << k); ++j) {
+      if (FIRST && j == 0) {
+#pragma unroll
+        for (int m = 0; m < (8 >> k); ++m) a.ct1(v[m], v[m + (8 >> k)]);
+      } else {
+        const typename A::tw_t w = tw[(1u << (S0 + k)) + (Hg << k) + j];
+#pragma unroll
+        for (int m = 0; m < (8 >> k); ++m) {
+          const int i0 = j * (16 >> k) + m;
+          a.ct(v[i0], v[i0 + (8 >> k)], w);
+        }
+      }
+    }
+  }
+}
+template <class A, int RS, bool FIRST>
+__device__ __forceinline__ void gs_phase_cyc(const A& a, typename A::word (&v)[16], const typename A::tw_t* tw,
+                                             uint32_t S0, uint32_t Hg) {
+#pragma unroll
+  for (int k = RS - 1; k >= 0; --k) {
+#pragma unroll
+    for (int j = 0; j < (1 << k); ++j) {
+      if (FIRST && j == 0) {
+#pragma unroll
+        for (int m = 0; m < (8 >> k); ++m) a.gs1(v[m], v[m + (8 >> k)]);
+      } else {
+        const typename A::tw_t w = tw[(1u << (S0 + k)) + (Hg << k) + j];
+#pragma unroll
+        for (int m = 0; m < (8 >> k); ++m) {
+          const int i0 = j * (16 >> k) + m;
+          a.gs(v[i0], v[i0 + (8 >> k)], w);
+        }
+      }
+    }
+  }
+}
+
+// ROWTWIST (forward): the row pass multiplies by the twist on load; otherwise
+// the column pass has already done it (k_col with TWIST).
+template <class A, int LOGN2, bool FWD, bool NATURAL, bool MULIN = false, bool ROWTWIST = false>
+__global__ void __launch_bounds__(16 << (LOGN2 - 4))
+k_row_tw(const typename A::word* in, typename A::word* out, const typename A::tw_t* __restrict__ twist_all,
+         const typename A::tw_t* __restrict__ cyc_all, const typename ModOf<A>::type* __restrict__ mods,
+         uint32_t L, uint32_t logN, uint32_t batch, const typename A::word* in2 = nullptr) {
+  using W = typename A::word;
+  using TW = typename A::tw_t;
+  using S = Sched<LOGN2>;
+  constexpr uint32_t N2 = 1u << LOGN2, TPR = N2 / 16, RSTR = N2 + N2 / 16 + 1;
+  static_assert(TPR <= 64, "a row must fit in one wavefront");
+  __shared__ W lds[16 * RSTR];
+  __shared__ TW cyc[N2];  // one entry per thread of the workgroup
+  const uint32_t logN1 = logN - LOGN2, N1 = 1u << logN1;
+  const uint32_t tiles = N1 / 16;
+  const uint32_t bid = xcd_remap(blockIdx.x, gridDim.x);
+  const uint32_t b = bid % batch, rest = bid / batch;
+  const uint32_t tile = rest % tiles, l = rest / tiles;
+  if (l >= L) return;  // whole workgroup leaves together
+  const uint32_t item = b * L + l;
+  const uint32_t t = threadIdx.x % TPR, rl = threadIdx.x / TPR;
+  const uint32_t k1 = tile * 16 + rl;
+  const uint32_t r = NATURAL ? brv(k1, logN1) : k1;
+  A a;
+  const auto* mi = mods + l;
+  a.load(*mi);
+  const TW cyc_entry = cyc_all[((size_t)l << LOGN2) + threadIdx.x];
+  const TW* twist = (FWD && !ROWTWIST) ? nullptr : twist_all + ((size_t)l << logN) + (size_t)r * N2;
+  const size_t pbase = (size_t)item << logN;
+  W* sh = lds + rl * RSTR;
+  W v[16];
+  if constexpr (FWD) {
+    const W* src = in + pbase + (size_t)r * N2;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = ld_data<NT_LD_MID>(src + i * TPR + t);
+    cyc[threadIdx.x] = cyc_entry;
+    __syncthreads();
+    if constexpr (ROWTWIST) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) v[i] = a.mul(v[i], twist[i * TPR + t]);
+    }
+    static_for<0, S::NPH>([&](auto P_) {
+      constexpr int p = decltype(P_)::value;
+      if constexpr (p > 0) {
+        if constexpr (p > 1) wave_lds_sync();
+#pragma unroll
+        for (int i = 0; i < 16; ++i) sh[pad16(pos<LOGN2>(p - 1, t, i))] = v[i];
+        wave_lds_sync();
+#pragma unroll
+        for (int i = 0; i < 16; ++i) v[i] = sh[pad16(pos<LOGN2>(p, t, i))];
+      }
+      ct_phase_cyc<A, S::rs(p), p == 0>(a, v, cyc, S::s0(p), grp<LOGN2>(p, t));
+    });
+    if constexpr (NATURAL) {
+      if (S::NPH > 1) wave_lds_sync();
+#pragma unroll
+      for (int i = 0; i < 16; ++i) sh[pad16(pos<LOGN2>(S::NPH - 1, t, i))] = a.canon_fwd(v[i]);
+      __syncthreads();
+      const uint32_t rr = threadIdx.x % 16, cg = threadIdx.x / 16;
+      W* dst = out + pbase + tile * 16 + rr;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const uint32_t cc = cg + TPR * j;
+        st_data<NT_ST_OUT>(dst + (size_t)brv(cc, LOGN2) * N1, lds[rr * RSTR + pad16(cc)]);
+      }
+    } else {
+      if (S::NPH > 1) wave_lds_sync();
+#pragma unroll
+      for (int i = 0; i < 16; ++i) sh[pad16(pos<LOGN2>(S::NPH - 1, t, i))] = a.canon_fwd(v[i]);
+      wave_lds_sync();
+      W* dst = out + pbase + (size_t)r * N2;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) st_data<NT_ST_OUT>(dst + i * TPR + t, sh[pad16(i * TPR + t)]);
+    }
+  } else {
+    cyc[threadIdx.x] = cyc_entry;
+    if constexpr (NATURAL) {
+      const uint32_t rr = threadIdx.x % 16, cg = threadIdx.x / 16;
+      const size_t off = pbase + tile * 16 + rr;
+      const W* src = in + off;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const uint32_t cc = cg + TPR * j;
+        const size_t e = (size_t)brv(cc, LOGN2) * N1;
+        W val = ld_data<NT_LD_IN>(src + e);
+        if constexpr (MULIN) val = mulmod_general(val, ld_data<NT_LD_IN>(in2 + off + e), *mi);
+        lds[rr * RSTR + pad16(cc)] = val;
+      }
+      __syncthreads();
+    } else {
+      const size_t off = pbase + (size_t)r * N2;
+      const W* src = in + off;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        W val = ld_data<NT_LD_IN>(src + i * TPR + t);
+        if constexpr (MULIN) val = mulmod_general(val, ld_data<NT_LD_IN>(in2 + off + i * TPR + t), *mi);
+        sh[pad16(i * TPR + t)] = val;
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = sh[pad16(pos<LOGN2>(S::NPH - 1, t, i))];
+    static_for_down<S::NPH - 1, 0>([&](auto P_) {
+      constexpr int p = decltype(P_)::value;
+      if constexpr (p < S::NPH - 1) {
+        wave_lds_sync();
+#pragma unroll
+        for (int i = 0; i < 16; ++i) sh[pad16(pos<LOGN2>(p + 1, t, i))] = v[i];
+        wave_lds_sync();
+#pragma unroll
+        for (int i = 0; i < 16; ++i) v[i] = sh[pad16(pos<LOGN2>(p, t, i))];
+      }
+      gs_phase_cyc<A, S::rs(p), p == 0>(a, v, cyc, S::s0(p), grp<LOGN2>(p, t));
+    });
+    // first-phase layout: value i of thread t is row element i * TPR + t
+    W* dst = out + pbase + (size_t)r * N2;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) st_data<NT_ST_MID>(dst + i * TPR + t, a.mul(v[i], twist[i * TPR + t]));
   }
 }
 

@@ -32,6 +32,10 @@ struct ntt_plan {
   std::vector<ScratchSlot> scratch;
   // tables of the paper's algorithm variants (cyclic plans), built on first use
   void* d_paper = nullptr;  // [L][N/2] forward, [L][N/2] inverse, [L] N^-1
+  // tables of the twisted row pass per split log2(N1), built on first use:
+  // [L][N] twist forward, [L][N] twist inverse, [L][N2] cyclic forward and inverse
+  void* d_rowtw[10] = {};
+  int row_twist = NTT_ROW_TWIST_INV;  // directions whose four-step row pass is twisted
 };
 
 namespace ntti {

@@ -102,6 +102,37 @@ void twiddles(uint64_t q, uint64_t root, uint32_t logN, int word, bool inverse, 
   }
 }
 
+static void put_entry(uint64_t w, uint64_t q, int word, void* out, size_t k) {
+  if (word == 32) {
+    uint32_t* o = (uint32_t*)out + 2 * k;
+    o[0] = (uint32_t)w;
+    o[1] = (uint32_t)(((uint64_t)w << 32) / q);
+  } else {
+    uint64_t* o = (uint64_t*)out + 2 * k;
+    o[0] = w;
+    o[1] = (uint64_t)(((u128)w << 64) / q);
+  }
+}
+
+void twist(uint64_t q, uint64_t root, uint32_t logN, uint32_t logN1, int word, bool inverse, bool cyclic, void* out) {
+  const uint32_t N = 1u << logN, N1 = 1u << logN1, N2 = N >> logN1;
+  const size_t order = cyclic ? (size_t)N : 2 * (size_t)N;
+  std::vector<uint64_t> pw(order);
+  pw[0] = 1;
+  for (size_t e = 1; e < order; ++e) pw[e] = mulmod(pw[e - 1], root, q);
+  for (uint32_t r = 0; r < N1; ++r) {
+    const size_t eb = cyclic ? bitrev(r, logN1) : 2 * (size_t)bitrev(r, logN1) + 1;
+    for (uint32_t j = 0; j < N2; ++j) {
+      const size_t e = (eb * j) % order;
+      put_entry(pw[inverse ? (order - e) % order : e], q, word, out, (size_t)r * N2 + j);
+    }
+  }
+}
+
+uint64_t row_root(uint64_t q, uint64_t root, uint32_t logN1, bool cyclic) {
+  return powmod(root, (cyclic ? 1ull : 2ull) << logN1, q);
+}
+
 void modinfo(uint64_t q, int word, void* out) {
   if (word == 32) {
     uint32_t m[8] = {0};

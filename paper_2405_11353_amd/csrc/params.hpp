@@ -30,6 +30,16 @@ uint64_t default_omega(uint64_t q, uint32_t N);
 //  x^m -+ sqrt(z) for the group's z; the inverse holds the inverses with the
 //  same N^-1 fold in slots 0 and 1.
 void twiddles(uint64_t q, uint64_t root, uint32_t logN, int word, bool inverse, void* out, bool cyclic = false);
+// Twist table of the twisted four-step row pass, N = N1 * N2 entries of
+// (w, Shoup companion): entry r * N2 + j holds beta_r^j (inverse: beta_r^-j)
+// with beta_r = root^(2 brv(r) + 1) for a negacyclic root of order 2N, or
+// root^brv(r) for a cyclic root of order N, brv over log2(N1) bits. Row r of
+// the matrix left by the first log2(N1) merged stages is the residue modulo
+// x^N2 - beta_r^N2, and its outputs are the values at beta_r * w2^brv(c), w2 =
+// root^(2 N1) (negacyclic) or root^N1 (cyclic), the root of row_root().
+void twist(uint64_t q, uint64_t root, uint32_t logN, uint32_t logN1, int word, bool inverse, bool cyclic, void* out);
+// the primitive N2-th root shared by every row of that factorisation
+uint64_t row_root(uint64_t q, uint64_t root, uint32_t logN1, bool cyclic);
 // per-limb constants in the layout of nttk::ModInfo64 / ModInfo32
 void modinfo(uint64_t q, int word, void* out);
 size_t tw_entry_bytes(int word);

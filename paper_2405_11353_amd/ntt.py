@@ -17,6 +17,7 @@ NTT_OK = 0
 NTT_WORD32 = 0x1
 NTT_ORDER_BITREV = 0x2
 NTT_CYCLIC = 0x4
+NTT_ROW_TWIST_FWD, NTT_ROW_TWIST_INV = 0x1, 0x2
 NTT_PATH_AUTO, NTT_PATH_TINY, NTT_PATH_LDS, NTT_PATH_FOURSTEP = 0, 1, 2, 3
 NTT_PATH_PAPER_DIT, NTT_PATH_PAPER_DIF, NTT_PATH_PAPER_PEASE, NTT_PATH_PAPER_PEASE_NC, NTT_PATH_PAPER_STOCKHAM = \
     4, 5, 6, 7, 8
@@ -112,6 +113,7 @@ def lib() -> ctypes.CDLL:
             "ntt_plan_get_variant": (i32, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
             "ntt_plan_set_variant": (i32, [vp, i32, i32]),
             "ntt_plan_set_quotient": (i32, [vp, i32]),
+            "ntt_plan_set_row_twist": (i32, [vp, i32]),
             "ntt_workspace_bytes": (sz, [vp, u32]),
             "ntt_last_error": (i32, []),
             "ntt_set_last_error": (None, [i32]),
@@ -279,6 +281,10 @@ def ntt_plan_set_variant(plan: int, path: int, log_n1: int = 0) -> None:
 
 def ntt_plan_set_quotient(plan: int, exact: bool) -> None:
     _check(lib().ntt_plan_set_quotient(plan, 1 if exact else 0), "ntt_plan_set_quotient")
+
+
+def ntt_plan_set_row_twist(plan: int, mask: int) -> None:
+    _check(lib().ntt_plan_set_row_twist(plan, int(mask)), "ntt_plan_set_row_twist")
 
 
 def ntt_workspace_bytes(plan: int, batch: int) -> int:
@@ -515,6 +521,15 @@ class Plan:
 
     def set_exact_quotient(self, exact: bool):
         ntt_plan_set_quotient(self.handle, exact)
+
+    def set_row_twist(self, mask):
+        """Directions whose four-step row pass is twisted: a mask of
+        NTT_ROW_TWIST_FWD / NTT_ROW_TWIST_INV (True: both, False: neither)."""
+        if mask is True:
+            mask = NTT_ROW_TWIST_FWD | NTT_ROW_TWIST_INV
+        elif mask is False:
+            mask = 0
+        ntt_plan_set_row_twist(self.handle, mask)
 
     def _batch(self, t, batch):
         if batch is None:

@@ -51,6 +51,28 @@ def test_cyclic_matches_oracle(ntt, word, logn, bitrev, variant):
     np.testing.assert_array_equal(from_dev(d, word).reshape(x.shape), x)
 
 
+@pytest.mark.parametrize("word,logn,logn1,bitrev", [(32, 16, 8, False), (32, 17, 9, True), (64, 12, 6, False),
+                                                   (64, 16, 8, True), (64, 16, 7, False)])
+@pytest.mark.parametrize("row_twist", [True, False])
+def test_cyclic_fourstep_row_forms(ntt, word, logn, logn1, bitrev, row_twist):
+    N = 1 << logn
+    moduli = Q32[:2] if word == 32 else P18[2:4]
+    log(f"case cyclic four-step word={word} N={N} logn1={logn1} bitrev={bitrev} row_twist={row_twist}")
+    flags = ntt.NTT_CYCLIC | (ntt.NTT_WORD32 if word == 32 else 0) | (ntt.NTT_ORDER_BITREV if bitrev else 0)
+    plan = ntt.Plan(N, moduli, flags=flags)
+    plan.set_variant(ntt.NTT_PATH_FOURSTEP, logn1)
+    plan.set_row_twist(row_twist)
+    x = si.poly_batch(logn + 3 * word, 2, moduli, N)
+    d = to_dev(x, word)
+    plan.forward(d)
+    ref = np.stack([np.stack([oracle.cyclic_forward(x[b, l], q) for l, q in enumerate(moduli)]) for b in range(2)])
+    if bitrev:
+        ref = ref[:, :, brv_perm(N)]
+    np.testing.assert_array_equal(from_dev(d, word).reshape(x.shape), ref)
+    plan.inverse(d)
+    np.testing.assert_array_equal(from_dev(d, word).reshape(x.shape), x)
+
+
 def test_cyclic_single_16k_u32_vs_direct_definition(ntt):
     # the paper's largest Table 1 size, sampled against the definition
     N, q = 16384, si.Q_SMALL

@@ -42,14 +42,17 @@ def brv_perm(N):
     return np.array([int(format(i, f"0{bits}b")[::-1], 2) if bits else 0 for i in range(N)])
 
 
-def run_roundtrip(ntt, N, moduli, batch, word=64, flags=0, variant=None, seed=1, exact=False):
-    log(f"case N={N} L={len(moduli)} batch={batch} word={word} flags={flags} variant={variant} exact={exact}")
+def run_roundtrip(ntt, N, moduli, batch, word=64, flags=0, variant=None, seed=1, exact=False, row_twist=None):
+    log(f"case N={N} L={len(moduli)} batch={batch} word={word} flags={flags} variant={variant} exact={exact} "
+        f"row_twist={row_twist}")
     x = si.poly_batch(seed, batch, moduli, N)
     plan = ntt.Plan(N, moduli, flags=flags | (ntt.NTT_WORD32 if word == 32 else 0))
     if variant is not None:
         plan.set_variant(*variant)
     if exact:
         plan.set_exact_quotient(True)
+    if row_twist is not None:
+        plan.set_row_twist(row_twist)
     assert plan.psi == [oracle.psi(q, N) for q in moduli]
     d = to_dev(x, word)
     plan.forward(d)
@@ -76,14 +79,17 @@ def test_default_path_u32(ntt, logn):
 @pytest.mark.parametrize("logn,logn1", [(12, 6), (13, 6), (13, 7), (14, 7), (14, 8), (15, 7), (15, 8),
                                         (16, 7), (16, 8), (16, 9), (17, 8), (17, 9)])
 @pytest.mark.parametrize("bitrev", [False, True])
-def test_fourstep_splits_u64(ntt, logn, logn1, bitrev):
+@pytest.mark.parametrize("row_twist", [True, False, None])
+def test_fourstep_splits_u64(ntt, logn, logn1, bitrev, row_twist):
     run_roundtrip(ntt, 1 << logn, P18[3:5], batch=2, flags=ntt.NTT_ORDER_BITREV if bitrev else 0,
-                  variant=(ntt.NTT_PATH_FOURSTEP, logn1), seed=logn * 10 + logn1)
+                  variant=(ntt.NTT_PATH_FOURSTEP, logn1), seed=logn * 10 + logn1, row_twist=row_twist)
 
 
-@pytest.mark.parametrize("logn,logn1", [(12, 6), (16, 8), (17, 8)])
-def test_fourstep_u32(ntt, logn, logn1):
-    run_roundtrip(ntt, 1 << logn, Q32[:2], batch=2, word=32, variant=(ntt.NTT_PATH_FOURSTEP, logn1), seed=7)
+@pytest.mark.parametrize("logn,logn1", [(12, 6), (14, 8), (16, 8), (17, 8), (17, 9)])
+@pytest.mark.parametrize("row_twist", [True, False])
+def test_fourstep_u32(ntt, logn, logn1, row_twist):
+    run_roundtrip(ntt, 1 << logn, Q32[:2], batch=2, word=32, variant=(ntt.NTT_PATH_FOURSTEP, logn1), seed=7,
+                  row_twist=row_twist)
 
 
 @pytest.mark.parametrize("logn", [4, 9, 12, 14])
@@ -98,9 +104,44 @@ def test_lds_path_large(ntt, logn):
 
 
 @pytest.mark.parametrize("logn", [14, 16])
-def test_exact_quotient_variant(ntt, logn):
+@pytest.mark.parametrize("row_twist", [True, False])
+def test_exact_quotient_variant(ntt, logn, row_twist):
     run_roundtrip(ntt, 1 << logn, P18[:2], batch=2, variant=(ntt.NTT_PATH_FOURSTEP, logn // 2), exact=True,
-                  seed=logn + 70)
+                  seed=logn + 70, row_twist=row_twist)
+
+
+@pytest.mark.parametrize("logn,logn1,bitrev", [(12, 6, False), (16, 8, False), (16, 8, True), (17, 9, False)])
+def test_row_forms_agree_and_stages_mix(ntt, logn, logn1, bitrev):
+    """The twisted and merged row passes give the same spectra, and a stage run
+    in one form composes with the other stage run in the other (the forward
+    intermediate is the same column pass; the inverse one is reduced by the
+    column pass either way). One plan, switched between the stages: the
+    natural-order intermediate lives in the plan's scratch."""
+    N, moduli = 1 << logn, P18[6:9]
+    log(f"case row forms N={N} logn1={logn1} bitrev={bitrev}")
+    plan = ntt.Plan(N, moduli, flags=ntt.NTT_ORDER_BITREV if bitrev else 0)
+    plan.set_variant(ntt.NTT_PATH_FOURSTEP, logn1)
+    x = si.poly_batch(logn + 400, 3, moduli, N)
+    ref = oracle_fwd(x, moduli)
+    if bitrev:
+        ref = ref[:, :, brv_perm(N)]
+    d = to_dev(x)
+    plan.set_row_twist(False)
+    plan.forward_stage(d, 0)
+    plan.set_row_twist(True)
+    plan.forward_stage(d, 1)
+    np.testing.assert_array_equal(from_dev(d).reshape(x.shape), ref)
+    plan.inverse_stage(d, 0)
+    plan.set_row_twist(False)
+    plan.inverse_stage(d, 1)
+    np.testing.assert_array_equal(from_dev(d).reshape(x.shape), x)
+    plan.forward(d)
+    np.testing.assert_array_equal(from_dev(d).reshape(x.shape), ref)
+    plan.inverse_stage(d, 0)
+    plan.set_row_twist(True)
+    plan.inverse_stage(d, 1)
+    np.testing.assert_array_equal(from_dev(d).reshape(x.shape), x)
+    plan.close()
 
 
 def test_single_ntt_u32_vs_direct(ntt):
@@ -270,6 +311,8 @@ def test_argument_errors_on_gpu(ntt):
     assert lib.ntt_pointwise_mul(plan.handle, None, t.data_ptr(), t.data_ptr(), 1, None) == -1
     with pytest.raises(ntt.NttError):
         plan.set_variant(ntt.NTT_PATH_FOURSTEP, 5)
+    with pytest.raises(ntt.NttError):
+        plan.set_row_twist(4)
 
 
 def test_stage_entry_points_compose(ntt):
@@ -293,12 +336,14 @@ def test_stage_entry_points_compose(ntt):
 @pytest.mark.parametrize("logn,bitrev,variant", [(16, False, None), (16, True, None), (15, False, None),
                                                   (12, False, None), (12, False, (3, 6)), (13, True, (3, 6)),
                                                   (17, False, None)])
-def test_fused_pointwise_inverse(ntt, logn, bitrev, variant):
+@pytest.mark.parametrize("row_twist", [True, False])
+def test_fused_pointwise_inverse(ntt, logn, bitrev, variant, row_twist):
     N, moduli = 1 << logn, P18[:3]
-    log(f"case fused pointwise+inverse N={N} bitrev={bitrev} variant={variant}")
+    log(f"case fused pointwise+inverse N={N} bitrev={bitrev} variant={variant} row_twist={row_twist}")
     plan = ntt.Plan(N, moduli, flags=ntt.NTT_ORDER_BITREV if bitrev else 0)
     if variant:
         plan.set_variant(*variant)
+    plan.set_row_twist(row_twist)
     a = si.poly_batch(31, 2, moduli, N)
     b = si.poly_batch(32, 2, moduli, N)
     da, db = to_dev(a), to_dev(b)
