@@ -170,11 +170,11 @@ int ntt_plan_set_quotient(ntt_plan* plan, int exact);
  * mask: NTT_ROW_TWIST_FWD and/or NTT_ROW_TWIST_INV select the twisted form
  * for that direction, the rest are merged; the default is NTT_ROW_TWIST_INV
  * (the faster setting on MI355X). Applies to ntt_forward, ntt_inverse,
- * ntt_pointwise_mul_inverse and their _stage forms; a stage run in one setting
- * composes with the other stage run in another (the forward intermediate is
- * the same column pass output, and the inverse intermediates agree modulo q
- * within the range the column pass accepts). ntt_polymul, batches and the
- * server use the merged form. Returns NTT_ERR_ARG for other mask bits. Not
+ * ntt_pointwise_mul_inverse and their _stage forms; a stage run in one
+ * setting composes with the other stage run in another (the forward
+ * intermediate is the same column pass output, and the inverse intermediates
+ * agree modulo q within the range the column pass accepts). ntt_polymul,
+ * batches and the server use the merged form. Returns NTT_ERR_ARG for other mask bits. Not
  * safe while other threads use the plan. */
 #define NTT_ROW_TWIST_FWD 1
 #define NTT_ROW_TWIST_INV 2

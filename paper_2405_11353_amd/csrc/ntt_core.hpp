@@ -273,15 +273,11 @@ __device__ __forceinline__ void st_data(T* p, T v) {
 // each row segment read or written is NC words (128 bytes).
 // Forward: global stages [0, logN1), out-of-place allowed (in == out is fine).
 // Inverse: global stages [logN1-1 .. 0] with the N^-1 fold, canonical output.
-// TWIST (forward, contiguous layout): the output element (row k, column j) is
-// multiplied by twist[l][k * N2 + j] before the store, for the twisted row pass
-// that follows (k_row_tw); its loads overlap the last phase.
-template <class A, int LOGN1, int NC, bool FWD, bool IND = false, bool TWIST = false>
+template <class A, int LOGN1, int NC, bool FWD, bool IND = false>
 __global__ void __launch_bounds__(NC << (LOGN1 - 4))
 k_col(const typename A::word* in, typename A::word* out, const typename A::tw_t* __restrict__ tw_all,
       const typename ModOf<A>::type* __restrict__ mods, uint32_t L, uint32_t logN, uint32_t items,
-      const ItemDesc* __restrict__ desc = nullptr, int io = 0,
-      const typename A::tw_t* __restrict__ twist_all = nullptr) {
+      const ItemDesc* __restrict__ desc = nullptr, int io = 0) {
   using W = typename A::word;
   using TW = typename A::tw_t;
   using M = typename ModOf<A>::type;
@@ -315,11 +311,6 @@ k_col(const typename A::word* in, typename A::word* out, const typename A::tw_t*
     src = in + base;
     dst = out + base;
   }
-  const TW* twist = nullptr;
-  if constexpr (TWIST) {
-    static_assert(FWD && !IND, "the twist applies to the contiguous forward pass");
-    twist = twist_all + ((size_t)(item % L) << logN) + off;
-  }
   W v[16];
   if constexpr (FWD) {
 #pragma unroll
@@ -337,12 +328,7 @@ k_col(const typename A::word* in, typename A::word* out, const typename A::tw_t*
       ct_phase<A, S::rs(p)>(a, v, tw, S::s0(p), grp<LOGN1>(p, t));
     });
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const size_t e = (size_t)pos<LOGN1>(S::NPH - 1, t, i) * N2;
-      W o = v[i];
-      if constexpr (TWIST) o = a.mul(o, twist[e]);
-      st_data<NT_ST_MID>(dst + e, o);
-    }
+    for (int i = 0; i < 16; ++i) st_data<NT_ST_MID>(dst + (size_t)pos<LOGN1>(S::NPH - 1, t, i) * N2, v[i]);
   } else {
 #pragma unroll
     for (int i = 0; i < 16; ++i) v[i] = ld_data<NT_LD_MID>(src + (size_t)pos<LOGN1>(S::NPH - 1, t, i) * N2);
@@ -504,13 +490,15 @@ k_row(const typename A::word* in, typename A::word* out, const typename A::tw_t*
 // holds the input reduced modulo x^N2 - beta_r^N2 with beta_r =
 // psi^(2 brv(r) + 1), and its outputs are the values at beta_r * omega^brv(c),
 // omega = psi^(2 N1). So the row is multiplied elementwise by beta_r^j (the
-// twist: one table entry per element, read together with the data) and then
-// transformed by a cyclic NTT of length N2 whose twiddles are the same for
-// every row. Those N2 entries are staged once per workgroup in LDS, so no
-// twiddle is fetched from global memory between butterflies (the merged-
-// twiddle row pass reads a different subtree of twiddles for every row, too
-// many for LDS). In the first phase every group 0 has twiddle 1 and takes the
-// unit butterfly, which pays for the twist's products.
+// twist: one table entry per element) and then transformed by a cyclic NTT of
+// length N2 whose twiddles are the same for every row. Those N2 entries are
+// staged once per workgroup in LDS, so no twiddle is fetched from global
+// memory between butterflies (the merged-twiddle row pass reads a different
+// subtree of twiddles for every row, too many for LDS). In the first phase
+// every group 0 has twiddle 1 and takes the unit butterfly, which pays for the
+// twist's products. The forward pass multiplies by the twist on load (those
+// loads join the data loads); the inverse multiplies by beta_r^-j before the
+// store, so its twist loads overlap the last phase.
 // Tables: twist[l][N], entry r * N2 + j = beta_r^j (forward) or beta_r^-j
 // (inverse); cyc[l][N2], the cyclic table of length N2 for omega (forward) or
 // its inverse (slots 0 and 1 are never read). The inverse runs the cyclic
@@ -559,9 +547,7 @@ __device__ __forceinline__ void gs_phase_cyc(const A& a, typename A::word (&v)[1
   }
 }
 
-// ROWTWIST (forward): the row pass multiplies by the twist on load; otherwise
-// the column pass has already done it (k_col with TWIST).
-template <class A, int LOGN2, bool FWD, bool NATURAL, bool MULIN = false, bool ROWTWIST = false>
+template <class A, int LOGN2, bool FWD, bool NATURAL, bool MULIN = false>
 __global__ void __launch_bounds__(16 << (LOGN2 - 4))
 k_row_tw(const typename A::word* in, typename A::word* out, const typename A::tw_t* __restrict__ twist_all,
          const typename A::tw_t* __restrict__ cyc_all, const typename ModOf<A>::type* __restrict__ mods,
@@ -587,7 +573,7 @@ k_row_tw(const typename A::word* in, typename A::word* out, const typename A::tw
   const auto* mi = mods + l;
   a.load(*mi);
   const TW cyc_entry = cyc_all[((size_t)l << LOGN2) + threadIdx.x];
-  const TW* twist = (FWD && !ROWTWIST) ? nullptr : twist_all + ((size_t)l << logN) + (size_t)r * N2;
+  const TW* twist = twist_all + ((size_t)l << logN) + (size_t)r * N2;
   const size_t pbase = (size_t)item << logN;
   W* sh = lds + rl * RSTR;
   W v[16];
@@ -597,10 +583,8 @@ k_row_tw(const typename A::word* in, typename A::word* out, const typename A::tw
     for (int i = 0; i < 16; ++i) v[i] = ld_data<NT_LD_MID>(src + i * TPR + t);
     cyc[threadIdx.x] = cyc_entry;
     __syncthreads();
-    if constexpr (ROWTWIST) {
 #pragma unroll
-      for (int i = 0; i < 16; ++i) v[i] = a.mul(v[i], twist[i * TPR + t]);
-    }
+    for (int i = 0; i < 16; ++i) v[i] = a.mul(v[i], twist[i * TPR + t]);
     static_for<0, S::NPH>([&](auto P_) {
       constexpr int p = decltype(P_)::value;
       if constexpr (p > 0) {

@@ -112,10 +112,10 @@ def test_exact_quotient_variant(ntt, logn, row_twist):
 
 @pytest.mark.parametrize("logn,logn1,bitrev", [(12, 6, False), (16, 8, False), (16, 8, True), (17, 9, False)])
 def test_row_forms_agree_and_stages_mix(ntt, logn, logn1, bitrev):
-    """The twisted and merged row passes give the same spectra, and a stage run
-    in one form composes with the other stage run in the other (the forward
-    intermediate is the same column pass; the inverse one is reduced by the
-    column pass either way). One plan, switched between the stages: the
+    """Every row-pass setting gives the same spectra, and a stage run in one
+    setting composes with the other stage run in another (the forward
+    intermediate is the same column pass output; the column pass reduces either
+    inverse intermediate). One plan, switched between the stages: the
     natural-order intermediate lives in the plan's scratch."""
     N, moduli = 1 << logn, P18[6:9]
     log(f"case row forms N={N} logn1={logn1} bitrev={bitrev}")
@@ -125,22 +125,19 @@ def test_row_forms_agree_and_stages_mix(ntt, logn, logn1, bitrev):
     ref = oracle_fwd(x, moduli)
     if bitrev:
         ref = ref[:, :, brv_perm(N)]
-    d = to_dev(x)
-    plan.set_row_twist(False)
-    plan.forward_stage(d, 0)
-    plan.set_row_twist(True)
-    plan.forward_stage(d, 1)
-    np.testing.assert_array_equal(from_dev(d).reshape(x.shape), ref)
-    plan.inverse_stage(d, 0)
-    plan.set_row_twist(False)
-    plan.inverse_stage(d, 1)
-    np.testing.assert_array_equal(from_dev(d).reshape(x.shape), x)
-    plan.forward(d)
-    np.testing.assert_array_equal(from_dev(d).reshape(x.shape), ref)
-    plan.inverse_stage(d, 0)
-    plan.set_row_twist(True)
-    plan.inverse_stage(d, 1)
-    np.testing.assert_array_equal(from_dev(d).reshape(x.shape), x)
+    F, I = ntt.NTT_ROW_TWIST_FWD, ntt.NTT_ROW_TWIST_INV
+    for fwd0, fwd1, inv0, inv1 in ((0, F, 0, I), (F, 0, I, 0), (F | I, F, I, 0), (0, 0, 0, I)):
+        d = to_dev(x)
+        plan.set_row_twist(fwd0)
+        plan.forward_stage(d, 0)
+        plan.set_row_twist(fwd1)
+        plan.forward_stage(d, 1)
+        np.testing.assert_array_equal(from_dev(d).reshape(x.shape), ref)
+        plan.set_row_twist(inv0)
+        plan.inverse_stage(d, 0)
+        plan.set_row_twist(inv1)
+        plan.inverse_stage(d, 1)
+        np.testing.assert_array_equal(from_dev(d).reshape(x.shape), x)
     plan.close()
 
 
