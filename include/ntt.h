@@ -163,8 +163,12 @@ int ntt_plan_set_quotient(ntt_plan* plan, int exact);
  * + 1) (omega^brv(r) for cyclic plans). The forward row pass multiplies
  * element j by b_r^j and runs a cyclic NTT of length N2 whose twiddles are the
  * same for every row and are kept in LDS; the inverse runs the cyclic inverse
- * and then multiplies by b_r^-j. Its tables (2 N + 2 N2 twiddle entries per
- * limb and split) are built on the first call that needs them. A merged row
+ * and then multiplies by b_r^-j. Its tables (N + N2 twiddle entries per limb,
+ * direction and split) are built when the plan is created, or this call or
+ * ntt_plan_set_variant selects them, for the plan's own split; a call that
+ * the tuning table sends to another split builds that split's tables on its
+ * first use (host work of about 10 ms per limb at N = 2^17, spread over up
+ * to 16 threads). A merged row
  * pass runs the row stages of the merged-twiddle transform, whose twiddles
  * differ from row to row and are read from global memory.
  * mask: NTT_ROW_TWIST_FWD and/or NTT_ROW_TWIST_INV select the twisted form

@@ -3,8 +3,11 @@
 #include <hip/hip_runtime.h>
 #include <string.h>
 
+#include <algorithm>
+#include <atomic>
 #include <mutex>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "launch.hpp"
@@ -59,12 +62,44 @@ static void select_variant(const ntt_plan* p, uint32_t items, int* path, int* lo
 }
 
 namespace ntti {
+void for_limbs(uint32_t L, const std::function<void(uint32_t)>& f) {
+  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+  const unsigned n = std::min<unsigned>(L, std::min(16u, hw));
+  std::atomic<uint32_t> next{0};
+  auto work = [&] {
+    for (uint32_t l; (l = next.fetch_add(1)) < L;) f(l);
+  };
+  std::vector<std::thread> th;
+  try {
+    for (unsigned i = 1; i < n; ++i) th.emplace_back(work);
+  } catch (...) {
+    // no more threads: the ones started and this one share the rest
+  }
+  work();
+  for (auto& t : th) t.join();
+}
+
 int check_modulus(uint64_t q, uint32_t N, int word) {
   const uint64_t qmax = word == 32 ? (1ull << 30) : (1ull << 61);
   if (q < 3 || q >= qmax || (q - 1) % (2ull * N) || !nttp::is_prime(q)) return NTT_ERR_MODULUS;
   return NTT_OK;
 }
 }  // namespace ntti
+
+static int row_tables(ntt_plan* p, int logN1, bool fwd, nttk::Launch* c);
+
+// the twisted row-pass tables of the plan's own four-step split, for the
+// directions its mask selects (calls that the autotuner sends to another
+// split build that split's tables on first use)
+static int prepare_row_tables(ntt_plan* p) {
+  if (p->path != NTT_PATH_FOURSTEP) return NTT_OK;
+  for (int dir = 0; dir < 2; ++dir) {
+    if (!(p->row_twist & (dir == 0 ? NTT_ROW_TWIST_FWD : NTT_ROW_TWIST_INV))) continue;
+    const int rc = row_tables(p, p->logN1, dir == 0, nullptr);
+    if (rc != NTT_OK) return rc;
+  }
+  return NTT_OK;
+}
 
 static void release(ntt_plan* p) {
   if (!p) return;
@@ -77,8 +112,9 @@ static void release(ntt_plan* p) {
   if (p->d_tw_inv) (void)hipFree(p->d_tw_inv);
   if (p->d_mod) (void)hipFree(p->d_mod);
   if (p->d_paper) (void)hipFree(p->d_paper);
-  for (void* t : p->d_rowtw)
-    if (t) (void)hipFree(t);
+  for (auto& dir : p->d_rowtw)
+    for (void* t : dir)
+      if (t) (void)hipFree(t);
   (void)hipSetDevice(cur);
   delete p;
 }
@@ -164,11 +200,11 @@ ntt_plan* ntt_plan_create_ex(uint32_t N, const uint64_t* moduli, uint32_t L, uin
   const size_t tw_bytes = (size_t)N * nttp::tw_entry_bytes(word);
   const size_t mod_bytes = nttp::modinfo_bytes(word);
   std::vector<unsigned char> fwd(tw_bytes * L), inv(tw_bytes * L), mod(mod_bytes * L);
-  for (uint32_t l = 0; l < L; ++l) {
+  ntti::for_limbs(L, [&](uint32_t l) {
     nttp::twiddles(moduli[l], roots[l], p->logN, word, false, fwd.data() + l * tw_bytes, cyclic);
     nttp::twiddles(moduli[l], roots[l], p->logN, word, true, inv.data() + l * tw_bytes, cyclic);
     nttp::modinfo(moduli[l], word, mod.data() + l * mod_bytes);
-  }
+  });
   if (hipMalloc(&p->d_tw_fwd, fwd.size()) != hipSuccess || hipMalloc(&p->d_tw_inv, inv.size()) != hipSuccess ||
       hipMalloc(&p->d_mod, mod.size()) != hipSuccess) {
     release(p);
@@ -180,6 +216,12 @@ ntt_plan* ntt_plan_create_ex(uint32_t N, const uint64_t* moduli, uint32_t L, uin
       hipMemcpy(p->d_mod, mod.data(), mod.size(), hipMemcpyHostToDevice) != hipSuccess) {
     release(p);
     fail(NTT_ERR_HIP);
+    return nullptr;
+  }
+  const int rc = prepare_row_tables(p);
+  if (rc != NTT_OK) {
+    release(p);
+    fail(rc);
     return nullptr;
   }
   return p;
@@ -226,7 +268,7 @@ int ntt_plan_set_variant(ntt_plan* p, int path, int log_n1) {
   p->logN1 = path == NTT_PATH_FOURSTEP ? log_n1 : 0;
   p->exact = 0;
   p->auto_variant = false;
-  return NTT_OK;
+  return prepare_row_tables(p);
 }
 
 int ntt_plan_set_quotient(ntt_plan* p, int exact) {
@@ -240,7 +282,7 @@ int ntt_plan_set_quotient(ntt_plan* p, int exact) {
 int ntt_plan_set_row_twist(ntt_plan* p, int mask) {
   if (!p || (mask & ~(NTT_ROW_TWIST_FWD | NTT_ROW_TWIST_INV))) return NTT_ERR_ARG;
   p->row_twist = mask;
-  return NTT_OK;
+  return prepare_row_tables(p);
 }
 
 size_t ntt_workspace_bytes(const ntt_plan* p, uint32_t batch) {
@@ -321,44 +363,41 @@ static int paper_tables(ntt_plan* p) {
 
 static int get_scratch(ntt_plan* p, void* stream, size_t bytes, void** out);
 
-// tables of the twisted row pass for the split N1 = 2^logN1, built and
-// uploaded on first use: [L][N] twist forward, [L][N] twist inverse, then
-// [L][N2] cyclic twiddles forward and inverse. Sets the launch's pointers for
-// the direction being run.
+// tables of the twisted row pass for one direction and the split N1 =
+// 2^logN1, built and uploaded on first use: [L][N] twist, then [L][N2] cyclic
+// twiddles. Sets the launch's pointers when c is given.
 static int row_tables(ntt_plan* p, int logN1, bool fwd, nttk::Launch* c) {
-  if (logN1 < 0 || logN1 >= (int)(sizeof p->d_rowtw / sizeof p->d_rowtw[0])) return NTT_ERR_UNSUPPORTED;
+  if (logN1 < 0 || logN1 >= (int)(sizeof p->d_rowtw[0] / sizeof p->d_rowtw[0][0])) return NTT_ERR_UNSUPPORTED;
   const uint32_t N = p->N, logN2 = p->logN - (uint32_t)logN1, N2 = 1u << logN2, L = p->L;
   const size_t eb = nttp::tw_entry_bytes(p->word);
   const size_t twist_bytes = (size_t)N * eb, cyc_bytes = (size_t)N2 * eb;
+  void*& slot = p->d_rowtw[fwd ? 0 : 1][logN1];
   {
     std::lock_guard<std::mutex> g(p->mu);
-    if (!p->d_rowtw[logN1]) {
+    if (!slot) {
       const bool cyclic = (p->flags & NTT_CYCLIC) != 0;
-      std::vector<unsigned char> host(2 * L * (twist_bytes + cyc_bytes));
-      unsigned char* tf = host.data();
-      unsigned char* ti = tf + L * twist_bytes;
-      unsigned char* cf = ti + L * twist_bytes;
-      unsigned char* ci = cf + L * cyc_bytes;
-      for (uint32_t l = 0; l < L; ++l) {
+      std::vector<unsigned char> host(L * (twist_bytes + cyc_bytes));
+      unsigned char* tt = host.data();
+      unsigned char* ct = tt + L * twist_bytes;
+      ntti::for_limbs(L, [&](uint32_t l) {
         const uint64_t q = p->moduli[l], root = p->psi[l];
-        nttp::twist(q, root, p->logN, (uint32_t)logN1, p->word, false, cyclic, tf + l * twist_bytes);
-        nttp::twist(q, root, p->logN, (uint32_t)logN1, p->word, true, cyclic, ti + l * twist_bytes);
+        nttp::twist(q, root, p->logN, (uint32_t)logN1, p->word, !fwd, cyclic, tt + l * twist_bytes);
         const uint64_t w2 = nttp::row_root(q, root, (uint32_t)logN1, cyclic);
-        nttp::twiddles(q, w2, logN2, p->word, false, cf + l * cyc_bytes, true);
-        nttp::twiddles(q, w2, logN2, p->word, true, ci + l * cyc_bytes, true);
-      }
+        nttp::twiddles(q, w2, logN2, p->word, !fwd, ct + l * cyc_bytes, true);
+      });
       void* d = nullptr;
       if (hipMalloc(&d, host.size()) != hipSuccess) return NTT_ERR_NOMEM;
       if (hipMemcpy(d, host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess) {
         (void)hipFree(d);
         return NTT_ERR_HIP;
       }
-      p->d_rowtw[logN1] = d;
+      slot = d;
     }
   }
-  const unsigned char* base = (const unsigned char*)p->d_rowtw[logN1];
-  c->twist = base + (fwd ? 0 : L * twist_bytes);
-  c->cyc = base + 2 * L * twist_bytes + (fwd ? 0 : L * cyc_bytes);
+  if (c) {
+    c->twist = slot;
+    c->cyc = (const unsigned char*)slot + L * twist_bytes;
+  }
   return NTT_OK;
 }
 

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
 #include <mutex>
 #include <vector>
 
@@ -32,9 +33,11 @@ struct ntt_plan {
   std::vector<ScratchSlot> scratch;
   // tables of the paper's algorithm variants (cyclic plans), built on first use
   void* d_paper = nullptr;  // [L][N/2] forward, [L][N/2] inverse, [L] N^-1
-  // tables of the twisted row pass per split log2(N1), built on first use:
-  // [L][N] twist forward, [L][N] twist inverse, [L][N2] cyclic forward and inverse
-  void* d_rowtw[10] = {};
+  // tables of the twisted row pass per direction (0 forward, 1 inverse) and
+  // split log2(N1): [L][N] twist, then [L][N2] cyclic twiddles. The plan's
+  // default split is built at creation for the directions its mask selects,
+  // other splits on first use.
+  void* d_rowtw[2][10] = {};
   int row_twist = NTT_ROW_TWIST_INV;  // directions whose four-step row pass is twisted
 };
 
@@ -64,5 +67,8 @@ size_t pool_bytes();
 
 // a prime q < 2^bits with q = 1 mod 2N (the largest one), for tuning runs
 uint64_t tuning_prime(uint32_t N, int word);
+
+// f(l) for every l < L, spread over up to 16 host threads (table generation)
+void for_limbs(uint32_t L, const std::function<void(uint32_t)>& f);
 
 }  // namespace ntti

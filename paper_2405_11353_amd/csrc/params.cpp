@@ -59,9 +59,65 @@ uint64_t default_omega(uint64_t q, uint32_t N) {
 }
 
 static uint32_t bitrev(uint32_t x, uint32_t bits) {
-  uint32_t r = 0;
-  for (uint32_t b = 0; b < bits; ++b) r |= ((x >> b) & 1u) << (bits - 1 - b);
-  return r;
+  if (bits == 0) return 0;
+  x = ((x >> 1) & 0x55555555u) | ((x & 0x55555555u) << 1);
+  x = ((x >> 2) & 0x33333333u) | ((x & 0x33333333u) << 2);
+  x = ((x >> 4) & 0x0F0F0F0Fu) | ((x & 0x0F0F0F0Fu) << 4);
+  x = ((x >> 8) & 0x00FF00FFu) | ((x & 0x00FF00FFu) << 8);
+  x = (x >> 16) | (x << 16);
+  return x >> (32 - bits);
+}
+
+// x * w mod q by Shoup's product with wp = floor(w * 2^64 / q): for x, w < q
+// < 2^63, x * w - hi64(x * wp) * q lies in [0, 2q).
+static inline uint64_t mul_shoup(uint64_t x, uint64_t w, uint64_t wp, uint64_t q) {
+  const uint64_t Q = (uint64_t)(((u128)x * wp) >> 64);
+  const uint64_t r = x * w - Q * q;
+  return r >= q ? r - q : r;
+}
+
+// root^0 .. root^(count-1) mod q with no division per step: eight
+// interleaved chains, each advanced by the fixed factor root^8.
+static void powers(uint64_t q, uint64_t root, size_t count, std::vector<uint64_t>& pw) {
+  pw.resize(count);
+  const uint64_t rp = (uint64_t)(((u128)root << 64) / q);
+  uint64_t x = 1 % q;
+  for (size_t e = 0; e < count && e < 8; ++e) {
+    pw[e] = x;
+    x = mul_shoup(x, root, rp, q);
+  }
+  const uint64_t r8 = x, r8p = (uint64_t)(((u128)r8 << 64) / q);  // root^8
+  for (size_t e = 8; e < count; ++e) pw[e] = mul_shoup(pw[e - 8], r8, r8p, q);
+}
+
+// Shoup companions floor(w * 2^64 / q) for w < q from v = floor((2^128 - 1) /
+// q), one division per table instead of one per entry: v > 2^128/q - 2, so
+// w * v / 2^64 > w * 2^64 / q - 2q / 2^64 > w * 2^64 / q - 1 (q < 2^63), and
+// floor(w * v / 2^64) = w * v_hi + hi64(w * v_lo) is the companion or one
+// below it; the remainder w * 2^64 - e * q says which.
+struct Recip {
+  uint64_t q, vhi, vlo;
+};
+static Recip recip(uint64_t q) {
+  const u128 v = ~(u128)0 / q;
+  return Recip{q, (uint64_t)(v >> 64), (uint64_t)v};
+}
+static uint64_t companion64(uint64_t w, const Recip& R) {
+  const uint64_t e = w * R.vhi + (uint64_t)(((u128)w * R.vlo) >> 64);
+  const u128 r = ((u128)w << 64) - (u128)e * R.q;
+  return e + (r >= R.q ? 1 : 0);
+}
+
+static void put_entry(uint64_t w, const Recip& R, int word, void* out, size_t k) {
+  if (word == 32) {
+    uint32_t* o = (uint32_t*)out + 2 * k;
+    o[0] = (uint32_t)w;
+    o[1] = (uint32_t)(((uint64_t)w << 32) / R.q);
+  } else {
+    uint64_t* o = (uint64_t*)out + 2 * k;
+    o[0] = w;
+    o[1] = companion64(w, R);
+  }
 }
 
 size_t tw_entry_bytes(int word) { return word == 32 ? 8 : 16; }
@@ -71,10 +127,10 @@ void twiddles(uint64_t q, uint64_t root, uint32_t logN, int word, bool inverse, 
   const uint32_t N = 1u << logN;
   // powers of the root; the root has order 2N (negacyclic) or N (cyclic)
   const size_t order = cyclic ? (size_t)N : 2 * (size_t)N;
-  std::vector<uint64_t> pw(order);
-  pw[0] = 1;
-  for (size_t e = 1; e < order; ++e) pw[e] = mulmod(pw[e - 1], root, q);
+  std::vector<uint64_t> pw;
+  powers(q, root, order, pw);
   const uint64_t n_inv = powmod(N % q, q - 2, q);
+  const Recip R = recip(q);
   auto exponent = [&](uint32_t k) -> size_t {  // k >= 1
     if (!cyclic) return bitrev(k, logN);
     uint32_t s = 0;
@@ -88,43 +144,23 @@ void twiddles(uint64_t q, uint64_t root, uint32_t logN, int word, bool inverse, 
     const uint64_t w = pw[(order - exponent(k)) % order];
     return k == 1 ? mulmod(w, n_inv, q) : w;
   };
-  for (uint32_t k = 0; k < N; ++k) {
-    const uint64_t w = value(k);
-    if (word == 32) {
-      uint32_t* o = (uint32_t*)out + 2 * (size_t)k;
-      o[0] = (uint32_t)w;
-      o[1] = (uint32_t)(((uint64_t)w << 32) / q);
-    } else {
-      uint64_t* o = (uint64_t*)out + 2 * (size_t)k;
-      o[0] = w;
-      o[1] = (uint64_t)(((u128)w << 64) / q);
-    }
-  }
+  for (uint32_t k = 0; k < N; ++k) put_entry(value(k), R, word, out, k);
 }
 
-static void put_entry(uint64_t w, uint64_t q, int word, void* out, size_t k) {
-  if (word == 32) {
-    uint32_t* o = (uint32_t*)out + 2 * k;
-    o[0] = (uint32_t)w;
-    o[1] = (uint32_t)(((uint64_t)w << 32) / q);
-  } else {
-    uint64_t* o = (uint64_t*)out + 2 * k;
-    o[0] = w;
-    o[1] = (uint64_t)(((u128)w << 64) / q);
-  }
-}
 
 void twist(uint64_t q, uint64_t root, uint32_t logN, uint32_t logN1, int word, bool inverse, bool cyclic, void* out) {
   const uint32_t N = 1u << logN, N1 = 1u << logN1, N2 = N >> logN1;
   const size_t order = cyclic ? (size_t)N : 2 * (size_t)N;
-  std::vector<uint64_t> pw(order);
-  pw[0] = 1;
-  for (size_t e = 1; e < order; ++e) pw[e] = mulmod(pw[e - 1], root, q);
+  std::vector<uint64_t> pw;
+  powers(q, root, order, pw);
+  const Recip R = recip(q);
   for (uint32_t r = 0; r < N1; ++r) {
     const size_t eb = cyclic ? bitrev(r, logN1) : 2 * (size_t)bitrev(r, logN1) + 1;
+    size_t e = 0;  // eb * j mod order
     for (uint32_t j = 0; j < N2; ++j) {
-      const size_t e = (eb * j) % order;
-      put_entry(pw[inverse ? (order - e) % order : e], q, word, out, (size_t)r * N2 + j);
+      put_entry(pw[inverse ? (order - e) % order : e], R, word, out, (size_t)r * N2 + j);
+      e += eb;
+      if (e >= order) e -= order;
     }
   }
 }

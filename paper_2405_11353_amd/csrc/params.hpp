@@ -2,6 +2,7 @@
 // psi, twiddle tables with Shoup companions, per-limb constants. Written
 // independently of the CPU oracle (which the library never links).
 #pragma once
+#include <stddef.h>
 #include <stdint.h>
 
 #include <vector>
