@@ -41,6 +41,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "polymul_n65536_l24_traffic.json")
 # rocprofv3 kernel names -> the names bench.py times them under
 KERNEL_KEYS = [("k_col<nttk::Arith64<false>, 8, 16, true", "fwd_col_pass"),
                ("k_row<nttk::Arith64<false>, 8, true, true", "fwd_row_pass"),
+               ("k_row_tw<nttk::Arith64<false>, 8, false, true, true", "inv_row_pass_mul"),
                ("k_row<nttk::Arith64<false>, 8, false, true, true", "inv_row_pass_mul"),
                ("k_col<nttk::Arith64<false>, 8, 16, false", "inv_col_pass"),
                ("k_pointwise<nttk::ModInfo64", "pointwise")]
@@ -422,7 +423,7 @@ def bench_polymul(ntt, si, torch, steps=100, warm=10):
     return res
 
 
-def bench_ablations(ntt, si, torch, steps=60, warm=5):
+def bench_ablations(ntt, si, torch, steps=100, warm=5):
     """The headline step (2 ciphertexts, N = 2^16, 24 limbs, one stream) with one
     design choice changed at a time: the row pass with the merged per-row
     twiddles instead of the twisted one, the four-step split N1 x N2, the
@@ -439,7 +440,7 @@ def bench_ablations(ntt, si, torch, steps=60, warm=5):
     sets = [base.clone() for _ in range(n_sets)]
     stream = torch.cuda.current_stream()
 
-    def run(plan, fused):
+    def make_step(plan, fused):
         def step(buf):
             plan.forward(buf, batch=4)
             a, b = buf[:2], buf[2:]
@@ -448,42 +449,59 @@ def bench_ablations(ntt, si, torch, steps=60, warm=5):
             else:
                 plan.pointwise(a, b, a, batch=2)
                 plan.inverse(a, batch=2)
-        chk = base.clone()
-        plan.forward(chk, batch=4)
-        plan.inverse(chk, batch=4)
-        torch.cuda.synchronize()
-        assert torch.equal(chk, base), "ablation variant is not exact"
+        return step
+
+    def timed(step, n):
         for s in range(warm):
             step(sets[s % n_sets])
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        for s in range(steps):
+        for s in range(n):
             step(sets[s % n_sets])
         e1.record(stream)
         torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / steps * 1e3
+        return e0.elapsed_time(e1) / n * 1e3
 
-    rows = []
-    for name, log_n1, exact, fused, twist in [
-            ("default: split 2^8 x 2^8, approximate quotient, fused product, twisted inverse rows", 8, False, True,
-             ntt.NTT_ROW_TWIST_INV),
-            ("merged-twiddle row passes", 8, False, True, 0),
-            ("twisted row passes in both directions", 8, False, True, ntt.NTT_ROW_TWIST_FWD | ntt.NTT_ROW_TWIST_INV),
-            ("split 2^7 x 2^9", 7, False, True, ntt.NTT_ROW_TWIST_INV),
-            ("split 2^9 x 2^7", 9, False, True, ntt.NTT_ROW_TWIST_INV),
-            ("exact quotient", 8, True, True, ntt.NTT_ROW_TWIST_INV),
-            ("separate pointwise pass", 8, False, False, ntt.NTT_ROW_TWIST_INV)]:
+    variants = [
+        ("default: split 2^8 x 2^8, approximate quotient, fused product, twisted inverse rows", 8, False, True,
+         ntt.NTT_ROW_TWIST_INV),
+        ("merged-twiddle row passes", 8, False, True, 0),
+        ("twisted row passes in both directions", 8, False, True, ntt.NTT_ROW_TWIST_FWD | ntt.NTT_ROW_TWIST_INV),
+        ("split 2^7 x 2^9", 7, False, True, ntt.NTT_ROW_TWIST_INV),
+        ("split 2^9 x 2^7", 9, False, True, ntt.NTT_ROW_TWIST_INV),
+        ("exact quotient", 8, True, True, ntt.NTT_ROW_TWIST_INV),
+        ("separate pointwise pass", 8, False, False, ntt.NTT_ROW_TWIST_INV)]
+    plans, steps_of = [], []
+    for name, log_n1, exact, fused, twist in variants:
         plan = ntt.Plan(N, moduli)
         plan.set_variant(ntt.NTT_PATH_FOURSTEP, log_n1)
         plan.set_exact_quotient(exact)
         plan.set_row_twist(twist)
-        us = run(plan, fused)
+        chk = base.clone()
+        plan.forward(chk, batch=4)
+        plan.inverse(chk, batch=4)
+        torch.cuda.synchronize()
+        assert torch.equal(chk, base), "ablation variant is not exact"
+        plans.append(plan)
+        steps_of.append(make_step(plan, fused))
+    # the variants take turns, round after round, and each reports its median
+    # round: drift of the GPU's speed during the section then falls on all alike
+    rounds = 5
+    times = [[] for _ in variants]
+    for _ in range(rounds):
+        for i, step in enumerate(steps_of):
+            times[i].append(timed(step, max(1, steps // rounds)))
+    rows = []
+    for (name, log_n1, exact, fused, twist), ts in zip(variants, times):
+        us = float(np.median(ts))
         rows.append({"variant": name, "log_n1": log_n1, "exact_quotient": exact, "fused_product": fused,
-                     "row_twist_mask": twist, "us_per_step": round(us, 1), "ntt_per_s": round(144 / (us * 1e-6), 1)})
-        log(f"ablation {name}: {us:.1f} us/step")
+                     "row_twist_mask": twist, "us_per_step": round(us, 1), "ntt_per_s": round(144 / (us * 1e-6), 1),
+                     "rounds_us": [round(t, 1) for t in ts]})
+        log(f"ablation {name}: {us:.1f} us/step (median of {rounds} interleaved rounds)")
+    for plan in plans:
         plan.close()
-    return {"workload": w.name, "streams": 1, "rows": rows}
+    return {"workload": w.name, "streams": 1, "rounds": rounds, "rows": rows}
 
 
 def bench_he_steps(ntt, si, torch, reps=50):
@@ -783,7 +801,21 @@ def main():
         f"{value / 1e6:.3f} M NTT/s (one stream: {ms_wall_1 * 1e3:.1f} us, "
         f"{ntts_per_step / (ms_wall_1 / 1e3) / 1e6:.3f} M NTT/s)")
 
-    # ---- per-kernel durations with HIP events on the launch stream
+    # ---- per-kernel durations with HIP events on the launch stream. First about
+    # 50 ms of device copies (another kernel, so a kernel-trace summary of these
+    # passes holds only their own launches): clocks settle under load, and the
+    # short profiled run then times the same state as a full run does after its
+    # hundreds of steps.
+    warm_a = torch.empty(32 << 20, dtype=torch.int64, device="cuda")
+    warm_b = torch.empty_like(warm_a)
+    torch.cuda.synchronize()
+    t_warm = time.perf_counter()
+    while time.perf_counter() - t_warm < 0.05:
+        for _ in range(8):
+            warm_b.copy_(warm_a)
+        torch.cuda.synchronize()
+    del warm_a, warm_b
+
     def time_kernel(fn, reps):
         evs = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
         for r in range(3):
