@@ -504,6 +504,21 @@ k_row(const typename A::word* in, typename A::word* out, const typename A::tw_t*
 // its inverse (slots 0 and 1 are never read). The inverse runs the cyclic
 // inverse and multiplies by beta_r^-j before the store; the factor N^-1 stays
 // with the column pass.
+// LDS position of cyclic-table slot m = 2^s + g for a row of 2^LOGN2. Stage s
+// lies in the phase that starts at stage S0 (k = s - S0); there the thread of
+// phase group Hg reads group g = (Hg << k) + j, so the groups are stored as
+// (j << S0) + Hg: for each j, the lanes of a row read consecutive entries
+// instead of entries 2^k apart (which fall in the same LDS banks).
+template <int LOGN2>
+__device__ __forceinline__ uint32_t cyc_pos(uint32_t m) {
+  using S = Sched<LOGN2>;
+  if (m < 2) return m;
+  const uint32_t s = 31u - (uint32_t)__builtin_clz(m);
+  const uint32_t S0 = (S::R0 && s < (uint32_t)S::R0) ? 0u : (S::R0 ? S::R0 + ((s - S::R0) & ~3u) : (s & ~3u));
+  const uint32_t k = s - S0, g = m - (1u << s);
+  return (1u << s) + ((g & ((1u << k) - 1u)) << S0) + (g >> k);
+}
+
 template <class A, int RS, bool FIRST>
 __device__ __forceinline__ void ct_phase_cyc(const A& a, typename A::word (&v)[16], const typename A::tw_t* tw,
                                              uint32_t S0, uint32_t Hg) {
@@ -515,7 +530,7 @@ __device__ __forceinline__ void ct_phase_cyc(const A& a, typename A::word (&v)[1
 #pragma unroll
         for (int m = 0; m < (8 >> k); ++m) a.ct1(v[m], v[m + (8 >> k)]);
       } else {
-        const typename A::tw_t w = tw[(1u << (S0 + k)) + (Hg << k) + j];
+        const typename A::tw_t w = tw[(1u << (S0 + k)) + ((uint32_t)j << S0) + Hg];  // see cyc_pos
 #pragma unroll
         for (int m = 0; m < (8 >> k); ++m) {
           const int i0 = j * (16 >> k) + m;
@@ -536,7 +551,7 @@ __device__ __forceinline__ void gs_phase_cyc(const A& a, typename A::word (&v)[1
 #pragma unroll
         for (int m = 0; m < (8 >> k); ++m) a.gs1(v[m], v[m + (8 >> k)]);
       } else {
-        const typename A::tw_t w = tw[(1u << (S0 + k)) + (Hg << k) + j];
+        const typename A::tw_t w = tw[(1u << (S0 + k)) + ((uint32_t)j << S0) + Hg];  // see cyc_pos
 #pragma unroll
         for (int m = 0; m < (8 >> k); ++m) {
           const int i0 = j * (16 >> k) + m;
@@ -581,7 +596,7 @@ k_row_tw(const typename A::word* in, typename A::word* out, const typename A::tw
     const W* src = in + pbase + (size_t)r * N2;
 #pragma unroll
     for (int i = 0; i < 16; ++i) v[i] = ld_data<NT_LD_MID>(src + i * TPR + t);
-    cyc[threadIdx.x] = cyc_entry;
+    cyc[cyc_pos<LOGN2>(threadIdx.x)] = cyc_entry;
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < 16; ++i) v[i] = a.mul(v[i], twist[i * TPR + t]);
@@ -619,7 +634,7 @@ k_row_tw(const typename A::word* in, typename A::word* out, const typename A::tw
       for (int i = 0; i < 16; ++i) st_data<NT_ST_OUT>(dst + i * TPR + t, sh[pad16(i * TPR + t)]);
     }
   } else {
-    cyc[threadIdx.x] = cyc_entry;
+    cyc[cyc_pos<LOGN2>(threadIdx.x)] = cyc_entry;
     if constexpr (NATURAL) {
       const uint32_t rr = threadIdx.x % 16, cg = threadIdx.x / 16;
       const size_t off = pbase + tile * 16 + rr;
