@@ -195,7 +195,9 @@ k_lds(typename A::word* __restrict__ data, const typename A::tw_t* __restrict__ 
 #pragma unroll
         for (int i = 0; i < 16; ++i) v[i] = sh[pad16(pos<LOGN>(p, t, i))];
       }
-      ct_phase<A, S::rs(p)>(a, v, tw, S::s0(p), grp<LOGN>(p, t));
+      // phase 0 has one group per transform: its twiddle addresses are
+      // uniform and the compiler reads them with scalar loads
+      ct_phase<A, S::rs(p)>(a, v, tw, S::s0(p), p == 0 ? 0u : grp<LOGN>(p, t));
     });
     if (S::NPH > 1) __syncthreads();
 #pragma unroll
@@ -227,7 +229,7 @@ k_lds(typename A::word* __restrict__ data, const typename A::tw_t* __restrict__ 
 #pragma unroll
         for (int i = 0; i < 16; ++i) v[i] = sh[pad16(pos<LOGN>(p, t, i))];
       }
-      gs_phase<A, S::rs(p), p == 0>(a, v, tw, S::s0(p), grp<LOGN>(p, t));
+      gs_phase<A, S::rs(p), p == 0>(a, v, tw, S::s0(p), p == 0 ? 0u : grp<LOGN>(p, t));
     });
     if (valid) {
 #pragma unroll
@@ -284,6 +286,10 @@ k_col(const typename A::word* in, typename A::word* out, const typename A::tw_t*
   using S = Sched<LOGN1>;
   constexpr uint32_t N1 = 1u << LOGN1, TPC = N1 / 16, LD = NC + 1;
   __shared__ W lds[N1 * LD];
+  // forward: the table slots [0, N1) in LDS for the phases after the first,
+  // written at the start and published by the first exchange's barrier
+  constexpr bool TWL = FWD && S::NPH > 1;
+  __shared__ TW twl[TWL ? N1 : 1];
   const uint32_t N2 = 1u << (logN - LOGN1);
   const uint32_t tiles = N2 / NC;
   const uint32_t bid = xcd_remap(blockIdx.x, gridDim.x);
@@ -291,8 +297,9 @@ k_col(const typename A::word* in, typename A::word* out, const typename A::tw_t*
   if (item >= items) return;  // whole workgroup leaves together
   const uint32_t c = threadIdx.x % NC, t = threadIdx.x / NC;
   A a;
-  // the column stages use table slots [0, N1) only; every lane of a wave reads
-  // the same slot, so these loads are served by one cache line each
+  // the column stages use table slots [0, N1) only. In the first phase every
+  // thread of the workgroup reads the same slots, which the compiler turns into
+  // scalar loads; the forward pass reads the later phases' slots from LDS.
   const TW* tw;
   const W* src;
   W* dst;
@@ -315,6 +322,9 @@ k_col(const typename A::word* in, typename A::word* out, const typename A::tw_t*
   if constexpr (FWD) {
 #pragma unroll
     for (int i = 0; i < 16; ++i) v[i] = ld_data<NT_LD_IN>(src + (size_t)(i * TPC + t) * N2);
+    if constexpr (TWL) {
+      for (uint32_t k = threadIdx.x; k < N1; k += blockDim.x) twl[k] = tw[k];
+    }
     static_for<0, S::NPH>([&](auto P_) {
       constexpr int p = decltype(P_)::value;
       if constexpr (p > 0) {
@@ -324,8 +334,10 @@ k_col(const typename A::word* in, typename A::word* out, const typename A::tw_t*
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < 16; ++i) v[i] = lds[pos<LOGN1>(p, t, i) * LD + c];
+        ct_phase<A, S::rs(p)>(a, v, twl, S::s0(p), grp<LOGN1>(p, t));
+      } else {
+        ct_phase<A, S::rs(p)>(a, v, tw, 0u, 0u);
       }
-      ct_phase<A, S::rs(p)>(a, v, tw, S::s0(p), grp<LOGN1>(p, t));
     });
 #pragma unroll
     for (int i = 0; i < 16; ++i) st_data<NT_ST_MID>(dst + (size_t)pos<LOGN1>(S::NPH - 1, t, i) * N2, v[i]);
@@ -342,7 +354,7 @@ k_col(const typename A::word* in, typename A::word* out, const typename A::tw_t*
 #pragma unroll
         for (int i = 0; i < 16; ++i) v[i] = lds[pos<LOGN1>(p, t, i) * LD + c];
       }
-      gs_phase<A, S::rs(p), p == 0>(a, v, tw, S::s0(p), grp<LOGN1>(p, t));
+      gs_phase<A, S::rs(p), p == 0>(a, v, tw, S::s0(p), p == 0 ? 0u : grp<LOGN1>(p, t));
     });
 #pragma unroll
     for (int i = 0; i < 16; ++i) st_data<NT_ST_OUT>(dst + (size_t)(i * TPC + t) * N2, a.canon_inv(v[i]));
