@@ -362,6 +362,26 @@ k_col(const typename A::word* in, typename A::word* out, const typename A::tw_t*
 }
 
 // ============================================================ row pass
+// The first phase of a row (stages logN1 .. logN1 + rs(0) - 1) uses the
+// 2^rs(0) - 1 twiddles of the row's own subtree: slot 2^k + j of row r is
+// table entry 2^(logN1 + k) + (r << k) + j. Each wave copies those of its own
+// 64 / TPR rows into LDS (lane q * 2^rs(0) + u: row q, slot u; at most 64
+// lanes for every LOGN2 from 6 to 9) and orders the copy with the wavefront
+// sync it already needs, so that phase reads no twiddle from global memory
+// between butterflies. row_of(rl) is the matrix row of workgroup row rl.
+template <int LOGN2, class TW, class F>
+__device__ __forceinline__ void stage_first_phase(TW (*tw0)[16], const TW* tw, uint32_t logN1, F row_of) {
+  constexpr uint32_t TPR = (1u << LOGN2) / 16, RPW = 64 / TPR, RS0 = Sched<LOGN2>::rs(0), SL = 1u << RS0;
+  static_assert(RPW * SL <= 64 && SL <= 16, "one lane per first-phase twiddle of the wave's rows");
+  const uint32_t lane = threadIdx.x & 63u, q = lane / SL, u = lane % SL;
+  const uint32_t rl = (threadIdx.x >> 6) * RPW + q;  // the rows this wave transforms
+  if (q < RPW && u) {
+    const uint32_t k = 31u - (uint32_t)__builtin_clz(u), j = u - (1u << k);
+    tw0[rl][u] = tw[(1u << (logN1 + k)) + (row_of(rl) << k) + j];
+  }
+}
+
+// ============================================================ row pass
 // 16 rows per workgroup, N2/16 threads per row (a row never spans two waves,
 // so exchanges between phases only need wavefront ordering).
 // Forward: global stages [logN1, logN), canonical output; NATURAL writes
@@ -383,6 +403,7 @@ k_row(const typename A::word* in, typename A::word* out, const typename A::tw_t*
   constexpr uint32_t N2 = 1u << LOGN2, TPR = N2 / 16, RSTR = N2 + N2 / 16 + 1;
   static_assert(TPR <= 64, "a row must fit in one wavefront");
   __shared__ W lds[16 * RSTR];
+  __shared__ TW tw0[16][16];  // first-phase twiddles of the 16 rows
   const uint32_t logN1 = logN - LOGN2, N1 = 1u << logN1;
   const uint32_t tiles = N1 / 16;
   // logical order (limb, tile, poly): the polynomials sharing a limb's row
@@ -415,10 +436,13 @@ k_row(const typename A::word* in, typename A::word* out, const typename A::tw_t*
   a.load(*mi);
   W* sh = lds + rl * RSTR;
   W v[16];
+  stage_first_phase<LOGN2>(tw0, tw, logN1,
+                           [&](uint32_t row) { return NATURAL ? brv(tile * 16 + row, logN1) : tile * 16 + row; });
   if constexpr (FWD) {
     const W* src = in + pbase + (size_t)r * N2;
 #pragma unroll
     for (int i = 0; i < 16; ++i) v[i] = ld_data<NT_LD_MID>(src + i * TPR + t);
+    wave_lds_sync();
     static_for<0, S::NPH>([&](auto P_) {
       constexpr int p = decltype(P_)::value;
       if constexpr (p > 0) {
@@ -428,8 +452,10 @@ k_row(const typename A::word* in, typename A::word* out, const typename A::tw_t*
         wave_lds_sync();
 #pragma unroll
         for (int i = 0; i < 16; ++i) v[i] = sh[pad16(pos<LOGN2>(p, t, i))];
+        ct_phase<A, S::rs(p)>(a, v, tw, logN1 + S::s0(p), (r << S::s0(p)) + grp<LOGN2>(p, t));
+      } else {
+        ct_phase<A, S::rs(p)>(a, v, &tw0[rl][0], 0u, 0u);
       }
-      ct_phase<A, S::rs(p)>(a, v, tw, logN1 + S::s0(p), (r << S::s0(p)) + grp<LOGN2>(p, t));
     });
     if constexpr (NATURAL) {
       if (S::NPH > 1) wave_lds_sync();
@@ -489,7 +515,8 @@ k_row(const typename A::word* in, typename A::word* out, const typename A::tw_t*
 #pragma unroll
         for (int i = 0; i < 16; ++i) v[i] = sh[pad16(pos<LOGN2>(p, t, i))];
       }
-      gs_phase<A, S::rs(p), false>(a, v, tw, logN1 + S::s0(p), (r << S::s0(p)) + grp<LOGN2>(p, t));
+      if constexpr (p == 0) gs_phase<A, S::rs(p), false>(a, v, &tw0[rl][0], 0u, 0u);
+      else gs_phase<A, S::rs(p), false>(a, v, tw, logN1 + S::s0(p), (r << S::s0(p)) + grp<LOGN2>(p, t));
     });
     W* dst = out + pbase + (size_t)r * N2;
 #pragma unroll
