@@ -28,6 +28,7 @@ k_row_polymul(typename A::word* sa, const typename A::word* __restrict__ sb,
   constexpr uint32_t N2 = 1u << LOGN2, TPR = N2 / 16, RSTR = N2 + N2 / 16 + 1;
   static_assert(TPR <= 64, "a row must fit in one wavefront");
   __shared__ W lds[16 * RSTR];
+  __shared__ TW tw0[16][16];  // first-phase twiddles of the 16 rows: forward, then inverse
   const uint32_t logN1 = logN - LOGN2, N1 = 1u << logN1;
   const uint32_t tiles = N1 / 16;
   const uint32_t bid = xcd_remap(blockIdx.x, gridDim.x);
@@ -67,10 +68,13 @@ k_row_polymul(typename A::word* sa, const typename A::word* __restrict__ sb,
   A a;
   a.load(m);
   W* sh = lds + rl * RSTR;
+  auto row_of = [&](uint32_t row) { return tile * 16 + row; };
 
   W va[16], vb[16];
+  stage_first_phase<LOGN2>(tw0, twf, logN1, row_of);
 #pragma unroll
   for (int i = 0; i < 16; ++i) va[i] = rowa[i * TPR + t];
+  wave_lds_sync();
 
   auto forward = [&](W (&v)[16], const TW* twf) {
     static_for<0, S::NPH>([&](auto P_) {
@@ -82,8 +86,10 @@ k_row_polymul(typename A::word* sa, const typename A::word* __restrict__ sb,
         wave_lds_sync();
 #pragma unroll
         for (int i = 0; i < 16; ++i) v[i] = sh[pad16(pos<LOGN2>(p, t, i))];
+        ct_phase<A, S::rs(p)>(a, v, twf, logN1 + S::s0(p), (r << S::s0(p)) + grp<LOGN2>(p, t));
+      } else {
+        ct_phase<A, S::rs(p)>(a, v, &tw0[rl][0], 0u, 0u);
       }
-      ct_phase<A, S::rs(p)>(a, v, twf, logN1 + S::s0(p), (r << S::s0(p)) + grp<LOGN2>(p, t));
     });
   };
   // one operand at a time, so that only one row's working set is live: a's
@@ -102,6 +108,10 @@ k_row_polymul(typename A::word* sa, const typename A::word* __restrict__ sb,
   forward(vb, twf_b);
 #pragma unroll
   for (int i = 0; i < 16; ++i) va[i] = mulmod_general(va[i], a.canon_fwd(vb[i]), m);
+  // the wave's rows switch to the inverse table's first-phase twiddles; the
+  // inverse phases' exchanges order the copy before their use
+  wave_lds_sync();
+  stage_first_phase<LOGN2>(tw0, twi, logN1, row_of);
   static_for_down<S::NPH - 1, 0>([&](auto P_) {
     constexpr int p = decltype(P_)::value;
     if constexpr (p < S::NPH - 1) {
@@ -112,7 +122,8 @@ k_row_polymul(typename A::word* sa, const typename A::word* __restrict__ sb,
 #pragma unroll
       for (int i = 0; i < 16; ++i) va[i] = sh[pad16(pos<LOGN2>(p, t, i))];
     }
-    gs_phase<A, S::rs(p), false>(a, va, twi, logN1 + S::s0(p), (r << S::s0(p)) + grp<LOGN2>(p, t));
+    if constexpr (p == 0) gs_phase<A, S::rs(p), false>(a, va, &tw0[rl][0], 0u, 0u);
+    else gs_phase<A, S::rs(p), false>(a, va, twi, logN1 + S::s0(p), (r << S::s0(p)) + grp<LOGN2>(p, t));
   });
   // phase 0 leaves thread t with positions i * TPR + t
 #pragma unroll
