@@ -28,7 +28,7 @@ k_row_polymul(typename A::word* sa, const typename A::word* __restrict__ sb,
   constexpr uint32_t N2 = 1u << LOGN2, TPR = N2 / 16, RSTR = N2 + N2 / 16 + 1;
   static_assert(TPR <= 64, "a row must fit in one wavefront");
   __shared__ W lds[16 * RSTR];
-  __shared__ TW tw0[16][16];  // first-phase twiddles of the 16 rows: forward, then inverse
+  __shared__ TW tw0[16][17];  // first-phase twiddles of the 16 rows: forward, then inverse
   const uint32_t logN1 = logN - LOGN2, N1 = 1u << logN1;
   const uint32_t tiles = N1 / 16;
   const uint32_t bid = xcd_remap(blockIdx.x, gridDim.x);

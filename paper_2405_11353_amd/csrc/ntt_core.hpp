@@ -366,11 +366,12 @@ k_col(const typename A::word* in, typename A::word* out, const typename A::tw_t*
 // 2^rs(0) - 1 twiddles of the row's own subtree: slot 2^k + j of row r is
 // table entry 2^(logN1 + k) + (r << k) + j. Each wave copies those of its own
 // 64 / TPR rows into LDS (lane q * 2^rs(0) + u: row q, slot u; at most 64
-// lanes for every LOGN2 from 6 to 9) and orders the copy with the wavefront
+// lanes for every LOGN2 from 6 to 9; rows padded to 17 entries so the wave's
+// rows fall in different LDS banks) and orders the copy with the wavefront
 // sync it already needs, so that phase reads no twiddle from global memory
 // between butterflies. row_of(rl) is the matrix row of workgroup row rl.
 template <int LOGN2, class TW, class F>
-__device__ __forceinline__ void stage_first_phase(TW (*tw0)[16], const TW* tw, uint32_t logN1, F row_of) {
+__device__ __forceinline__ void stage_first_phase(TW (*tw0)[17], const TW* tw, uint32_t logN1, F row_of) {
   constexpr uint32_t TPR = (1u << LOGN2) / 16, RPW = 64 / TPR, RS0 = Sched<LOGN2>::rs(0), SL = 1u << RS0;
   static_assert(RPW * SL <= 64 && SL <= 16, "one lane per first-phase twiddle of the wave's rows");
   const uint32_t lane = threadIdx.x & 63u, q = lane / SL, u = lane % SL;
@@ -403,7 +404,7 @@ k_row(const typename A::word* in, typename A::word* out, const typename A::tw_t*
   constexpr uint32_t N2 = 1u << LOGN2, TPR = N2 / 16, RSTR = N2 + N2 / 16 + 1;
   static_assert(TPR <= 64, "a row must fit in one wavefront");
   __shared__ W lds[16 * RSTR];
-  __shared__ TW tw0[16][16];  // first-phase twiddles of the 16 rows
+  __shared__ TW tw0[16][17];  // first-phase twiddles of the 16 rows
   const uint32_t logN1 = logN - LOGN2, N1 = 1u << logN1;
   const uint32_t tiles = N1 / 16;
   // logical order (limb, tile, poly): the polynomials sharing a limb's row
