@@ -242,7 +242,12 @@ def bench_batched(ntt, si, torch, reps=10):
     us_graph = timed(fwd.run, reps)
     us_eager = timed(eager.run, reps)
     # autotuned: every bucket size is tuned at its own item count, then the
-    # batch is rebuilt (buckets pick their variants from the tuning table)
+    # batch is rebuilt (buckets pick their variants from the tuning table). The
+    # process's table (the shipped one) is saved first and restored after, so
+    # the sections that follow run with it.
+    import tempfile
+    saved_table = os.path.join(tempfile.mkdtemp(prefix="ntt_tune_"), "table.json")
+    ntt.ntt_tune_save(saved_table)
     ntt.ntt_tune_clear()
     items_by_n = {}
     for j in jobs:
@@ -256,6 +261,12 @@ def bench_batched(ntt, si, torch, reps=10):
     us_tuned = timed(tuned.run, reps)
     tuned.close()
     ntt.ntt_tune_clear()
+    try:
+        ntt.ntt_tune_load(saved_table)
+    except ntt.NttError:
+        pass  # the process had no table: defaults, as before the section
+    os.remove(saved_table)
+    os.rmdir(os.path.dirname(saved_table))
     plans = {}
     for j in jobs:
         if (j.N, j.L) not in plans:
