@@ -648,11 +648,8 @@ def bench_serving(ntt, si, torch, n_jobs=3000, warm=300, rate=15000.0):
     for t in tk:
         assert server.wait(t) == 0
     sat_jobs_s = len(burst) / (time.perf_counter() - t0)
-    trace = si.serving_trace(count=warm + n_jobs, rate_per_s=rate)
-    treqs = prepare(trace)
-    server.reset_stats()
-
-    def replay_server():
+    def replay_server(trace, treqs):
+        server.reset_stats()
         tickets = []
         start = time.perf_counter()
         for i, j in enumerate(trace):
@@ -665,7 +662,22 @@ def bench_serving(ntt, si, torch, n_jobs=3000, warm=300, rate=15000.0):
             assert server.wait(t) == 0
         return time.perf_counter() - start
 
-    wall = replay_server()
+    # latency against offered load: the same job mix at fractions of the burst rate
+    curve = []
+    for frac in (0.3, 0.5, 0.7):
+        r = frac * sat_jobs_s
+        tr = si.serving_trace(seed=si.BASE_SEED + 42, count=warm + n_jobs, rate_per_s=r)
+        replay_server(tr, prepare(tr))
+        cs = server.stats()
+        curve.append({"offered_jobs_per_s": round(r, 1), "fraction_of_burst_rate": frac,
+                      "p50_us": round(cs["p50_us"], 1), "p99_us": round(cs["p99_us"], 1),
+                      "mean_jobs_per_batch": round(cs["completed"] / max(1, cs["batches"]), 2)})
+        log(f"serving at {r:.0f} jobs/s ({frac:.0%} of the burst rate): p50 {curve[-1]['p50_us']} us "
+            f"p99 {curve[-1]['p99_us']} us, {curve[-1]['mean_jobs_per_batch']} jobs per batch")
+
+    trace = si.serving_trace(count=warm + n_jobs, rate_per_s=rate)
+    treqs = prepare(trace)
+    wall = replay_server(trace, treqs)
     st = server.stats()
     server.close()
 
@@ -714,7 +726,7 @@ def bench_serving(ntt, si, torch, n_jobs=3000, warm=300, rate=15000.0):
            "ntt_per_s": round(st["ntts"] / st["wall_s"], 1), "batches": st["batches"],
            "mean_jobs_per_batch": round(st["completed"] / max(1, st["batches"]), 2),
            "max_inflight_batches": st["max_inflight_batches"], "admission_stalls": st["admission_stalls"],
-           "hbm_budget_GiB": 4,
+           "hbm_budget_GiB": 4, "load_curve": curve,
            "per_call_fifo": {"p50_us": round(float(fl[len(fl) // 2]), 1),
                              "p99_us": round(float(fl[int(0.99 * (len(fl) - 1))]), 1),
                              "ntt_per_s": round(sum(ntts_of(j) for j in trace) / fifo_wall, 1)}}
