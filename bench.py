@@ -681,6 +681,21 @@ def bench_serving(ntt, si, torch, n_jobs=3000, warm=300, rate=15000.0):
     st = server.stats()
     server.close()
 
+    # the 70%-of-burst trace under other HBM budgets: admission holds jobs whose
+    # working memory does not fit beside the jobs in flight
+    budgets = []
+    hi = si.serving_trace(seed=si.BASE_SEED + 42, count=warm + n_jobs, rate_per_s=0.7 * sat_jobs_s)
+    for gib in (0.25, 1, 4, 16):
+        server = ntt.Server(hbm_budget_bytes=int(gib * (1 << 30)), n_streams=4, max_batch_items=4096)
+        replay_server(hi, prepare(hi))
+        bs = server.stats()
+        server.close()
+        budgets.append({"hbm_budget_GiB": gib, "offered_jobs_per_s": round(0.7 * sat_jobs_s, 1), "p50_us": round(bs["p50_us"], 1), "p99_us": round(bs["p99_us"], 1),
+                        "admission_stalls": bs["admission_stalls"],
+                        "max_inflight_batches": bs["max_inflight_batches"]})
+        log(f"serving, {gib} GiB budget: p50 {budgets[-1]['p50_us']} us p99 {budgets[-1]['p99_us']} us, "
+            f"{bs['admission_stalls']} admission stalls")
+
     # per-call FIFO: each job run on arrival with plain plan calls, one at a time;
     # every plan runs one product first, so one-time work (scratch allocation,
     # tables of the split the tuning table picks) stays out of the replay
@@ -726,7 +741,7 @@ def bench_serving(ntt, si, torch, n_jobs=3000, warm=300, rate=15000.0):
            "ntt_per_s": round(st["ntts"] / st["wall_s"], 1), "batches": st["batches"],
            "mean_jobs_per_batch": round(st["completed"] / max(1, st["batches"]), 2),
            "max_inflight_batches": st["max_inflight_batches"], "admission_stalls": st["admission_stalls"],
-           "hbm_budget_GiB": 4, "load_curve": curve,
+           "hbm_budget_GiB": 4, "load_curve": curve, "budget_sweep_at_70pct": budgets,
            "per_call_fifo": {"p50_us": round(float(fl[len(fl) // 2]), 1),
                              "p99_us": round(float(fl[int(0.99 * (len(fl) - 1))]), 1),
                              "ntt_per_s": round(sum(ntts_of(j) for j in trace) / fifo_wall, 1)}}
