@@ -97,7 +97,7 @@ def summarize_counters(d: str, he: bool = False):
         md = os.path.join(ROOT, "profiles", "polymul_n65536_l24_counters.md")
         title = "# Counters and kernel trace: polymul_n65536_l24 (N=2^16, 24 limbs, 2 ciphertexts), MI355X"
         B = ("python3 bench.py --steps 2 --warmup 1 --kernel-reps 40 --streams 1 --no-cpu-baseline --no-per-call "
-             "--no-batched --no-serving --no-paper-sizes --no-he --no-ablations --no-polymul")
+             "--no-batched --no-serving --no-paper-sizes --no-he --no-ablations --no-polymul --no-batch-sweep")
     copy_f = [v["FETCH_SIZE"] for k, v in pmc("pmc_copy_fetch").items() if "k_copy" in k][0]
     copy_w = [v["WRITE_SIZE"] for k, v in pmc("pmc_copy_write").items() if "k_copy" in k][0]
     gib_kib = float(1 << 20)
@@ -197,6 +197,7 @@ def parse():
     ap.add_argument("--summarize-he-counters", metavar="DIR", default=None,
                     help="write the HE-step counter summary under profiles/ from a rocprofv3 session")
     ap.add_argument("--serving-jobs", type=int, default=3000)
+    ap.add_argument("--no-batch-sweep", action="store_true")
     ap.add_argument("--serving-rate", type=float, default=15000.0,
                     help="offered load of the serving workload, jobs/s (Poisson arrivals)")
     ap.add_argument("--summarize-counters", metavar="DIR", default=None,
@@ -381,6 +382,49 @@ def bench_paper_sizes(ntt, si, torch, reps=100, batch=1024):
         log(f"paper size N={N}: " + ", ".join(f"{v}: {row[v]['single_us']} us / {row[v]['batched_ntt_per_s'] / 1e6:.1f} M/s"
                                              for v, _ in variants) + f"; fused from a graph: {row['fused']['single_us_graph']} us")
     return {"workload": "cyclic_u32_q998244353_single_and_batched", "reps": reps, "batch": batch, "sizes": out}
+
+
+def bench_batch_sweep(ntt, si, torch, reps=30):
+    """The headline shape (N = 2^16, 24 limbs) at B = 1..32 polynomials per call,
+    forward and inverse timed separately (HIP events, mean over reps dependent
+    calls on buffers rotated over >= 1 GiB): how the fixed cost of a launch is
+    amortised as the batch grows. Each call is 24 B transforms."""
+    w = si.workload_polymul_n16()
+    N, moduli, L = w.N, w.moduli, len(w.moduli)
+    plan = ntt.Plan(N, moduli)
+    stream = torch.cuda.current_stream()
+    host = si.poly_batch(w.seed, 1, moduli, N)
+    one = torch.from_numpy(host.view(np.int64)).cuda()
+    rows = []
+    for B in (1, 2, 4, 8, 16, 32):
+        base = one.repeat(B, 1, 1).contiguous()
+        n_sets = max(2, math.ceil((1 << 30) / (base.numel() * 8)))
+        sets = [base.clone() for _ in range(n_sets)]
+        chk = base.clone()
+        plan.forward(chk, batch=B)
+        plan.inverse(chk, batch=B)
+        torch.cuda.synchronize()
+        assert torch.equal(chk, base), "batch sweep round trip is not exact"
+        row = {"polys": B, "ntts_per_call": B * L}
+        for name, fn in (("forward", plan.forward), ("inverse", plan.inverse)):
+            for r in range(3):
+                fn(sets[r % n_sets], batch=B)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for r in range(reps):
+                fn(sets[r % n_sets], batch=B)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            us = e0.elapsed_time(e1) / reps * 1e3
+            row[name + "_us"] = round(us, 1)
+            row[name + "_ntt_per_s"] = round(B * L / (us * 1e-6), 1)
+        rows.append(row)
+        log(f"batch sweep B={B}: forward {row['forward_us']} us ({row['forward_ntt_per_s'] / 1e6:.2f} M NTT/s), "
+            f"inverse {row['inverse_us']} us ({row['inverse_ntt_per_s'] / 1e6:.2f} M NTT/s)")
+        del sets, base
+    plan.close()
+    return {"workload": w.name, "limbs": L, "N": N, "rows": rows}
 
 
 def bench_polymul(ntt, si, torch, steps=100, warm=10):
@@ -977,6 +1021,7 @@ def main():
     he_steps = None if args.no_he else bench_he_steps(ntt, si, torch)
     ablations = None if args.no_ablations else bench_ablations(ntt, si, torch)
     polymul = None if args.no_polymul else bench_polymul(ntt, si, torch)
+    batch_sweep = None if args.no_batch_sweep else bench_batch_sweep(ntt, si, torch)
 
     res = {
         "metric": "NTT/s at N=2^16 x 24 limbs (forward + inverse NTTs of a batched 2-ciphertext negacyclic product)",
@@ -1008,6 +1053,7 @@ def main():
         "he_steps": he_steps,
         "ablations": ablations,
         "polymul": polymul,
+        "batch_sweep": batch_sweep,
     }
     print(json.dumps(res), flush=True)
 
