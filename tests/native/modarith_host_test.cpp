@@ -1,7 +1,7 @@
 // Host unit test of the GPU library's modular arithmetic (modarith.hpp, built
 // for the CPU) against exact 128-bit arithmetic: the Shoup quotient estimates,
-// the lazy-range invariants of the butterflies, canonicalisation and the
-// general products. Prints "ok <checks>" or the first failure; exit code 0/1.
+// the lazy-range invariants of the butterflies (also the unit-twiddle ones of
+// the cyclic row transform), canonicalisation and the general products. Prints "ok <checks>" or the first failure; exit code 0/1.
 #include <stdint.h>
 #include <stdio.h>
 
@@ -81,6 +81,19 @@ static int test64(uint64_t q) {
     b0 = y4e;
     X.ct(a0, b0, t);
     CHECK(a0 < 4 * q && b0 < 4 * q, "exact ct range");
+    // unit-twiddle butterflies (group 0 of a cyclic stage): the ranges of
+    // ct / gs, with y in place of w y, for both lazy bounds
+    for (int fl = 0; fl < 2; ++fl) {
+      const uint64_t Lz = fl ? 2 * q : 4 * q;
+      uint64_t x1 = rnd() % (2 * Lz), y1 = rnd() % (2 * Lz);
+      const uint64_t xs1 = x1 % q, ys1 = y1 % q;
+      if (fl) X.ct1(x1, y1); else A.ct1(x1, y1);
+      CHECK(x1 < 2 * Lz && y1 < 2 * Lz && x1 % q == (xs1 + ys1) % q && y1 % q == (xs1 + q - ys1) % q, "ct1");
+      uint64_t x2 = rnd() % Lz, y2 = rnd() % Lz;
+      const uint64_t xs2 = x2 % q, ys2 = y2 % q;
+      if (fl) X.gs1(x2, y2); else A.gs1(x2, y2);
+      CHECK(x2 < Lz && y2 < Lz && x2 % q == (xs2 + ys2) % q && y2 % q == (xs2 + q - ys2) % q, "gs1");
+    }
     CHECK(A.canon_fwd(x8) == x8 % q && A.canon_inv(x4) == x4 % q, "canonical (approx)");
     CHECK(X.canon_fwd(x4e) == x4e % q && X.canon_inv(x4e % (2 * q)) == (x4e % (2 * q)) % q, "canonical (exact)");
     // general product
@@ -115,6 +128,16 @@ static int test32(uint32_t q) {
     b0 = y2;
     A.gs(a0, b0, t);
     CHECK(a0 < 2 * q && b0 < 2 * q, "32-bit gs range");
+    a0 = x4;
+    b0 = y4;
+    A.ct1(a0, b0);
+    CHECK(a0 < 4 * q && b0 < 4 * q && a0 % q == (x4 % q + y4 % q) % q && b0 % q == (x4 % q + q - y4 % q) % q,
+          "32-bit ct1");
+    a0 = x2;
+    b0 = y2;
+    A.gs1(a0, b0);
+    CHECK(a0 < 2 * q && b0 < 2 * q && a0 % q == (x2 % q + y2 % q) % q && b0 % q == (x2 % q + q - y2 % q) % q,
+          "32-bit gs1");
     CHECK(A.canon_fwd(x4) == x4 % q && A.canon_inv(x2) == x2 % q, "32-bit canonical");
     const uint32_t u = (uint32_t)(rnd() % q), v = (uint32_t)(rnd() % q);
     CHECK(mulmod_general(u, v, m) == (uint32_t)((uint64_t)u * v % q), "32-bit general product");
