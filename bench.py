@@ -198,6 +198,10 @@ def parse():
                     help="write the HE-step counter summary under profiles/ from a rocprofv3 session")
     ap.add_argument("--serving-jobs", type=int, default=3000)
     ap.add_argument("--no-batch-sweep", action="store_true")
+    ap.add_argument("--polymul-only", action="store_true",
+                    help="only the fused product (ntt_polymul) on one stream, --steps steps after --warmup")
+    ap.add_argument("--summarize-polymul-trace", metavar="DIR",
+                    help="write profiles/polymul_fused_n65536_l24_trace.md from a kernel trace of --polymul-only")
     ap.add_argument("--serving-rate", type=float, default=15000.0,
                     help="offered load of the serving workload, jobs/s (Poisson arrivals)")
     ap.add_argument("--summarize-counters", metavar="DIR", default=None,
@@ -427,7 +431,7 @@ def bench_batch_sweep(ntt, si, torch, reps=30):
     return {"workload": w.name, "limbs": L, "N": N, "rows": rows}
 
 
-def bench_polymul(ntt, si, torch, steps=100, warm=10):
+def bench_polymul(ntt, si, torch, steps=100, warm=10, stream_counts=(1, 2)):
     """The headline product (2 ciphertexts, N = 2^16, 24 limbs) through
     ntt_polymul, which keeps the spectra on chip: c = a * b for the 2 pairs of
     components, coefficients in and out. Reported per step and as the
@@ -451,7 +455,7 @@ def bench_polymul(ntt, si, torch, steps=100, warm=10):
     torch.cuda.synchronize()
     assert torch.equal(out, ref[:2]), "fused product differs from the unfused one"
     res = {"workload": w.name, "products_per_step": 2 * L, "ntt_equivalent_per_step": 144}
-    for n_streams in (1, 2):
+    for n_streams in stream_counts:
         sts = [stream] + [torch.cuda.Stream() for _ in range(n_streams - 1)]
         for s in range(warm):
             x, c = sets[s % n_sets]
@@ -794,6 +798,54 @@ def bench_serving(ntt, si, torch, n_jobs=3000, warm=300, rate=15000.0):
     return res
 
 
+POLYMUL_TRACE_KEYS = [("k_col<nttk::Arith64<false>, 8, 16, true", "column passes of a and b (one launch)"),
+                      ("k_row_polymul<nttk::Arith64<false>, 8", "fused rows: both forward, product, first inverse"),
+                      ("k_col<nttk::Arith64<false>, 8, 16, false", "inverse column pass")]
+
+
+def summarize_polymul_trace(d: str):
+    """Writes profiles/polymul_fused_n65536_l24_trace.md from the rocprofv3
+    kernel trace (kt/*kernel_stats.csv under d) of `bench.py --polymul-only`:
+    the three kernels of ntt_polymul at the headline shape, with the per-step
+    sum beside the bench's own one-stream step time (bench.json under d)."""
+    import csv
+    import glob
+    stats = {}
+    for f in glob.glob(os.path.join(d, "kt", "*kernel_stats.csv")):
+        for r in csv.DictReader(open(f)):
+            stats[r["Name"]] = r
+    cmd = "python3 bench.py --polymul-only --steps 20 --warmup 5"
+    lines = ["# Kernel trace: ntt_polymul at polymul_n65536_l24 (N=2^16, 24 limbs, 2 products of 2 components), "
+             "MI355X", "",
+             "Command (repository root on the GPU box):", "",
+             f"    rocprofv3 --kernel-trace --stats --output-format csv -d <dir>/kt -o kt -- {cmd} > <dir>/bench.json",
+             f"    python3 bench.py --summarize-polymul-trace <dir>", "",
+             f"Kernel source hash: {kernel_source_hash(KERNEL_SOURCES + ['paper_2405_11353_amd/csrc/k_polymul.hip'])}",
+             "", "| kernel | role | calls | rocprof avg us |", "|---|---|---|---|"]
+    per_step = 0.0
+    for pat, role in POLYMUL_TRACE_KEYS:
+        rows = [r for n, r in stats.items() if pat in n]
+        if not rows:
+            continue
+        r = rows[0]
+        avg = float(r["AverageNs"]) / 1e3
+        per_step += avg
+        name = r["Name"].split("(")[0].replace("void ", "")
+        lines.append(f"| `{name}` | {role} | {r['Calls']} | {avg:.2f} |")
+    lines.append("")
+    lines.append(f"Sum of the three kernels per step: {per_step:.1f} us.")
+    bj = os.path.join(d, "bench.json")
+    if os.path.exists(bj):
+        res = json.loads(open(bj).read().strip().splitlines()[-1])
+        st = res.get("streams_1", {})
+        lines.append(f"The same run's `bench.py` step time on one stream (wall clock, launches included): "
+                     f"{st.get('us_per_step')} us, {st.get('ntt_equivalent_per_s', 0) / 1e6:.3f} M NTT-equivalent/s.")
+    out = os.path.join(ROOT, "profiles", "polymul_fused_n65536_l24_trace.md")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     args = parse()
     if args.summarize_counters:
@@ -801,6 +853,9 @@ def main():
         return
     if args.summarize_he_counters:
         summarize_counters(args.summarize_he_counters, he=True)
+        return
+    if args.summarize_polymul_trace:
+        summarize_polymul_trace(args.summarize_polymul_trace)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -816,6 +871,11 @@ def main():
     torch.cuda.set_device(0)
     if args.he_only:
         print(json.dumps(bench_he_steps(ntt, si, torch)), flush=True)
+        return
+    if args.polymul_only:
+        # one stream, so a kernel trace of this run holds unoverlapped launches
+        print(json.dumps(bench_polymul(ntt, si, torch, steps=args.steps, warm=args.warmup, stream_counts=(1,))),
+              flush=True)
         return
     w = si.workload_polymul_n16()
     N, moduli, L = w.N, w.moduli, len(w.moduli)
