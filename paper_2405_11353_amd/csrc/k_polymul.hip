@@ -8,15 +8,15 @@
 
 namespace nttk {
 
-// 16 rows per workgroup, N2/16 threads per row (a row lies inside one wave,
-// so every exchange is wave-local). The forward phases leave thread t holding
+// 16 rows per workgroup, N2/V threads per row (V = 2^LV values each; a row
+// lies inside one wave, so every exchange is wave-local). The forward phases leave thread t holding
 // positions pos(last phase, t, i) of each row, which is the layout the
 // inverse phases start from, so the product needs no exchange.
 // IND: items come from a descriptor table (data: a's column-pass output,
 // overwritten with the product; aux: b's; twiddles and modulus per item), as
 // in the server's batches.
-template <class A, int LOGN2, bool IND = false>
-__global__ void __launch_bounds__(16 << (LOGN2 - 4))
+template <class A, int LOGN2, bool IND = false, int LV = 4>
+__global__ void __launch_bounds__(16 << (LOGN2 - LV))
 k_row_polymul(typename A::word* sa, const typename A::word* __restrict__ sb,
               const typename A::tw_t* __restrict__ twf_all, const typename A::tw_t* __restrict__ twi_all,
               const typename ModOf<A>::type* __restrict__ mods, uint32_t L, uint32_t logN, uint32_t batch,
@@ -24,8 +24,9 @@ k_row_polymul(typename A::word* sa, const typename A::word* __restrict__ sb,
   using W = typename A::word;
   using TW = typename A::tw_t;
   using M = typename ModOf<A>::type;
-  using S = Sched<LOGN2>;
-  constexpr uint32_t N2 = 1u << LOGN2, TPR = N2 / 16, RSTR = N2 + N2 / 16 + 1;
+  using S = Sched<LOGN2, LV>;
+  constexpr int V = 1 << LV;
+  constexpr uint32_t N2 = 1u << LOGN2, TPR = N2 / V, RSTR = N2 + N2 / 16 + 1;
   static_assert(TPR <= 64, "a row must fit in one wavefront");
   __shared__ W lds[16 * RSTR];
   __shared__ TW tw0[16][17];  // first-phase twiddles of the 16 rows: forward, then inverse
@@ -70,23 +71,23 @@ k_row_polymul(typename A::word* sa, const typename A::word* __restrict__ sb,
   W* sh = lds + rl * RSTR;
   auto row_of = [&](uint32_t row) { return tile * 16 + row; };
 
-  W va[16], vb[16];
-  stage_first_phase<LOGN2>(tw0, twf, logN1, row_of);
+  W va[V], vb[V];
+  stage_first_phase<LOGN2, LV>(tw0, twf, logN1, row_of);
 #pragma unroll
-  for (int i = 0; i < 16; ++i) va[i] = rowa[i * TPR + t];
+  for (int i = 0; i < V; ++i) va[i] = rowa[i * TPR + t];
   wave_lds_sync();
 
-  auto forward = [&](W (&v)[16], const TW* twf) {
+  auto forward = [&](W (&v)[V], const TW* twf) {
     static_for<0, S::NPH>([&](auto P_) {
       constexpr int p = decltype(P_)::value;
       if constexpr (p > 0) {
         wave_lds_sync();
 #pragma unroll
-        for (int i = 0; i < 16; ++i) sh[pad16(pos<LOGN2>(p - 1, t, i))] = v[i];
+        for (int i = 0; i < V; ++i) sh[pad16(pos<LOGN2, LV>(p - 1, t, i))] = v[i];
         wave_lds_sync();
 #pragma unroll
-        for (int i = 0; i < 16; ++i) v[i] = sh[pad16(pos<LOGN2>(p, t, i))];
-        ct_phase<A, S::rs(p)>(a, v, twf, logN1 + S::s0(p), (r << S::s0(p)) + grp<LOGN2>(p, t));
+        for (int i = 0; i < V; ++i) v[i] = sh[pad16(pos<LOGN2, LV>(p, t, i))];
+        ct_phase<A, S::rs(p)>(a, v, twf, logN1 + S::s0(p), (r << S::s0(p)) + grp<LOGN2, LV>(p, t));
       } else {
         ct_phase<A, S::rs(p)>(a, v, &tw0[rl][0], 0u, 0u);
       }
@@ -97,9 +98,9 @@ k_row_polymul(typename A::word* sa, const typename A::word* __restrict__ sb,
   // before b's row is loaded
   forward(va, twf);
 #pragma unroll
-  for (int i = 0; i < 16; ++i) va[i] = a.canon_fwd(va[i]);
+  for (int i = 0; i < V; ++i) va[i] = a.canon_fwd(va[i]);
 #pragma unroll
-  for (int i = 0; i < 16; ++i) vb[i] = rowb[i * TPR + t];
+  for (int i = 0; i < V; ++i) vb[i] = rowb[i * TPR + t];
   // b's transform reads the same twiddles; an opaque copy of the table
   // pointer makes the compiler load them again (cache hits) instead of
   // keeping all of a's twiddles live across both transforms
@@ -107,28 +108,37 @@ k_row_polymul(typename A::word* sa, const typename A::word* __restrict__ sb,
   asm volatile("" : "+v"(twf_b));
   forward(vb, twf_b);
 #pragma unroll
-  for (int i = 0; i < 16; ++i) va[i] = mulmod_general(va[i], a.canon_fwd(vb[i]), m);
+  for (int i = 0; i < V; ++i) va[i] = mulmod_general(va[i], a.canon_fwd(vb[i]), m);
   // the wave's rows switch to the inverse table's first-phase twiddles; the
   // inverse phases' exchanges order the copy before their use
   wave_lds_sync();
-  stage_first_phase<LOGN2>(tw0, twi, logN1, row_of);
+  stage_first_phase<LOGN2, LV>(tw0, twi, logN1, row_of);
   static_for_down<S::NPH - 1, 0>([&](auto P_) {
     constexpr int p = decltype(P_)::value;
     if constexpr (p < S::NPH - 1) {
       wave_lds_sync();
 #pragma unroll
-      for (int i = 0; i < 16; ++i) sh[pad16(pos<LOGN2>(p + 1, t, i))] = va[i];
+      for (int i = 0; i < V; ++i) sh[pad16(pos<LOGN2, LV>(p + 1, t, i))] = va[i];
       wave_lds_sync();
 #pragma unroll
-      for (int i = 0; i < 16; ++i) va[i] = sh[pad16(pos<LOGN2>(p, t, i))];
+      for (int i = 0; i < V; ++i) va[i] = sh[pad16(pos<LOGN2, LV>(p, t, i))];
     }
     if constexpr (p == 0) gs_phase<A, S::rs(p), false>(a, va, &tw0[rl][0], 0u, 0u);
-    else gs_phase<A, S::rs(p), false>(a, va, twi, logN1 + S::s0(p), (r << S::s0(p)) + grp<LOGN2>(p, t));
+    else gs_phase<A, S::rs(p), false>(a, va, twi, logN1 + S::s0(p), (r << S::s0(p)) + grp<LOGN2, LV>(p, t));
   });
   // phase 0 leaves thread t with positions i * TPR + t
 #pragma unroll
-  for (int i = 0; i < 16; ++i) rowa[i * TPR + t] = va[i];
+  for (int i = 0; i < V; ++i) rowa[i * TPR + t] = va[i];
 }
+
+// values per thread (2^LV) of the fused product kernel; rows of 2^9 keep 16
+// values per thread: at 8 a workgroup has 1024 threads, which caps a thread
+// at 128 registers, fewer than the two operands' rows need without spilling
+#ifndef NTT_LV_POLYMUL
+#define NTT_LV_POLYMUL 4
+#endif
+static_assert(NTT_LV_POLYMUL == 3 || NTT_LV_POLYMUL == 4, "8 or 16 values per thread");
+constexpr int pm_lv(int lg2) { return lg2 >= 9 ? 4 : NTT_LV_POLYMUL; }
 
 template <class A>
 static hipError_t go(int logN, int logN1, void* sa, const void* sb, const void* twf, const void* twi,
@@ -139,11 +149,12 @@ static hipError_t go(int logN, int logN1, void* sa, const void* sb, const void* 
   const int lg2 = logN - logN1;
   if (logN1 < 6 || logN1 > 9 || lg2 < 6 || lg2 > 9) return hipErrorNotSupported;
   const uint32_t tiles = (1u << logN1) / 16;
-  const dim3 grid(batch * L * tiles), block(16u << (lg2 - 4));
+  const dim3 grid(batch * L * tiles);
 #define POLYMUL_CASE(LG2)                                                                                  \
   case LG2:                                                                                                \
-    hipLaunchKernelGGL((k_row_polymul<A, LG2>), grid, block, 0, s, (W*)sa, (const W*)sb, (const TW*)twf, \
-                       (const TW*)twi, (const M*)mods, L, (uint32_t)logN, batch);                          \
+    hipLaunchKernelGGL((k_row_polymul<A, LG2, false, pm_lv(LG2)>), grid, dim3(16u << (LG2 - pm_lv(LG2))), 0, s, \
+                       (W*)sa, (const W*)sb, (const TW*)twf, (const TW*)twi, (const M*)mods, L, (uint32_t)logN,   \
+                       batch);                                                                             \
     break;
   switch (lg2) {
     POLYMUL_CASE(6)
@@ -167,11 +178,11 @@ hipError_t launch_ind_row_polymul(const ItemDesc* desc, uint32_t items, int logN
   const int lg2 = logN - logN1;
   if (items == 0) return hipSuccess;
   if (logN1 < 6 || logN1 > 9 || lg2 < 6 || lg2 > 9) return hipErrorNotSupported;
-  const dim3 grid(items * ((1u << logN1) / 16)), block(16u << (lg2 - 4));
+  const dim3 grid(items * ((1u << logN1) / 16));
 #define IND_CASE(LG2)                                                                                      \
   case LG2:                                                                                                \
-    hipLaunchKernelGGL((k_row_polymul<A, LG2, true>), grid, block, 0, s, nullptr, nullptr, nullptr, nullptr, \
-                       nullptr, 1u, (uint32_t)logN, items, desc);                                          \
+    hipLaunchKernelGGL((k_row_polymul<A, LG2, true, pm_lv(LG2)>), grid, dim3(16u << (LG2 - pm_lv(LG2))), 0, s,  \
+                       nullptr, nullptr, nullptr, nullptr, nullptr, 1u, (uint32_t)logN, items, desc);      \
     break;
   switch (lg2) {
     IND_CASE(6)

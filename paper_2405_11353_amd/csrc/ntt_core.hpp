@@ -72,30 +72,32 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t bid, uint32_t G) {
 }
 
 // ----------------------------------------------------------- phase schedule
-template <int LOGN> struct Sched {
-  static_assert(LOGN >= 4, "16 values per thread need N >= 16");
-  static constexpr int R0 = LOGN % 4;
-  static constexpr int NPH = LOGN / 4 + (R0 ? 1 : 0);
-  __host__ __device__ static constexpr int rs(int p) { return (R0 && p == 0) ? R0 : 4; }
-  __host__ __device__ static constexpr int s0(int p) { return p == 0 ? 0 : (R0 ? R0 + 4 * (p - 1) : 4 * p); }
-  __host__ __device__ static constexpr int lgs(int p) { return LOGN - s0(p) - 4; }  // log2 of the stride
+// A thread holds V = 2^LV values (16 by default, 8 where more threads pay)
+// and applies up to LV stages to them per phase.
+template <int LOGN, int LV = 4> struct Sched {
+  static_assert(LOGN >= LV, "N must hold at least V values per thread");
+  static constexpr int R0 = LOGN % LV;
+  static constexpr int NPH = LOGN / LV + (R0 ? 1 : 0);
+  __host__ __device__ static constexpr int rs(int p) { return (R0 && p == 0) ? R0 : LV; }
+  __host__ __device__ static constexpr int s0(int p) { return p == 0 ? 0 : (R0 ? R0 + LV * (p - 1) : LV * p); }
+  __host__ __device__ static constexpr int lgs(int p) { return LOGN - s0(p) - LV; }  // log2 of the stride
 };
 
 // position of value i of thread t in phase p (transform-local)
-template <int LOGN>
+template <int LOGN, int LV = 4>
 __device__ __forceinline__ uint32_t pos(int p, uint32_t t, int i) {
-  const int lg = Sched<LOGN>::lgs(p);
+  const int lg = Sched<LOGN, LV>::lgs(p);
   const uint32_t H = t >> lg, low = t & ((1u << lg) - 1u);
-  return (H << (lg + 4)) + ((uint32_t)i << lg) + low;
+  return (H << (lg + LV)) + ((uint32_t)i << lg) + low;
 }
 // group index of thread t at the first stage of phase p (transform-local)
-template <int LOGN>
-__device__ __forceinline__ uint32_t grp(int p, uint32_t t) { return t >> Sched<LOGN>::lgs(p); }
+template <int LOGN, int LV = 4>
+__device__ __forceinline__ uint32_t grp(int p, uint32_t t) { return t >> Sched<LOGN, LV>::lgs(p); }
 
 // ----------------------------------------------------------- register phases
 // RS stages starting at global stage S0; Hg = global group index at S0.
-template <class A, int RS>
-__device__ __forceinline__ void ct_phase(const A& a, typename A::word (&v)[16],
+template <class A, int RS, int V>
+__device__ __forceinline__ void ct_phase(const A& a, typename A::word (&v)[V],
                                          const typename A::tw_t* __restrict__ tw, uint32_t S0, uint32_t Hg) {
 #pragma unroll
   for (int k = 0; k < RS; ++k) {
@@ -104,9 +106,9 @@ __device__ __forceinline__ void ct_phase(const A& a, typename A::word (&v)[16],
     for (int j = 0; j < (1 << k); ++j) {
       const typename A::tw_t w = tk[j];
 #pragma unroll
-      for (int m = 0; m < (8 >> k); ++m) {
-        const int i0 = j * (16 >> k) + m;
-        a.ct(v[i0], v[i0 + (8 >> k)], w);
+      for (int m = 0; m < ((V / 2) >> k); ++m) {
+        const int i0 = j * (V >> k) + m;
+        a.ct(v[i0], v[i0 + ((V / 2) >> k)], w);
       }
     }
   }
@@ -114,24 +116,24 @@ __device__ __forceinline__ void ct_phase(const A& a, typename A::word (&v)[16],
 
 // Inverse: the same pairs, stages in reverse order. HAS0: this phase contains
 // global stage 0, whose two outputs are both scaled (tables slots 0 and 1).
-template <class A, int RS, bool HAS0>
-__device__ __forceinline__ void gs_phase(const A& a, typename A::word (&v)[16],
+template <class A, int RS, bool HAS0, int V>
+__device__ __forceinline__ void gs_phase(const A& a, typename A::word (&v)[V],
                                          const typename A::tw_t* __restrict__ tw, uint32_t S0, uint32_t Hg) {
 #pragma unroll
   for (int k = RS - 1; k >= 0; --k) {
     if (HAS0 && k == 0) {
       const typename A::tw_t w0 = tw[0], w1 = tw[1];
 #pragma unroll
-      for (int m = 0; m < 8; ++m) a.gs_last(v[m], v[m + 8], w0, w1);
+      for (int m = 0; m < V / 2; ++m) a.gs_last(v[m], v[m + V / 2], w0, w1);
     } else {
       const typename A::tw_t* tk = tw + (1u << (S0 + k)) + (Hg << k);
 #pragma unroll
       for (int j = 0; j < (1 << k); ++j) {
         const typename A::tw_t w = tk[j];
 #pragma unroll
-        for (int m = 0; m < (8 >> k); ++m) {
-          const int i0 = j * (16 >> k) + m;
-          a.gs(v[i0], v[i0 + (8 >> k)], w);
+        for (int m = 0; m < ((V / 2) >> k); ++m) {
+          const int i0 = j * (V >> k) + m;
+          a.gs(v[i0], v[i0 + ((V / 2) >> k)], w);
         }
       }
     }
@@ -271,20 +273,21 @@ __device__ __forceinline__ void st_data(T* p, T v) {
 }
 
 // ============================================================ column pass
-// NC columns per workgroup, N1/16 threads per column; columns are adjacent so
-// each row segment read or written is NC words (128 bytes).
+// NC columns per workgroup, N1/V threads per column (V = 2^LV values each);
+// columns are adjacent so each row segment read or written is NC words.
 // Forward: global stages [0, logN1), out-of-place allowed (in == out is fine).
 // Inverse: global stages [logN1-1 .. 0] with the N^-1 fold, canonical output.
-template <class A, int LOGN1, int NC, bool FWD, bool IND = false>
-__global__ void __launch_bounds__(NC << (LOGN1 - 4))
+template <class A, int LOGN1, int NC, bool FWD, bool IND = false, int LV = 4>
+__global__ void __launch_bounds__(NC << (LOGN1 - LV))
 k_col(const typename A::word* in, typename A::word* out, const typename A::tw_t* __restrict__ tw_all,
       const typename ModOf<A>::type* __restrict__ mods, uint32_t L, uint32_t logN, uint32_t items,
       const ItemDesc* __restrict__ desc = nullptr, int io = 0) {
   using W = typename A::word;
   using TW = typename A::tw_t;
   using M = typename ModOf<A>::type;
-  using S = Sched<LOGN1>;
-  constexpr uint32_t N1 = 1u << LOGN1, TPC = N1 / 16, LD = NC + 1;
+  using S = Sched<LOGN1, LV>;
+  constexpr int V = 1 << LV;
+  constexpr uint32_t N1 = 1u << LOGN1, TPC = N1 / V, LD = NC + 1;
   __shared__ W lds[N1 * LD];
   // forward: the table slots [0, N1) in LDS for the phases after the first,
   // written at the start and published by the first exchange's barrier
@@ -318,10 +321,10 @@ k_col(const typename A::word* in, typename A::word* out, const typename A::tw_t*
     src = in + base;
     dst = out + base;
   }
-  W v[16];
+  W v[V];
   if constexpr (FWD) {
 #pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = ld_data<NT_LD_IN>(src + (size_t)(i * TPC + t) * N2);
+    for (int i = 0; i < V; ++i) v[i] = ld_data<NT_LD_IN>(src + (size_t)(i * TPC + t) * N2);
     if constexpr (TWL) {
       for (uint32_t k = threadIdx.x; k < N1; k += blockDim.x) twl[k] = tw[k];
     }
@@ -330,34 +333,34 @@ k_col(const typename A::word* in, typename A::word* out, const typename A::tw_t*
       if constexpr (p > 0) {
         if constexpr (p > 1) __syncthreads();
 #pragma unroll
-        for (int i = 0; i < 16; ++i) lds[pos<LOGN1>(p - 1, t, i) * LD + c] = v[i];
+        for (int i = 0; i < V; ++i) lds[pos<LOGN1, LV>(p - 1, t, i) * LD + c] = v[i];
         __syncthreads();
 #pragma unroll
-        for (int i = 0; i < 16; ++i) v[i] = lds[pos<LOGN1>(p, t, i) * LD + c];
-        ct_phase<A, S::rs(p)>(a, v, twl, S::s0(p), grp<LOGN1>(p, t));
+        for (int i = 0; i < V; ++i) v[i] = lds[pos<LOGN1, LV>(p, t, i) * LD + c];
+        ct_phase<A, S::rs(p)>(a, v, twl, S::s0(p), grp<LOGN1, LV>(p, t));
       } else {
         ct_phase<A, S::rs(p)>(a, v, tw, 0u, 0u);
       }
     });
 #pragma unroll
-    for (int i = 0; i < 16; ++i) st_data<NT_ST_MID>(dst + (size_t)pos<LOGN1>(S::NPH - 1, t, i) * N2, v[i]);
+    for (int i = 0; i < V; ++i) st_data<NT_ST_MID>(dst + (size_t)pos<LOGN1, LV>(S::NPH - 1, t, i) * N2, v[i]);
   } else {
 #pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = ld_data<NT_LD_MID>(src + (size_t)pos<LOGN1>(S::NPH - 1, t, i) * N2);
+    for (int i = 0; i < V; ++i) v[i] = ld_data<NT_LD_MID>(src + (size_t)pos<LOGN1, LV>(S::NPH - 1, t, i) * N2);
     static_for_down<S::NPH - 1, 0>([&](auto P_) {
       constexpr int p = decltype(P_)::value;
       if constexpr (p < S::NPH - 1) {
         if constexpr (p < S::NPH - 2) __syncthreads();
 #pragma unroll
-        for (int i = 0; i < 16; ++i) lds[pos<LOGN1>(p + 1, t, i) * LD + c] = v[i];
+        for (int i = 0; i < V; ++i) lds[pos<LOGN1, LV>(p + 1, t, i) * LD + c] = v[i];
         __syncthreads();
 #pragma unroll
-        for (int i = 0; i < 16; ++i) v[i] = lds[pos<LOGN1>(p, t, i) * LD + c];
+        for (int i = 0; i < V; ++i) v[i] = lds[pos<LOGN1, LV>(p, t, i) * LD + c];
       }
-      gs_phase<A, S::rs(p), p == 0>(a, v, tw, S::s0(p), p == 0 ? 0u : grp<LOGN1>(p, t));
+      gs_phase<A, S::rs(p), p == 0>(a, v, tw, S::s0(p), p == 0 ? 0u : grp<LOGN1, LV>(p, t));
     });
 #pragma unroll
-    for (int i = 0; i < 16; ++i) st_data<NT_ST_OUT>(dst + (size_t)(i * TPC + t) * N2, a.canon_inv(v[i]));
+    for (int i = 0; i < V; ++i) st_data<NT_ST_OUT>(dst + (size_t)(i * TPC + t) * N2, a.canon_inv(v[i]));
   }
 }
 
@@ -366,13 +369,13 @@ k_col(const typename A::word* in, typename A::word* out, const typename A::tw_t*
 // 2^rs(0) - 1 twiddles of the row's own subtree: slot 2^k + j of row r is
 // table entry 2^(logN1 + k) + (r << k) + j. Each wave copies those of its own
 // 64 / TPR rows into LDS (lane q * 2^rs(0) + u: row q, slot u; at most 64
-// lanes for every LOGN2 from 6 to 9; rows padded to 17 entries so the wave's
-// rows fall in different LDS banks) and orders the copy with the wavefront
+// lanes for every LOGN2 from 6 to 9 and 8 or 16 values per thread; rows padded
+// to 17 entries so the wave's rows fall in different LDS banks) and orders the copy with the wavefront
 // sync it already needs, so that phase reads no twiddle from global memory
 // between butterflies. row_of(rl) is the matrix row of workgroup row rl.
-template <int LOGN2, class TW, class F>
+template <int LOGN2, int LV, class TW, class F>
 __device__ __forceinline__ void stage_first_phase(TW (*tw0)[17], const TW* tw, uint32_t logN1, F row_of) {
-  constexpr uint32_t TPR = (1u << LOGN2) / 16, RPW = 64 / TPR, RS0 = Sched<LOGN2>::rs(0), SL = 1u << RS0;
+  constexpr uint32_t TPR = (1u << LOGN2) >> LV, RPW = 64 / TPR, RS0 = Sched<LOGN2, LV>::rs(0), SL = 1u << RS0;
   static_assert(RPW * SL <= 64 && SL <= 16, "one lane per first-phase twiddle of the wave's rows");
   const uint32_t lane = threadIdx.x & 63u, q = lane / SL, u = lane % SL;
   const uint32_t rl = (threadIdx.x >> 6) * RPW + q;  // the rows this wave transforms
@@ -383,16 +386,17 @@ __device__ __forceinline__ void stage_first_phase(TW (*tw0)[17], const TW* tw, u
 }
 
 // ============================================================ row pass
-// 16 rows per workgroup, N2/16 threads per row (a row never spans two waves,
-// so exchanges between phases only need wavefront ordering).
+// 16 rows per workgroup, N2/V threads per row (V = 2^LV values each; a row
+// never spans two waves, so exchanges between phases only need wavefront
+// ordering).
 // Forward: global stages [logN1, logN), canonical output; NATURAL writes
 // element (r, c) to brv(c) * N1 + brv(r) with rows r = brv(k1), k1 in the tile.
 // Inverse: reads that layout (or rows in place), runs the row stages
 // backwards and writes rows in lazy range for the column pass.
 // MULIN (inverse only): the input is in * in2 elementwise mod q (the pointwise
 // product fused into the load), read from two buffers.
-template <class A, int LOGN2, bool FWD, bool NATURAL, bool MULIN = false, bool IND = false>
-__global__ void __launch_bounds__(16 << (LOGN2 - 4))
+template <class A, int LOGN2, bool FWD, bool NATURAL, bool MULIN = false, bool IND = false, int LV = 4>
+__global__ void __launch_bounds__(16 << (LOGN2 - LV))
 k_row(const typename A::word* in, typename A::word* out, const typename A::tw_t* __restrict__ tw_all,
       const typename ModOf<A>::type* __restrict__ mods, uint32_t L, uint32_t logN, uint32_t items,
       uint32_t batch, const typename A::word* in2 = nullptr, const ItemDesc* __restrict__ desc = nullptr,
@@ -400,8 +404,9 @@ k_row(const typename A::word* in, typename A::word* out, const typename A::tw_t*
   using W = typename A::word;
   using TW = typename A::tw_t;
   using M = typename ModOf<A>::type;
-  using S = Sched<LOGN2>;
-  constexpr uint32_t N2 = 1u << LOGN2, TPR = N2 / 16, RSTR = N2 + N2 / 16 + 1;
+  using S = Sched<LOGN2, LV>;
+  constexpr int V = 1 << LV;
+  constexpr uint32_t N2 = 1u << LOGN2, TPR = N2 / V, RSTR = N2 + N2 / 16 + 1;
   static_assert(TPR <= 64, "a row must fit in one wavefront");
   __shared__ W lds[16 * RSTR];
   __shared__ TW tw0[16][17];  // first-phase twiddles of the 16 rows
@@ -436,24 +441,24 @@ k_row(const typename A::word* in, typename A::word* out, const typename A::tw_t*
   }
   a.load(*mi);
   W* sh = lds + rl * RSTR;
-  W v[16];
-  stage_first_phase<LOGN2>(tw0, tw, logN1,
+  W v[V];
+  stage_first_phase<LOGN2, LV>(tw0, tw, logN1,
                            [&](uint32_t row) { return NATURAL ? brv(tile * 16 + row, logN1) : tile * 16 + row; });
   if constexpr (FWD) {
     const W* src = in + pbase + (size_t)r * N2;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = ld_data<NT_LD_MID>(src + i * TPR + t);
+    for (int i = 0; i < V; ++i) v[i] = ld_data<NT_LD_MID>(src + i * TPR + t);
     wave_lds_sync();
     static_for<0, S::NPH>([&](auto P_) {
       constexpr int p = decltype(P_)::value;
       if constexpr (p > 0) {
         if constexpr (p > 1) wave_lds_sync();
 #pragma unroll
-        for (int i = 0; i < 16; ++i) sh[pad16(pos<LOGN2>(p - 1, t, i))] = v[i];
+        for (int i = 0; i < V; ++i) sh[pad16(pos<LOGN2, LV>(p - 1, t, i))] = v[i];
         wave_lds_sync();
 #pragma unroll
-        for (int i = 0; i < 16; ++i) v[i] = sh[pad16(pos<LOGN2>(p, t, i))];
-        ct_phase<A, S::rs(p)>(a, v, tw, logN1 + S::s0(p), (r << S::s0(p)) + grp<LOGN2>(p, t));
+        for (int i = 0; i < V; ++i) v[i] = sh[pad16(pos<LOGN2, LV>(p, t, i))];
+        ct_phase<A, S::rs(p)>(a, v, tw, logN1 + S::s0(p), (r << S::s0(p)) + grp<LOGN2, LV>(p, t));
       } else {
         ct_phase<A, S::rs(p)>(a, v, &tw0[rl][0], 0u, 0u);
       }
@@ -461,23 +466,23 @@ k_row(const typename A::word* in, typename A::word* out, const typename A::tw_t*
     if constexpr (NATURAL) {
       if (S::NPH > 1) wave_lds_sync();
 #pragma unroll
-      for (int i = 0; i < 16; ++i) sh[pad16(pos<LOGN2>(S::NPH - 1, t, i))] = a.canon_fwd(v[i]);
+      for (int i = 0; i < V; ++i) sh[pad16(pos<LOGN2, LV>(S::NPH - 1, t, i))] = a.canon_fwd(v[i]);
       __syncthreads();
       const uint32_t rr = threadIdx.x % 16, cg = threadIdx.x / 16;
       W* dst = out + pbase + tile * 16 + rr;
 #pragma unroll
-      for (int j = 0; j < 16; ++j) {
+      for (int j = 0; j < V; ++j) {
         const uint32_t cc = cg + TPR * j;
         st_data<NT_ST_OUT>(dst + (size_t)brv(cc, LOGN2) * N1, lds[rr * RSTR + pad16(cc)]);
       }
     } else {
       if (S::NPH > 1) wave_lds_sync();
 #pragma unroll
-      for (int i = 0; i < 16; ++i) sh[pad16(pos<LOGN2>(S::NPH - 1, t, i))] = a.canon_fwd(v[i]);
+      for (int i = 0; i < V; ++i) sh[pad16(pos<LOGN2, LV>(S::NPH - 1, t, i))] = a.canon_fwd(v[i]);
       wave_lds_sync();
       W* dst = out + pbase + (size_t)r * N2;
 #pragma unroll
-      for (int i = 0; i < 16; ++i) st_data<NT_ST_OUT>(dst + i * TPR + t, sh[pad16(i * TPR + t)]);
+      for (int i = 0; i < V; ++i) st_data<NT_ST_OUT>(dst + i * TPR + t, sh[pad16(i * TPR + t)]);
     }
   } else {
     if constexpr (NATURAL) {
@@ -485,7 +490,7 @@ k_row(const typename A::word* in, typename A::word* out, const typename A::tw_t*
       const size_t off = pbase + tile * 16 + rr;
       const W* src = in + off;
 #pragma unroll
-      for (int j = 0; j < 16; ++j) {
+      for (int j = 0; j < V; ++j) {
         const uint32_t cc = cg + TPR * j;
         const size_t e = (size_t)brv(cc, LOGN2) * N1;
         W val = ld_data<NT_LD_IN>(src + e);
@@ -497,7 +502,7 @@ k_row(const typename A::word* in, typename A::word* out, const typename A::tw_t*
       const size_t off = pbase + (size_t)r * N2;
       const W* src = in + off;
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
+      for (int i = 0; i < V; ++i) {
         W val = ld_data<NT_LD_IN>(src + i * TPR + t);
         if constexpr (MULIN) val = mulmod_general(val, ld_data<NT_LD_IN>(in2 + off + i * TPR + t), *mi);
         sh[pad16(i * TPR + t)] = val;
@@ -505,23 +510,23 @@ k_row(const typename A::word* in, typename A::word* out, const typename A::tw_t*
       wave_lds_sync();
     }
 #pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = sh[pad16(pos<LOGN2>(S::NPH - 1, t, i))];
+    for (int i = 0; i < V; ++i) v[i] = sh[pad16(pos<LOGN2, LV>(S::NPH - 1, t, i))];
     static_for_down<S::NPH - 1, 0>([&](auto P_) {
       constexpr int p = decltype(P_)::value;
       if constexpr (p < S::NPH - 1) {
         wave_lds_sync();
 #pragma unroll
-        for (int i = 0; i < 16; ++i) sh[pad16(pos<LOGN2>(p + 1, t, i))] = v[i];
+        for (int i = 0; i < V; ++i) sh[pad16(pos<LOGN2, LV>(p + 1, t, i))] = v[i];
         wave_lds_sync();
 #pragma unroll
-        for (int i = 0; i < 16; ++i) v[i] = sh[pad16(pos<LOGN2>(p, t, i))];
+        for (int i = 0; i < V; ++i) v[i] = sh[pad16(pos<LOGN2, LV>(p, t, i))];
       }
       if constexpr (p == 0) gs_phase<A, S::rs(p), false>(a, v, &tw0[rl][0], 0u, 0u);
-      else gs_phase<A, S::rs(p), false>(a, v, tw, logN1 + S::s0(p), (r << S::s0(p)) + grp<LOGN2>(p, t));
+      else gs_phase<A, S::rs(p), false>(a, v, tw, logN1 + S::s0(p), (r << S::s0(p)) + grp<LOGN2, LV>(p, t));
     });
     W* dst = out + pbase + (size_t)r * N2;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) st_data<NT_ST_MID>(dst + i * TPR + t, v[i]);
+    for (int i = 0; i < V; ++i) st_data<NT_ST_MID>(dst + i * TPR + t, v[i]);
   }
 }
 
@@ -549,18 +554,18 @@ k_row(const typename A::word* in, typename A::word* out, const typename A::tw_t*
 // phase group Hg reads group g = (Hg << k) + j, so the groups are stored as
 // (j << S0) + Hg: for each j, the lanes of a row read consecutive entries
 // instead of entries 2^k apart (which fall in the same LDS banks).
-template <int LOGN2>
+template <int LOGN2, int LV = 4>
 __device__ __forceinline__ uint32_t cyc_pos(uint32_t m) {
-  using S = Sched<LOGN2>;
+  using S = Sched<LOGN2, LV>;
   if (m < 2) return m;
   const uint32_t s = 31u - (uint32_t)__builtin_clz(m);
-  const uint32_t S0 = (S::R0 && s < (uint32_t)S::R0) ? 0u : (S::R0 ? S::R0 + ((s - S::R0) & ~3u) : (s & ~3u));
+  const uint32_t S0 = (S::R0 && s < (uint32_t)S::R0) ? 0u : (S::R0 ? S::R0 + ((s - S::R0) / LV) * LV : (s / LV) * LV);
   const uint32_t k = s - S0, g = m - (1u << s);
   return (1u << s) + ((g & ((1u << k) - 1u)) << S0) + (g >> k);
 }
 
-template <class A, int RS, bool FIRST>
-__device__ __forceinline__ void ct_phase_cyc(const A& a, typename A::word (&v)[16], const typename A::tw_t* tw,
+template <class A, int RS, bool FIRST, int V>
+__device__ __forceinline__ void ct_phase_cyc(const A& a, typename A::word (&v)[V], const typename A::tw_t* tw,
                                              uint32_t S0, uint32_t Hg) {
 #pragma unroll
   for (int k = 0; k < RS; ++k) {
@@ -568,20 +573,20 @@ __device__ __forceinline__ void ct_phase_cyc(const A& a, typename A::word (&v)[1
     for (int j = 0; j < (1 << k); ++j) {
       if (FIRST && j == 0) {
 #pragma unroll
-        for (int m = 0; m < (8 >> k); ++m) a.ct1(v[m], v[m + (8 >> k)]);
+        for (int m = 0; m < ((V / 2) >> k); ++m) a.ct1(v[m], v[m + ((V / 2) >> k)]);
       } else {
         const typename A::tw_t w = tw[(1u << (S0 + k)) + ((uint32_t)j << S0) + Hg];  // see cyc_pos
 #pragma unroll
-        for (int m = 0; m < (8 >> k); ++m) {
-          const int i0 = j * (16 >> k) + m;
-          a.ct(v[i0], v[i0 + (8 >> k)], w);
+        for (int m = 0; m < ((V / 2) >> k); ++m) {
+          const int i0 = j * (V >> k) + m;
+          a.ct(v[i0], v[i0 + ((V / 2) >> k)], w);
         }
       }
     }
   }
 }
-template <class A, int RS, bool FIRST>
-__device__ __forceinline__ void gs_phase_cyc(const A& a, typename A::word (&v)[16], const typename A::tw_t* tw,
+template <class A, int RS, bool FIRST, int V>
+__device__ __forceinline__ void gs_phase_cyc(const A& a, typename A::word (&v)[V], const typename A::tw_t* tw,
                                              uint32_t S0, uint32_t Hg) {
 #pragma unroll
   for (int k = RS - 1; k >= 0; --k) {
@@ -589,31 +594,32 @@ __device__ __forceinline__ void gs_phase_cyc(const A& a, typename A::word (&v)[1
     for (int j = 0; j < (1 << k); ++j) {
       if (FIRST && j == 0) {
 #pragma unroll
-        for (int m = 0; m < (8 >> k); ++m) a.gs1(v[m], v[m + (8 >> k)]);
+        for (int m = 0; m < ((V / 2) >> k); ++m) a.gs1(v[m], v[m + ((V / 2) >> k)]);
       } else {
         const typename A::tw_t w = tw[(1u << (S0 + k)) + ((uint32_t)j << S0) + Hg];  // see cyc_pos
 #pragma unroll
-        for (int m = 0; m < (8 >> k); ++m) {
-          const int i0 = j * (16 >> k) + m;
-          a.gs(v[i0], v[i0 + (8 >> k)], w);
+        for (int m = 0; m < ((V / 2) >> k); ++m) {
+          const int i0 = j * (V >> k) + m;
+          a.gs(v[i0], v[i0 + ((V / 2) >> k)], w);
         }
       }
     }
   }
 }
 
-template <class A, int LOGN2, bool FWD, bool NATURAL, bool MULIN = false>
-__global__ void __launch_bounds__(16 << (LOGN2 - 4))
+template <class A, int LOGN2, bool FWD, bool NATURAL, bool MULIN = false, int LV = 4>
+__global__ void __launch_bounds__(16 << (LOGN2 - LV))
 k_row_tw(const typename A::word* in, typename A::word* out, const typename A::tw_t* __restrict__ twist_all,
          const typename A::tw_t* __restrict__ cyc_all, const typename ModOf<A>::type* __restrict__ mods,
          uint32_t L, uint32_t logN, uint32_t batch, const typename A::word* in2 = nullptr) {
   using W = typename A::word;
   using TW = typename A::tw_t;
-  using S = Sched<LOGN2>;
-  constexpr uint32_t N2 = 1u << LOGN2, TPR = N2 / 16, RSTR = N2 + N2 / 16 + 1;
+  using S = Sched<LOGN2, LV>;
+  constexpr int V = 1 << LV;
+  constexpr uint32_t N2 = 1u << LOGN2, TPR = N2 / V, RSTR = N2 + N2 / 16 + 1;
   static_assert(TPR <= 64, "a row must fit in one wavefront");
   __shared__ W lds[16 * RSTR];
-  __shared__ TW cyc[N2];  // one entry per thread of the workgroup
+  __shared__ TW cyc[N2];  // entry k written by thread k (the workgroup has N2 or 2 N2 threads)
   const uint32_t logN1 = logN - LOGN2, N1 = 1u << logN1;
   const uint32_t tiles = N1 / 16;
   const uint32_t bid = xcd_remap(blockIdx.x, gridDim.x);
@@ -627,60 +633,61 @@ k_row_tw(const typename A::word* in, typename A::word* out, const typename A::tw
   A a;
   const auto* mi = mods + l;
   a.load(*mi);
-  const TW cyc_entry = cyc_all[((size_t)l << LOGN2) + threadIdx.x];
+  const bool has_entry = threadIdx.x < N2;
+  const TW cyc_entry = cyc_all[((size_t)l << LOGN2) + (has_entry ? threadIdx.x : 0u)];
   const TW* twist = twist_all + ((size_t)l << logN) + (size_t)r * N2;
   const size_t pbase = (size_t)item << logN;
   W* sh = lds + rl * RSTR;
-  W v[16];
+  W v[V];
   if constexpr (FWD) {
     const W* src = in + pbase + (size_t)r * N2;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = ld_data<NT_LD_MID>(src + i * TPR + t);
-    cyc[cyc_pos<LOGN2>(threadIdx.x)] = cyc_entry;
+    for (int i = 0; i < V; ++i) v[i] = ld_data<NT_LD_MID>(src + i * TPR + t);
+    if (has_entry) cyc[cyc_pos<LOGN2, LV>(threadIdx.x)] = cyc_entry;
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = a.mul(v[i], twist[i * TPR + t]);
+    for (int i = 0; i < V; ++i) v[i] = a.mul(v[i], twist[i * TPR + t]);
     static_for<0, S::NPH>([&](auto P_) {
       constexpr int p = decltype(P_)::value;
       if constexpr (p > 0) {
         if constexpr (p > 1) wave_lds_sync();
 #pragma unroll
-        for (int i = 0; i < 16; ++i) sh[pad16(pos<LOGN2>(p - 1, t, i))] = v[i];
+        for (int i = 0; i < V; ++i) sh[pad16(pos<LOGN2, LV>(p - 1, t, i))] = v[i];
         wave_lds_sync();
 #pragma unroll
-        for (int i = 0; i < 16; ++i) v[i] = sh[pad16(pos<LOGN2>(p, t, i))];
+        for (int i = 0; i < V; ++i) v[i] = sh[pad16(pos<LOGN2, LV>(p, t, i))];
       }
-      ct_phase_cyc<A, S::rs(p), p == 0>(a, v, cyc, S::s0(p), grp<LOGN2>(p, t));
+      ct_phase_cyc<A, S::rs(p), p == 0>(a, v, cyc, S::s0(p), grp<LOGN2, LV>(p, t));
     });
     if constexpr (NATURAL) {
       if (S::NPH > 1) wave_lds_sync();
 #pragma unroll
-      for (int i = 0; i < 16; ++i) sh[pad16(pos<LOGN2>(S::NPH - 1, t, i))] = a.canon_fwd(v[i]);
+      for (int i = 0; i < V; ++i) sh[pad16(pos<LOGN2, LV>(S::NPH - 1, t, i))] = a.canon_fwd(v[i]);
       __syncthreads();
       const uint32_t rr = threadIdx.x % 16, cg = threadIdx.x / 16;
       W* dst = out + pbase + tile * 16 + rr;
 #pragma unroll
-      for (int j = 0; j < 16; ++j) {
+      for (int j = 0; j < V; ++j) {
         const uint32_t cc = cg + TPR * j;
         st_data<NT_ST_OUT>(dst + (size_t)brv(cc, LOGN2) * N1, lds[rr * RSTR + pad16(cc)]);
       }
     } else {
       if (S::NPH > 1) wave_lds_sync();
 #pragma unroll
-      for (int i = 0; i < 16; ++i) sh[pad16(pos<LOGN2>(S::NPH - 1, t, i))] = a.canon_fwd(v[i]);
+      for (int i = 0; i < V; ++i) sh[pad16(pos<LOGN2, LV>(S::NPH - 1, t, i))] = a.canon_fwd(v[i]);
       wave_lds_sync();
       W* dst = out + pbase + (size_t)r * N2;
 #pragma unroll
-      for (int i = 0; i < 16; ++i) st_data<NT_ST_OUT>(dst + i * TPR + t, sh[pad16(i * TPR + t)]);
+      for (int i = 0; i < V; ++i) st_data<NT_ST_OUT>(dst + i * TPR + t, sh[pad16(i * TPR + t)]);
     }
   } else {
-    cyc[cyc_pos<LOGN2>(threadIdx.x)] = cyc_entry;
+    if (has_entry) cyc[cyc_pos<LOGN2, LV>(threadIdx.x)] = cyc_entry;
     if constexpr (NATURAL) {
       const uint32_t rr = threadIdx.x % 16, cg = threadIdx.x / 16;
       const size_t off = pbase + tile * 16 + rr;
       const W* src = in + off;
 #pragma unroll
-      for (int j = 0; j < 16; ++j) {
+      for (int j = 0; j < V; ++j) {
         const uint32_t cc = cg + TPR * j;
         const size_t e = (size_t)brv(cc, LOGN2) * N1;
         W val = ld_data<NT_LD_IN>(src + e);
@@ -692,7 +699,7 @@ k_row_tw(const typename A::word* in, typename A::word* out, const typename A::tw
       const size_t off = pbase + (size_t)r * N2;
       const W* src = in + off;
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
+      for (int i = 0; i < V; ++i) {
         W val = ld_data<NT_LD_IN>(src + i * TPR + t);
         if constexpr (MULIN) val = mulmod_general(val, ld_data<NT_LD_IN>(in2 + off + i * TPR + t), *mi);
         sh[pad16(i * TPR + t)] = val;
@@ -700,23 +707,23 @@ k_row_tw(const typename A::word* in, typename A::word* out, const typename A::tw
       __syncthreads();
     }
 #pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = sh[pad16(pos<LOGN2>(S::NPH - 1, t, i))];
+    for (int i = 0; i < V; ++i) v[i] = sh[pad16(pos<LOGN2, LV>(S::NPH - 1, t, i))];
     static_for_down<S::NPH - 1, 0>([&](auto P_) {
       constexpr int p = decltype(P_)::value;
       if constexpr (p < S::NPH - 1) {
         wave_lds_sync();
 #pragma unroll
-        for (int i = 0; i < 16; ++i) sh[pad16(pos<LOGN2>(p + 1, t, i))] = v[i];
+        for (int i = 0; i < V; ++i) sh[pad16(pos<LOGN2, LV>(p + 1, t, i))] = v[i];
         wave_lds_sync();
 #pragma unroll
-        for (int i = 0; i < 16; ++i) v[i] = sh[pad16(pos<LOGN2>(p, t, i))];
+        for (int i = 0; i < V; ++i) v[i] = sh[pad16(pos<LOGN2, LV>(p, t, i))];
       }
-      gs_phase_cyc<A, S::rs(p), p == 0>(a, v, cyc, S::s0(p), grp<LOGN2>(p, t));
+      gs_phase_cyc<A, S::rs(p), p == 0>(a, v, cyc, S::s0(p), grp<LOGN2, LV>(p, t));
     });
     // first-phase layout: value i of thread t is row element i * TPR + t
     W* dst = out + pbase + (size_t)r * N2;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) st_data<NT_ST_MID>(dst + i * TPR + t, a.mul(v[i], twist[i * TPR + t]));
+    for (int i = 0; i < V; ++i) st_data<NT_ST_MID>(dst + i * TPR + t, a.mul(v[i], twist[i * TPR + t]));
   }
 }
 
