@@ -38,7 +38,8 @@ struct ModInfo64 {
   uint64_t qinv;  // q^-1 mod 2^64 (Montgomery reduction in the pointwise product)
   uint64_t r1;    // 2^64 mod q
   uint64_t r1p;   // floor(r1 * 2^64 / q), Shoup companion of r1
-  uint64_t pad0, pad1;
+  uint64_t n2q;   // 2^64 - 2q and 2^64 - 4q: the lazy reductions subtract 2q or
+  uint64_t n4q;   // 4q by one 64-bit add of these (no borrow chain)
 };
 
 struct Tw64 {
@@ -82,20 +83,29 @@ struct Arith64 {
   using word = uint64_t;
   using tw_t = Tw64;
   static constexpr bool kExact = EXACT;
-  uint64_t q, L, nq;
+  uint64_t q, L, nq, nL, n2q;
 
-  NTT_HD void load(const ModInfo64& m) { q = m.q; L = EXACT ? 2 * m.q : 4 * m.q; nq = m.nq; }
+  NTT_HD void load(const ModInfo64& m) {
+    q = m.q;
+    L = EXACT ? 2 * m.q : 4 * m.q;
+    nq = m.nq;
+    nL = EXACT ? m.n2q : m.n4q;
+    n2q = m.n2q;
+  }
 
   // y * w mod q, result in [0, L) (L = 4q approx, 2q exact), any y < 2^64
   NTT_HD uint64_t mul(uint64_t y, const Tw64& t) const {
     uint64_t Q = EXACT ? shoup_q_exact(y, t.wp) : shoup_q_approx(y, t.wp);
     return shoup_r(y, t.w, Q, nq);
   }
-  NTT_HD static uint64_t csub(uint64_t x, uint64_t m) { return x >= m ? x - m : x; }
+  // x - m if x >= m, else x; nm = 2^64 - m, so that the subtraction is a single
+  // 64-bit add instead of a subtract with borrow, whose carry register also
+  // costs wait states before the select can read it
+  NTT_HD static uint64_t csub(uint64_t x, uint64_t m, uint64_t nm) { return x >= m ? x + nm : x; }
 
   // Cooley-Tukey butterfly (x, y) -> (x + w y, x - w y); values in [0, 2L)
   NTT_HD void ct(uint64_t& x, uint64_t& y, const Tw64& t) const {
-    uint64_t xr = csub(x, L);
+    uint64_t xr = csub(x, L, nL);
     uint64_t T = mul(y, t);
     x = xr + T;
     y = xr + L - T;
@@ -104,21 +114,21 @@ struct Arith64 {
   NTT_HD void gs(uint64_t& x, uint64_t& y, const Tw64& t) const {
     uint64_t s = x + y;
     uint64_t d = x + L - y;
-    x = csub(s, L);
+    x = csub(s, L, nL);
     y = mul(d, t);
   }
   // butterflies whose twiddle is 1 (group 0 of a cyclic transform): both
   // inputs are reduced instead of multiplied, same ranges as ct / gs
   NTT_HD void ct1(uint64_t& x, uint64_t& y) const {
-    uint64_t xr = csub(x, L), yr = csub(y, L);
+    uint64_t xr = csub(x, L, nL), yr = csub(y, L, nL);
     x = xr + yr;
     y = xr + L - yr;
   }
   NTT_HD void gs1(uint64_t& x, uint64_t& y) const {
     uint64_t s = x + y;
     uint64_t d = x + L - y;
-    x = csub(s, L);
-    y = csub(d, L);
+    x = csub(s, L, nL);
+    y = csub(d, L, nL);
   }
   // last inverse stage: both outputs scaled (N^-1 folded into two twiddles)
   NTT_HD void gs_last(uint64_t& x, uint64_t& y, const Tw64& t0, const Tw64& t1) const {
@@ -129,13 +139,13 @@ struct Arith64 {
   }
   // canonical from [0, 2L) (forward) or [0, L) (inverse)
   NTT_HD uint64_t canon_fwd(uint64_t x) const {
-    x = csub(x, L);
-    if (!EXACT) x = csub(x, 2 * q);
-    return csub(x, q);
+    x = csub(x, L, nL);
+    if (!EXACT) x = csub(x, 2 * q, n2q);
+    return csub(x, q, nq);
   }
   NTT_HD uint64_t canon_inv(uint64_t x) const {
-    if (!EXACT) x = csub(x, 2 * q);
-    return csub(x, q);
+    if (!EXACT) x = csub(x, 2 * q, n2q);
+    return csub(x, q, nq);
   }
 };
 

@@ -190,6 +190,8 @@ void modinfo(uint64_t q, int word, void* out) {
     m[3] = inv;
     m[4] = r1;
     m[5] = (uint64_t)(((u128)r1 << 64) / q);
+    m[6] = 0 - 2 * q;
+    m[7] = 0 - 4 * q;
     memcpy(out, m, sizeof m);
   }
 }

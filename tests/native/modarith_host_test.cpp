@@ -41,6 +41,8 @@ static int test64(uint64_t q) {
   m.qinv = inv;
   m.r1 = (uint64_t)(((u128)1 << 64) % q);
   m.r1p = (uint64_t)(((u128)m.r1 << 64) / q);
+  m.n2q = 0 - 2 * q;
+  m.n4q = 0 - 4 * q;
   Arith64<false> A;
   A.load(m);
   Arith64<true> X;

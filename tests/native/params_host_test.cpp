@@ -42,6 +42,15 @@ int main() {
   auto rnd = [&]() { seed ^= seed << 13; seed ^= seed >> 7; seed ^= seed << 17; return seed; };
   for (const P& pr : primes) {
     const uint64_t q = pr.q;
+    if (pr.word == 64) {
+      // per-limb constants: q, -q, q^-1, 2^64 mod q and its companion, -2q, -4q (all mod 2^64)
+      uint64_t m[8];
+      nttp::modinfo(q, 64, m);
+      const uint64_t r1 = (uint64_t)(((u128)1 << 64) % q);
+      expect(m[0] == q && m[2] + q == 0 && m[3] * q == 1 && m[4] == r1, "modinfo", q, 0);
+      expect(m[5] == (uint64_t)(((u128)r1 << 64) / q), "modinfo r1 companion", q, 5);
+      expect(m[6] + 2 * q == 0 && m[7] + 4 * q == 0, "modinfo -2q, -4q", q, 6);
+    }
     for (uint32_t logN = 12; logN <= 16; logN += 2) {
       const uint32_t N = 1u << logN;
       if ((q - 1) % (2ull * N)) continue;
