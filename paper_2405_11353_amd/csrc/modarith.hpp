@@ -75,6 +75,12 @@ NTT_HD uint64_t shoup_r(uint64_t y, uint64_t w, uint64_t Q, uint64_t nq) {
   uint32_t Q0 = lo32(Q), Q1 = hi32(Q), n0 = lo32(nq), n1 = hi32(nq);
   uint64_t lo = mad32(Q0, n0, mad32(y0, w0, 0));
   uint32_t hi = hi32(lo) + y1 * w0 + y0 * w1 + Q1 * n0 + Q0 * n1;
+#if defined(__HIP_DEVICE_COMPILE__)
+  // An empty asm (no instruction) that hides hi's value, so that the compiler
+  // keeps the 32-bit add of hi32(lo) instead of turning the result into a
+  // 64-bit add of lo and hi << 32, which costs a move to zero the low half
+  asm("" : "+v"(hi));
+#endif
   return ((uint64_t)hi << 32) | lo32(lo);
 }
 
