@@ -110,7 +110,7 @@ def summarize_counters(d: str, he: bool = False):
     out = {"source_hash": kernel_source_hash(sources), "fetch_scale": f_scale, "write_scale": w_scale,
            "kernels": {}}
     lines = [title, "",
-             "Commands (repository root on the GPU box; each pass is its own run):", "",
+             "Commands (run from the repository root on an MI355X; each pass is its own run):", "",
              f"    B='{B}'",
              "    rocprofv3 --kernel-trace --stats --output-format csv -d <dir>/kt -o kt -- $B",
              "    rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir>/pmc_fetch -o run -- $B",
@@ -817,7 +817,7 @@ def summarize_polymul_trace(d: str):
     cmd = "python3 bench.py --polymul-only --steps 20 --warmup 5"
     lines = ["# Kernel trace: ntt_polymul at polymul_n65536_l24 (N=2^16, 24 limbs, 2 products of 2 components), "
              "MI355X", "",
-             "Command (repository root on the GPU box):", "",
+             "Command (run from the repository root on an MI355X):", "",
              f"    rocprofv3 --kernel-trace --stats --output-format csv -d <dir>/kt -o kt -- {cmd} > <dir>/bench.json",
              f"    python3 bench.py --summarize-polymul-trace <dir>", "",
              f"Kernel source hash: {kernel_source_hash(KERNEL_SOURCES + ['paper_2405_11353_amd/csrc/k_polymul.hip'])}",
