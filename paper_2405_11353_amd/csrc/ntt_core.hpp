@@ -9,11 +9,12 @@
 // Compared with the paper's DIT (Alg. 1) the psi^j twist is absorbed into the
 // twiddles and the bit reversal is done by the store, through LDS.
 //
-// Work split: each thread holds 16 values and applies up to 4 stages to them
-// in registers (a "phase"); values are exchanged through LDS between phases.
-// A remainder phase of logN mod 4 stages comes first, so that in every phase
-// the 16 values of a thread sit at a power-of-two stride with the stride of
-// the phase's last stage. Twiddles are read from global memory (L1/L2 hits:
+// Work split: each thread holds V = 2^LV values (16, or 8 in the four-step
+// kernels that take LV = 3) and applies up to LV stages to them in registers
+// (a "phase"); values are exchanged through LDS between phases. A remainder
+// phase of logN mod LV stages comes first, so that in every phase the V values
+// of a thread sit at a power-of-two stride with the stride of the phase's last
+// stage. Twiddles are read from global memory (L1/L2 hits:
 // the per-limb table is shared by all polynomials of that limb).
 //
 // Kernel shapes:
