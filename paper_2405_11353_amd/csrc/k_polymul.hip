@@ -72,9 +72,14 @@ k_row_polymul(typename A::word* sa, const typename A::word* __restrict__ sb,
   auto row_of = [&](uint32_t row) { return tile * 16 + row; };
 
   W va[V], vb[V];
-  stage_first_phase<LOGN2, LV>(tw0, twf, logN1, row_of);
+  // the first-phase twiddles are loaded ahead of the row and written to LDS
+  // after the row's loads are issued (loads complete in order)
+  FirstPhaseStage<LOGN2, LV, TW> first;
+  first.load(twf, logN1, row_of);
+  __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
   for (int i = 0; i < V; ++i) va[i] = rowa[i * TPR + t];
+  first.put(tw0);
   wave_lds_sync();
 
   auto forward = [&](W (&v)[V], const TW* twf) {

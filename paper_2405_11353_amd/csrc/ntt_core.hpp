@@ -374,16 +374,37 @@ k_col(const typename A::word* in, typename A::word* out, const typename A::tw_t*
 // to 17 entries so the wave's rows fall in different LDS banks) and orders the copy with the wavefront
 // sync it already needs, so that phase reads no twiddle from global memory
 // between butterflies. row_of(rl) is the matrix row of workgroup row rl.
+// In two halves: load() reads this lane's entry (if it has one) and put()
+// writes it to LDS, so that the data loads can be issued in between: loads
+// complete in order, and the write then waits for the twiddle alone.
+template <int LOGN2, int LV, class TW>
+struct FirstPhaseStage {
+  static constexpr uint32_t TPR = (1u << LOGN2) >> LV, RPW = 64 / TPR, RS0 = Sched<LOGN2, LV>::rs(0),
+                            SL = 1u << RS0;
+  static_assert(RPW * SL <= 64 && SL <= 16, "one lane per first-phase twiddle of the wave's rows");
+  uint32_t rl = 0, u = 0;
+  bool has = false;
+  TW e{};
+  template <class F>
+  __device__ __forceinline__ void load(const TW* tw, uint32_t logN1, F row_of) {
+    const uint32_t lane = threadIdx.x & 63u, q = lane / SL;
+    u = lane % SL;
+    rl = (threadIdx.x >> 6) * RPW + q;  // the rows this wave transforms
+    has = q < RPW && u;
+    if (has) {
+      const uint32_t k = 31u - (uint32_t)__builtin_clz(u), j = u - (1u << k);
+      e = tw[(1u << (logN1 + k)) + (row_of(rl) << k) + j];
+    }
+  }
+  __device__ __forceinline__ void put(TW (*tw0)[17]) const {
+    if (has) tw0[rl][u] = e;
+  }
+};
 template <int LOGN2, int LV, class TW, class F>
 __device__ __forceinline__ void stage_first_phase(TW (*tw0)[17], const TW* tw, uint32_t logN1, F row_of) {
-  constexpr uint32_t TPR = (1u << LOGN2) >> LV, RPW = 64 / TPR, RS0 = Sched<LOGN2, LV>::rs(0), SL = 1u << RS0;
-  static_assert(RPW * SL <= 64 && SL <= 16, "one lane per first-phase twiddle of the wave's rows");
-  const uint32_t lane = threadIdx.x & 63u, q = lane / SL, u = lane % SL;
-  const uint32_t rl = (threadIdx.x >> 6) * RPW + q;  // the rows this wave transforms
-  if (q < RPW && u) {
-    const uint32_t k = 31u - (uint32_t)__builtin_clz(u), j = u - (1u << k);
-    tw0[rl][u] = tw[(1u << (logN1 + k)) + (row_of(rl) << k) + j];
-  }
+  FirstPhaseStage<LOGN2, LV, TW> st;
+  st.load(tw, logN1, row_of);
+  st.put(tw0);
 }
 
 // ============================================================ row pass
@@ -443,12 +464,17 @@ k_row(const typename A::word* in, typename A::word* out, const typename A::tw_t*
   a.load(*mi);
   W* sh = lds + rl * RSTR;
   W v[V];
-  stage_first_phase<LOGN2, LV>(tw0, tw, logN1,
-                           [&](uint32_t row) { return NATURAL ? brv(tile * 16 + row, logN1) : tile * 16 + row; });
+  // the first-phase twiddles are loaded before the data and written to LDS
+  // after the data loads are issued, so that neither waits for the other
+  FirstPhaseStage<LOGN2, LV, TW> first;
+  first.load(tw, logN1, [&](uint32_t row) { return NATURAL ? brv(tile * 16 + row, logN1) : tile * 16 + row; });
+  __builtin_amdgcn_sched_barrier(0);
+  auto stage = [&]() { first.put(tw0); };
   if constexpr (FWD) {
     const W* src = in + pbase + (size_t)r * N2;
 #pragma unroll
     for (int i = 0; i < V; ++i) v[i] = ld_data<NT_LD_MID>(src + i * TPR + t);
+    stage();
     wave_lds_sync();
     static_for<0, S::NPH>([&](auto P_) {
       constexpr int p = decltype(P_)::value;
@@ -490,22 +516,37 @@ k_row(const typename A::word* in, typename A::word* out, const typename A::tw_t*
       const uint32_t rr = threadIdx.x % 16, cg = threadIdx.x / 16;
       const size_t off = pbase + tile * 16 + rr;
       const W* src = in + off;
+      // every load is issued before the first product, so that a wave has all
+      // of its loads in flight at once rather than one pair per product
+      W xa[V], xb[MULIN ? V : 1];
 #pragma unroll
       for (int j = 0; j < V; ++j) {
-        const uint32_t cc = cg + TPR * j;
-        const size_t e = (size_t)brv(cc, LOGN2) * N1;
-        W val = ld_data<NT_LD_IN>(src + e);
-        if constexpr (MULIN) val = mulmod_general(val, ld_data<NT_LD_IN>(in2 + off + e), *mi);
-        lds[rr * RSTR + pad16(cc)] = val;
+        const size_t e = (size_t)brv(cg + TPR * j, LOGN2) * N1;
+        xa[j] = ld_data<NT_LD_IN>(src + e);
+        if constexpr (MULIN) xb[j] = ld_data<NT_LD_IN>(in2 + off + e);
+      }
+      stage();
+#pragma unroll
+      for (int j = 0; j < V; ++j) {
+        W val = xa[j];
+        if constexpr (MULIN) val = mulmod_general(val, xb[j], *mi);
+        lds[rr * RSTR + pad16(cg + TPR * j)] = val;
       }
       __syncthreads();
     } else {
       const size_t off = pbase + (size_t)r * N2;
       const W* src = in + off;
+      W xa[V], xb[MULIN ? V : 1];
 #pragma unroll
       for (int i = 0; i < V; ++i) {
-        W val = ld_data<NT_LD_IN>(src + i * TPR + t);
-        if constexpr (MULIN) val = mulmod_general(val, ld_data<NT_LD_IN>(in2 + off + i * TPR + t), *mi);
+        xa[i] = ld_data<NT_LD_IN>(src + i * TPR + t);
+        if constexpr (MULIN) xb[i] = ld_data<NT_LD_IN>(in2 + off + i * TPR + t);
+      }
+      stage();
+#pragma unroll
+      for (int i = 0; i < V; ++i) {
+        W val = xa[i];
+        if constexpr (MULIN) val = mulmod_general(val, xb[i], *mi);
         sh[pad16(i * TPR + t)] = val;
       }
       wave_lds_sync();
@@ -687,22 +728,35 @@ k_row_tw(const typename A::word* in, typename A::word* out, const typename A::tw
       const uint32_t rr = threadIdx.x % 16, cg = threadIdx.x / 16;
       const size_t off = pbase + tile * 16 + rr;
       const W* src = in + off;
+      // every load is issued before the first product, so that a wave has all
+      // of its loads in flight at once rather than one pair per product
+      W xa[V], xb[MULIN ? V : 1];
 #pragma unroll
       for (int j = 0; j < V; ++j) {
-        const uint32_t cc = cg + TPR * j;
-        const size_t e = (size_t)brv(cc, LOGN2) * N1;
-        W val = ld_data<NT_LD_IN>(src + e);
-        if constexpr (MULIN) val = mulmod_general(val, ld_data<NT_LD_IN>(in2 + off + e), *mi);
-        lds[rr * RSTR + pad16(cc)] = val;
+        const size_t e = (size_t)brv(cg + TPR * j, LOGN2) * N1;
+        xa[j] = ld_data<NT_LD_IN>(src + e);
+        if constexpr (MULIN) xb[j] = ld_data<NT_LD_IN>(in2 + off + e);
+      }
+#pragma unroll
+      for (int j = 0; j < V; ++j) {
+        W val = xa[j];
+        if constexpr (MULIN) val = mulmod_general(val, xb[j], *mi);
+        lds[rr * RSTR + pad16(cg + TPR * j)] = val;
       }
       __syncthreads();
     } else {
       const size_t off = pbase + (size_t)r * N2;
       const W* src = in + off;
+      W xa[V], xb[MULIN ? V : 1];
 #pragma unroll
       for (int i = 0; i < V; ++i) {
-        W val = ld_data<NT_LD_IN>(src + i * TPR + t);
-        if constexpr (MULIN) val = mulmod_general(val, ld_data<NT_LD_IN>(in2 + off + i * TPR + t), *mi);
+        xa[i] = ld_data<NT_LD_IN>(src + i * TPR + t);
+        if constexpr (MULIN) xb[i] = ld_data<NT_LD_IN>(in2 + off + i * TPR + t);
+      }
+#pragma unroll
+      for (int i = 0; i < V; ++i) {
+        W val = xa[i];
+        if constexpr (MULIN) val = mulmod_general(val, xb[i], *mi);
         sh[pad16(i * TPR + t)] = val;
       }
       __syncthreads();
