@@ -76,8 +76,9 @@ def test_default_path_u32(ntt, logn):
     run_roundtrip(ntt, 1 << logn, Q32, batch=2, word=32, seed=100 + logn)
 
 
-@pytest.mark.parametrize("logn,logn1", [(12, 6), (13, 6), (13, 7), (14, 7), (14, 8), (15, 7), (15, 8),
-                                        (16, 7), (16, 8), (16, 9), (17, 8), (17, 9)])
+# every (log2 N1, log2 N2) pair in 6..9 x 6..9 that N <= 2^17 allows
+@pytest.mark.parametrize("logn,logn1", [(12, 6), (13, 6), (13, 7), (14, 6), (14, 7), (14, 8), (15, 6), (15, 7),
+                                        (15, 8), (15, 9), (16, 7), (16, 8), (16, 9), (17, 8), (17, 9)])
 @pytest.mark.parametrize("bitrev", [False, True])
 @pytest.mark.parametrize("row_twist", [True, False, None])
 def test_fourstep_splits_u64(ntt, logn, logn1, bitrev, row_twist):
@@ -332,7 +333,7 @@ def test_stage_entry_points_compose(ntt):
 
 @pytest.mark.parametrize("logn,bitrev,variant", [(16, False, None), (16, True, None), (15, False, None),
                                                   (12, False, None), (12, False, (3, 6)), (13, True, (3, 6)),
-                                                  (17, False, None)])
+                                                  (16, False, (3, 7)), (15, True, (3, 9)), (17, False, None)])
 @pytest.mark.parametrize("row_twist", [True, False])
 def test_fused_pointwise_inverse(ntt, logn, bitrev, variant, row_twist):
     N, moduli = 1 << logn, P18[:3]
