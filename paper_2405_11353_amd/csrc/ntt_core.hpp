@@ -365,18 +365,19 @@ k_col(const typename A::word* in, typename A::word* out, const typename A::tw_t*
   }
 }
 
-// ============================================================ row pass
+// ------------------------------------------- first-phase twiddles of a row
 // The first phase of a row (stages logN1 .. logN1 + rs(0) - 1) uses the
 // 2^rs(0) - 1 twiddles of the row's own subtree: slot 2^k + j of row r is
 // table entry 2^(logN1 + k) + (r << k) + j. Each wave copies those of its own
 // 64 / TPR rows into LDS (lane q * 2^rs(0) + u: row q, slot u; at most 64
-// lanes for every LOGN2 from 6 to 9 and 8 or 16 values per thread; rows padded
-// to 17 entries so the wave's rows fall in different LDS banks) and orders the copy with the wavefront
-// sync it already needs, so that phase reads no twiddle from global memory
-// between butterflies. row_of(rl) is the matrix row of workgroup row rl.
-// In two halves: load() reads this lane's entry (if it has one) and put()
-// writes it to LDS, so that the data loads can be issued in between: loads
-// complete in order, and the write then waits for the twiddle alone.
+// lanes for every LOGN2 from 6 to 9 and 8 or 16 values per thread; rows
+// padded to 17 entries so the wave's rows fall in different LDS banks) and
+// orders the copy with the wavefront sync it already needs, so that phase
+// reads no twiddle from global memory between butterflies. row_of(rl) is the
+// matrix row of workgroup row rl. The copy comes in two halves: load() reads
+// this lane's entry (if it has one) and put() writes it to LDS, so that the
+// data loads can be issued in between: loads complete in order, and the write
+// then waits for the twiddle alone.
 template <int LOGN2, int LV, class TW>
 struct FirstPhaseStage {
   static constexpr uint32_t TPR = (1u << LOGN2) >> LV, RPW = 64 / TPR, RS0 = Sched<LOGN2, LV>::rs(0),
