@@ -360,3 +360,27 @@ def test_fused_pointwise_inverse(ntt, logn, bitrev, variant, row_twist):
     if logn <= 12:
         for l, q in enumerate(moduli):
             np.testing.assert_array_equal(got[1, l], oracle.negacyclic_mul(a[1, l], b[1, l], q))
+
+
+@pytest.mark.parametrize("logn,logn1", [(14, 7), (16, 8), (17, 9)])
+@pytest.mark.parametrize("row_twist", [True, False])
+def test_fused_pointwise_inverse_exact_quotient(ntt, logn, logn1, row_twist):
+    """The fused product + inverse with the exact Shoup quotient (lazy bound 2q)."""
+    N, moduli = 1 << logn, P18[3:5]
+    log(f"case fused pointwise+inverse exact N={N} logn1={logn1} row_twist={row_twist}")
+    plan = ntt.Plan(N, moduli)
+    plan.set_variant(ntt.NTT_PATH_FOURSTEP, logn1)
+    plan.set_exact_quotient(True)
+    plan.set_row_twist(row_twist)
+    a = si.poly_batch(41, 2, moduli, N)
+    b = si.poly_batch(42, 2, moduli, N)
+    da, db = to_dev(a), to_dev(b)
+    plan.forward(da)
+    plan.forward(db)
+    np.testing.assert_array_equal(from_dev(da).reshape(a.shape), oracle_fwd(a, moduli))
+    plan.pointwise_inverse(da, db)
+    A = oracle_fwd(a, moduli)
+    B = oracle_fwd(b, moduli)
+    ref = oracle_inv(oracle.pointwise_batch(A, B, moduli)[0], moduli)
+    np.testing.assert_array_equal(from_dev(da).reshape(a.shape), ref)
+    plan.close()
