@@ -54,6 +54,8 @@ extern "C" {
 #define NTT_ERR_UNSUPPORTED (-7) /* no kernel for this shape/variant           */
 #define NTT_ERR_STATE (-8)       /* unknown ticket, or object shut down        */
 #define NTT_ERR_TIMEOUT (-9)     /* wait timed out; the job is still pending   */
+#define NTT_ERR_SCRATCH (-10)    /* ntt_forward_noalloc: the call needs more   */
+                                 /* scratch than NTT_NOALLOC_SCRATCH_BYTES     */
 
 /* ---- plan flags ---------------------------------------------------------- */
 #define NTT_WORD32 0x1u          /* uint32_t words, every q_l < 2^30            */
@@ -187,6 +189,27 @@ int ntt_plan_set_row_twist(ntt_plan* plan, int mask);
 /* Scratch a natural-order four-step call of `batch` polynomials needs (bytes;
  * 0 when the chosen variant works in place). The plan allocates it. */
 size_t ntt_workspace_bytes(const ntt_plan* plan, uint32_t batch);
+
+/* ntt_forward for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, and harnesses that forbid
+ * hipMalloc. Same arguments, transform and asynchrony as ntt_forward, but the
+ * four-step intermediate lives in a fixed device array that the library
+ * holds on each GPU it runs on (NTT_NOALLOC_SCRATCH_BYTES, 64 MiB, kept until
+ * the process ends) instead of the plan's per-stream scratch, and the call
+ * makes no allocation of any kind. That is enough for natural-order spectra
+ * of batch * L * N <= 2^23 words, e.g. 4 polynomials of 24 limbs at N = 2^16.
+ * Errors: NTT_ERR_SCRATCH when ntt_workspace_bytes(plan, batch) exceeds the
+ * array; NTT_ERR_UNSUPPORTED when the call would first have to build tables
+ * (a twisted forward row pass for a split whose tables the plan has not built,
+ * or the paper's per-stage variants); the argument errors of ntt_forward.
+ * Calls that need no scratch (LDS-resident sizes, bit-reversed spectra) use
+ * none. Every call on one GPU shares that GPU's array and the array keeps the
+ * last call's contents (each call writes the whole intermediate before it
+ * reads it back, so nothing needs clearing): calls that can overlap on one GPU
+ * (on different streams, or from several threads) race and must be ordered by
+ * the caller. */
+#define NTT_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int ntt_forward_noalloc(const ntt_plan* plan, void* d_data, uint32_t batch, void* stream);
 
 /* The variant a call with `batch` polynomials would run (after tuning). */
 int ntt_plan_get_variant_for(const ntt_plan* plan, uint32_t batch, int* path, int* log_n1, int* exact);

@@ -136,6 +136,7 @@ const char* ntt_strerror(int code) {
     case NTT_ERR_UNSUPPORTED: return "no kernel for this shape or variant";
     case NTT_ERR_STATE: return "unknown ticket or object shut down";
     case NTT_ERR_TIMEOUT: return "timed out";
+    case NTT_ERR_SCRATCH: return "workspace larger than the fixed scratch of the no-allocation entry point";
     default: return "unknown error";
   }
 }
@@ -434,7 +435,12 @@ static int check_common(const ntt_plan* p, uint32_t batch) {
   return NTT_OK;
 }
 
-static int run_ntt(const ntt_plan* pc, void* data, uint32_t batch, void* stream, bool fwd, int stage_mask = 3) {
+// fixed_scratch: the caller's scratch of fixed_bytes bytes instead of the
+// plan's, and nothing allocated: a call that would need a device allocation
+// (a larger scratch, row tables not built yet, the paper variants' tables)
+// is refused instead
+static int run_ntt(const ntt_plan* pc, void* data, uint32_t batch, void* stream, bool fwd, int stage_mask = 3,
+                   void* fixed_scratch = nullptr, size_t fixed_bytes = 0) {
   int rc = check_common(pc, batch);
   if (rc != NTT_OK) return rc;
   if (!data) return NTT_ERR_ARG;
@@ -442,7 +448,7 @@ static int run_ntt(const ntt_plan* pc, void* data, uint32_t batch, void* stream,
   int path, logN1, exact;
   select_variant(p, batch * p->L, &path, &logN1, &exact);
   if (is_paper_path(path)) {
-    if (stage_mask != 3) return NTT_ERR_UNSUPPORTED;
+    if (stage_mask != 3 || fixed_scratch) return NTT_ERR_UNSUPPORTED;
     return run_paper(p, data, batch, stream, fwd, path);
   }
   nttk::Launch c;
@@ -461,13 +467,23 @@ static int run_ntt(const ntt_plan* pc, void* data, uint32_t batch, void* stream,
   c.stream = (hipStream_t)stream;
   c.stage_mask = stage_mask;
   if (stage_mask != 3 && c.path != nttk::PATH_TWO) return NTT_ERR_UNSUPPORTED;
-  if (c.path == nttk::PATH_TWO && c.natural) {
+  const bool twisted = c.path == nttk::PATH_TWO && (p->row_twist & (fwd ? NTT_ROW_TWIST_FWD : NTT_ROW_TWIST_INV));
+  if (fixed_scratch) {
+    if (c.path == nttk::PATH_TWO && c.natural) {
+      if (ntt_workspace_bytes(p, batch) > fixed_bytes) return NTT_ERR_SCRATCH;
+      c.scratch = fixed_scratch;
+    }
+    if (twisted) {
+      std::lock_guard<std::mutex> g(p->mu);
+      if (!p->d_rowtw[fwd ? 0 : 1][logN1]) return NTT_ERR_UNSUPPORTED;
+    }
+  } else if (c.path == nttk::PATH_TWO && c.natural) {
     rc = get_scratch(p, stream, ntt_workspace_bytes(p, batch), &c.scratch);
     if (rc != NTT_OK) return rc;
   }
-  if (c.path == nttk::PATH_TWO && (p->row_twist & (fwd ? NTT_ROW_TWIST_FWD : NTT_ROW_TWIST_INV)) &&
-      (rc = row_tables(p, logN1, fwd, &c)) != NTT_OK)
-    return rc;
+  // tables that exist are only looked up (row_tables allocates only when a
+  // split's tables are missing, which the fixed-scratch form has ruled out)
+  if (twisted && (rc = row_tables(p, logN1, fwd, &c)) != NTT_OK) return rc;
   const hipError_t e = nttk::launch_ntt(c, fwd);
   if (e == hipErrorNotSupported) return NTT_ERR_UNSUPPORTED;
   return e == hipSuccess ? NTT_OK : NTT_ERR_HIP;
@@ -502,6 +518,12 @@ int ntt_pointwise_mul_inverse_stage(const ntt_plan* pc, const void* a, const voi
 }
 
 }  // extern "C"
+
+int ntti::forward_fixed_scratch(const ntt_plan* p, void* data, uint32_t batch, void* stream, void* scratch,
+                                size_t scratch_bytes) {
+  if (!scratch) return NTT_ERR_ARG;
+  return run_ntt(p, data, batch, stream, true, 3, scratch, scratch_bytes);
+}
 
 static int run_mul_inverse(const ntt_plan* pc, const void* a, const void* b, void* c, uint32_t batch,
                            void* stream, int stage_mask) {

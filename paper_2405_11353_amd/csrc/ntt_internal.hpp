@@ -68,6 +68,13 @@ size_t pool_bytes();
 // a prime q < 2^bits with q = 1 mod 2N (the largest one), for tuning runs
 uint64_t tuning_prime(uint32_t N, int word);
 
+// ntt_forward with a caller-supplied scratch of scratch_bytes bytes in place
+// of the plan's per-stream scratch; allocates nothing and returns
+// NTT_ERR_SCRATCH if the call needs more, NTT_ERR_UNSUPPORTED if it would need
+// tables the plan has not built
+int forward_fixed_scratch(const ntt_plan* p, void* data, uint32_t batch, void* stream, void* scratch,
+                          size_t scratch_bytes);
+
 // f(l) for every l < L, spread over up to 16 host threads (table generation)
 void for_limbs(uint32_t L, const std::function<void(uint32_t)>& f);
 

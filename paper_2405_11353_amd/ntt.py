@@ -43,6 +43,8 @@ class BatchInfo(ctypes.Structure):
 NTT_REQ_NTT, NTT_REQ_INTT, NTT_REQ_POLYMUL = 0, 1, 2
 NTT_SERVER_SIMULATE = 0x1
 NTT_ERR_TIMEOUT = -9
+NTT_ERR_SCRATCH = -10
+NTT_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class Request(ctypes.Structure):
@@ -96,6 +98,7 @@ def lib() -> ctypes.CDLL:
             "ntt_plan_create_ex": (vp, [u32, u64p, u32, u32, u64p]),
             "ntt_plan_destroy": (None, [vp]),
             "ntt_forward": (i32, [vp, vp, u32, vp]),
+            "ntt_forward_noalloc": (i32, [vp, vp, u32, vp]),
             "ntt_inverse": (i32, [vp, vp, u32, vp]),
             "ntt_pointwise_mul": (i32, [vp, vp, vp, vp, u32, vp]),
             "ntt_pointwise_mul_inverse": (i32, [vp, vp, vp, vp, u32, vp]),

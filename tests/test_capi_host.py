@@ -62,7 +62,7 @@ def test_plan_argument_validation(lib):
 
 def test_strerror_covers_codes(lib):
     lib.ntt_strerror.restype = ctypes.c_char_p
-    for c in range(0, -10, -1):
+    for c in range(0, -11, -1):
         assert lib.ntt_strerror(c) and lib.ntt_strerror(c) != b"unknown error"
 
 
