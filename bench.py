@@ -184,9 +184,11 @@ def parse():
     ap.add_argument("--streams", type=int, default=2,
                     help="streams that consecutive steps alternate between (1: all on one stream)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=3.0,
+                    help="seconds per CPU-oracle leg (headline sample, all cores and one thread)")
     ap.add_argument("--no-per-call", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-latency", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-paper-sizes", action="store_true")
     ap.add_argument("--no-he", action="store_true")
@@ -196,7 +198,8 @@ def parse():
                     help="time only the HE steps (tensor product, ModUp, ModDown) and print their JSON")
     ap.add_argument("--summarize-he-counters", metavar="DIR", default=None,
                     help="write the HE-step counter summary under profiles/ from a rocprofv3 session")
-    ap.add_argument("--serving-jobs", type=int, default=3000)
+    ap.add_argument("--serving-jobs", type=int, default=20000)
+    ap.add_argument("--serving-warmup", type=int, default=1000)
     ap.add_argument("--no-batch-sweep", action="store_true")
     ap.add_argument("--polymul-only", action="store_true",
                     help="only the fused product (ntt_polymul) on one stream, --steps steps after --warmup")
@@ -207,6 +210,218 @@ def parse():
     ap.add_argument("--summarize-counters", metavar="DIR", default=None,
                     help="write profiles/ summaries from a rocprofv3 session directory and exit")
     return ap.parse_args()
+
+
+def dist_us(xs) -> dict:
+    """Mean, median, 99th percentile and minimum of per-run times (us)."""
+    a = np.sort(np.asarray(xs, dtype=np.float64))
+    return {"runs": int(a.size), "mean_us": round(float(a.mean()), 3), "p50_us": round(float(np.percentile(a, 50)), 3),
+            "p99_us": round(float(np.percentile(a, 99)), 3), "min_us": round(float(a[0]), 3)}
+
+
+def per_run_us(torch, fn, runs, stream):
+    """Times of `runs` calls of fn(r), each between its own pair of HIP events
+    on `stream` (the launch stream), in us."""
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(runs)]
+    for r, (e0, e1) in enumerate(evs):
+        e0.record(stream)
+        fn(r)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    return [e0.elapsed_time(e1) * 1e3 for e0, e1 in evs]
+
+
+def bench_latency(ntt, si, torch, runs=200, warm=20):
+    """The two small configurations, timed per call as the paper times its GPU
+    runs (device-resident input and output, mean of at least 100 runs), with
+    the median, 99th percentile and minimum beside the mean:
+    single_ntt_n1024_u32 (one negacyclic NTT of 1024 32-bit words, q =
+    998244353) and ciphertext_n16384_l8 (2 polynomials x 8 limbs of 2^14
+    64-bit words, 16 transforms per call). Forward and inverse are timed
+    apart, eagerly (events around each call) and replayed from a HIP graph
+    that holds the one call. Each configuration's forward output is checked
+    against the oracle first (the 1024-point one also against the O(N^2)
+    definition), and every graph replay against the eager result."""
+    import oracle
+    stream = torch.cuda.current_stream()
+    out = {}
+    for w in (si.workload_single_u32(), si.workload_ct_n14()):
+        flags = ntt.NTT_WORD32 if w.word == 32 else 0
+        plan = ntt.Plan(w.N, w.moduli, flags=flags)
+        host = si.poly_batch(w.seed, w.batch, w.moduli, w.N)
+        as_dev = (lambda h: torch.from_numpy(h.astype(np.uint32).view(np.int32)).cuda()) if w.word == 32 else \
+            (lambda h: torch.from_numpy(h.view(np.int64)).cuda())
+        as_host = (lambda t: t.cpu().numpy().view(np.uint32).astype(np.uint64)) if w.word == 32 else \
+            (lambda t: t.cpu().numpy().view(np.uint64))
+        x = as_dev(host)
+        chk = x.clone()
+        plan.forward(chk)
+        torch.cuda.synchronize()
+        got = as_host(chk).reshape(host.shape)
+        want = oracle.ntt_forward_batch(host, w.moduli)[0]
+        assert (got == want).all(), f"{w.name}: forward differs from the oracle"
+        if w.N <= 1024:
+            assert (got[0, 0] == oracle.ntt_direct(host[0, 0], w.moduli[0])).all()
+        plan.inverse(chk)
+        torch.cuda.synchronize()
+        assert torch.equal(chk, x), f"{w.name}: inverse(forward(x)) != x"
+        n_ntt = w.batch * len(w.moduli)
+        res = {"N": w.N, "L": len(w.moduli), "polys": w.batch, "word_bits": w.word, "ntts_per_call": n_ntt,
+               "variant": list(ntt.ntt_plan_get_variant_for(plan.handle, w.batch))}
+        for name, fn in (("forward", plan.forward), ("inverse", plan.inverse)):
+            buf = x.clone()
+            for _ in range(warm):
+                fn(buf)
+            eager = dist_us(per_run_us(torch, lambda r: fn(buf), runs, stream))
+            # the same call captured once and replayed; any per-stream
+            # workspace exists before the capture
+            cs = torch.cuda.Stream()
+            gbuf = x.clone()
+            with torch.cuda.stream(cs):
+                fn(gbuf, stream=cs)
+            torch.cuda.synchronize()
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=cs):
+                fn(gbuf, stream=cs)
+            ref = x.clone()
+            gbuf.copy_(x)
+            for rep in range(3):
+                g.replay()
+                fn(ref)
+                torch.cuda.synchronize()
+                assert torch.equal(gbuf, ref), f"{w.name} {name}: graph replay {rep} differs from the eager call"
+            for _ in range(warm):
+                g.replay()
+            graph = dist_us(per_run_us(torch, lambda r: g.replay(), runs, stream))
+            res[name] = {"eager": eager, "graph": graph,
+                         "eager_ntt_per_s": round(n_ntt / (eager["mean_us"] * 1e-6), 1),
+                         "graph_ntt_per_s": round(n_ntt / (graph["mean_us"] * 1e-6), 1)}
+            log(f"latency {w.name} {name}: eager mean {eager['mean_us']:.2f} p50 {eager['p50_us']:.2f} "
+                f"p99 {eager['p99_us']:.2f} min {eager['min_us']:.2f} us; graph mean {graph['mean_us']:.2f} "
+                f"p50 {graph['p50_us']:.2f} p99 {graph['p99_us']:.2f} min {graph['min_us']:.2f} us")
+            del g
+        plan.close()
+        out[w.name] = res
+    return out
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(ntt, si, torch, host, base, step, seconds=3.0):
+    """The CPU oracle (plain C, one 128-bit % per modular operation; a
+    correctness reference, not a tuned CPU library) timed on this machine's
+    host cores, on one thread and on all of them (OpenMP over independent
+    (polynomial, limb) transforms), on bounded samples of each workload:
+      polymul_n65536_l24: the headline step restricted to 4 of its 24 limbs
+        (16 forward + 8 inverse NTTs + 8 products); its all-core rate is
+        `value`, and the GPU's step output on that sample must equal it;
+      single_ntt_n1024_u32: one 1024-point forward + inverse (32-bit words);
+      ciphertext_n16384_l8: the whole configuration, 16 forward + 16 inverse;
+      batched_uneven_256polys: forward transforms of the uneven batch (all
+        256 polynomials on all cores, the first 16 on one thread).
+    Each leg repeats its sample for about `seconds`."""
+    import oracle
+    w = si.workload_polymul_n16()
+    moduli = w.moduli
+    polys = host.shape[0]
+
+    def rate(fn, ntts, nthreads, secs=seconds):
+        done, t, used = 0, 0.0, 0
+        while t < secs or done == 0:
+            t0 = time.perf_counter()
+            used = fn(nthreads)
+            t += time.perf_counter() - t0
+            done += ntts
+        return round(done / t, 2), int(used), round(t, 2)
+
+    legs = {}
+    sub = 4
+    ref_in = np.ascontiguousarray(host[:, :sub])
+    last = {}
+
+    def step_sample(nt):
+        spec, used = oracle.ntt_forward_batch(ref_in, moduli[:sub], nthreads=nt)
+        prod, _ = oracle.pointwise_batch(spec[:2], spec[2:], moduli[:sub], nthreads=nt)
+        last["out"], _ = oracle.ntt_inverse_batch(prod, moduli[:sub], nthreads=nt)
+        return used
+
+    n_step = polys * sub + 2 * sub
+    for key, nt in (("all_cores", 0), ("one_thread", 1)):
+        v, used, t = rate(step_sample, n_step, nt)
+        legs.setdefault(w.name, {})[key] = {"ntt_per_s": v, "threads": used, "seconds": t}
+    legs[w.name]["sample"] = (f"the step restricted to limbs 0..{sub - 1}: {polys * sub} forward + {2 * sub} "
+                              f"inverse NTTs + {2 * sub} pointwise products")
+    gpu_buf = base.clone()
+    step(gpu_buf)
+    torch.cuda.synchronize()
+    gpu_out = gpu_buf.cpu().numpy().view(np.uint64).reshape(host.shape)[:2, :sub]
+    exact = bool((gpu_out == last["out"]).all())
+    assert exact, "GPU result differs from the oracle on the CPU sample"
+
+    w1 = si.workload_single_u32()
+    x1 = si.poly_batch(w1.seed, 1, w1.moduli, w1.N)
+
+    def single(nt):
+        X, used = oracle.ntt_forward_batch(x1, w1.moduli, nthreads=nt)
+        oracle.ntt_inverse_batch(X, w1.moduli, nthreads=nt)
+        return used
+
+    w2 = si.workload_ct_n14()
+    x2 = si.poly_batch(w2.seed, w2.batch, w2.moduli, w2.N)
+
+    def ct(nt):
+        X, used = oracle.ntt_forward_batch(x2, w2.moduli, nthreads=nt)
+        oracle.ntt_inverse_batch(X, w2.moduli, nthreads=nt)
+        return used
+
+    for wl, fn_, n in ((w1, single, 2), (w2, ct, 2 * w2.batch * len(w2.moduli))):
+        legs[wl.name] = {}
+        for key, nt in (("all_cores", 0), ("one_thread", 1)):
+            v, used, t = rate(fn_, n, nt, secs=min(seconds, 1.5))
+            legs[wl.name][key] = {"ntt_per_s": v, "threads": used, "seconds": t}
+        legs[wl.name]["sample"] = "the whole configuration (forward + inverse)"
+
+    jobs = si.batched_jobs()
+    primes = si.batched_primes()
+    s = si.Stream(si.BASE_SEED + 30)
+    xs = [np.stack([s.uniform_mod(q, j.N) for q in primes[:j.L]])[None] for j in jobs]
+
+    def batch_fwd(count):
+        def run(nt):
+            used = 0
+            for j, x in zip(jobs[:count], xs[:count]):
+                used = max(used, oracle.ntt_forward_batch(x, primes[:j.L], nthreads=nt)[1])
+            return used
+        return run
+
+    legs["batched_uneven_256polys"] = {}
+    for key, nt, count in (("all_cores", 0, len(jobs)), ("one_thread", 1, 16)):
+        v, used, t = rate(batch_fwd(count), sum(j.L for j in jobs[:count]), nt, secs=0.0)
+        legs["batched_uneven_256polys"][key] = {"ntt_per_s": v, "threads": used, "seconds": t, "polys": count}
+    legs["batched_uneven_256polys"]["sample"] = "forward NTTs: all 256 polynomials on all cores, the first 16 on one thread"
+
+    head = legs[w.name]
+    res = {"value": head["all_cores"]["ntt_per_s"], "unit": "NTT/s", "cores": head["all_cores"]["threads"],
+           "kind": "oracle", "sample": head["sample"] + f", repeated for {head['all_cores']['seconds']} s; "
+                                                      "OpenMP over (poly, limb)",
+           "value_one_thread": head["one_thread"]["ntt_per_s"], "cpu_model": cpu_model(),
+           "nproc": os.cpu_count(), "affinity_cpus": len(os.sched_getaffinity(0)),
+           "framing": "plain C correctness reference (one 128-bit % per modular operation), not a tuned CPU library",
+           "gpu_matches_oracle_on_sample": exact, "workloads": legs}
+    for name, lg in legs.items():
+        log(f"cpu oracle {name}: {lg['all_cores']['ntt_per_s']:.1f} NTT/s on {lg['all_cores']['threads']} threads, "
+            f"{lg['one_thread']['ntt_per_s']:.1f} NTT/s on 1 thread")
+    return res
 
 
 def bench_batched(ntt, si, torch, reps=10):
@@ -227,11 +442,30 @@ def bench_batched(ntt, si, torch, reps=10):
     inv = ntt.Batch([(j.N, primes[:j.L], ntt.NTT_JOB_INVERSE, t) for j, t in zip(jobs, tensors)])
     eager = ntt.Batch([(j.N, primes[:j.L], ntt.NTT_JOB_FORWARD, t) for j, t in zip(jobs, tensors)],
                       flags=ntt.NTT_BATCH_NO_GRAPH)
-    # exactness of the timed configuration: forward then inverse is the identity
+    import oracle
+    # the oracle's forward of the first and last limb of every job
+    chk_limbs = [sorted({0, j.L - 1}) for j in jobs]
+    want = [oracle.ntt_forward_batch(np.ascontiguousarray(x[ls])[None], [primes[l] for l in ls])[0][0]
+            for x, ls in zip(hosts, chk_limbs)]
+
+    def check_forward(what):
+        torch.cuda.synchronize()
+        for i, (t, x, ls, w_) in enumerate(zip(tensors, hosts, chk_limbs, want)):
+            got = t.cpu().numpy().view(np.uint64).reshape(x.shape)[ls]
+            assert (got == w_).all(), f"{what}: job {i} differs from the oracle"
+
+    def reload():
+        for t, h in zip(tensors, hosts):
+            t.copy_(torch.from_numpy(h.view(np.int64)))
+
+    # exactness of the timed configuration: every job's forward output against
+    # the oracle (first and last limb), then forward + inverse is the identity
     fwd.run()
+    check_forward("graph batch")
     inv.run()
     torch.cuda.synchronize()
-    exact = all(torch.equal(t, torch.from_numpy(h.view(np.int64)).cuda()) for t, h in zip(tensors[:64], hosts[:64]))
+    exact = all(torch.equal(t, torch.from_numpy(h.view(np.int64)).cuda()) for t, h in zip(tensors, hosts))
+    assert exact, "batched forward + inverse is not the identity"
 
     def timed(fn, n):
         fn()
@@ -264,6 +498,9 @@ def bench_batched(ntt, si, torch, reps=10):
                       "log_n1": c["log_n1"], "exact": c["exact"], "us": round(c["us_per_call"], 1)}
     tuned = ntt.Batch([(j.N, primes[:j.L], ntt.NTT_JOB_FORWARD, t) for j, t in zip(jobs, tensors)])
     us_tuned = timed(tuned.run, reps)
+    reload()
+    tuned.run()
+    check_forward("tuned batch")
     tuned.close()
     ntt.ntt_tune_clear()
     try:
@@ -295,7 +532,9 @@ def bench_batched(ntt, si, torch, reps=10):
            "eager_us": round(us_eager, 1), "per_call_us": round(us_call, 1),
            "per_call_ntt_per_s": round(n_ntt / (us_call * 1e-6), 1),
            "graph_speedup_vs_per_call": round(us_call / us_graph, 2),
-           "buckets": info["buckets"], "kernels": info["kernels"], "round_trip_exact": bool(exact)}
+           "buckets": info["buckets"], "kernels": info["kernels"], "round_trip_exact": bool(exact),
+           "checked": "forward of every job (first and last limb) vs the oracle, for the default and the tuned "
+                      "batch; forward + inverse of every job is the identity"}
     log(f"batched: autotuned graph {us_tuned:.0f} us; choices {choices}")
     log(f"batched: {n_ntt} NTTs in {us_graph:.0f} us (graph), {us_eager:.0f} us (eager), "
         f"{us_call:.0f} us (per-call) -> {res['graph_ntt_per_s'] / 1e6:.2f} M NTT/s")
@@ -642,7 +881,7 @@ def bench_he_steps(ntt, si, torch, reps=50):
     return out
 
 
-def bench_serving(ntt, si, torch, n_jobs=3000, warm=300, rate=15000.0):
+def bench_serving(ntt, si, torch, n_jobs=20000, warm=1000, rate=15000.0):
     """Poisson stream of NTT and poly-mult jobs (N 2^12..2^17, L 1..40) at a fixed
     offered load through the server, against a per-call FIFO; the saturated
     rate of a queued burst is reported beside it."""
@@ -719,7 +958,9 @@ def bench_serving(ntt, si, torch, n_jobs=3000, warm=300, rate=15000.0):
         cs = server.stats()
         curve.append({"offered_jobs_per_s": round(r, 1), "fraction_of_burst_rate": frac,
                       "p50_us": round(cs["p50_us"], 1), "p99_us": round(cs["p99_us"], 1),
-                      "mean_jobs_per_batch": round(cs["completed"] / max(1, cs["batches"]), 2)})
+                      "mean_jobs_per_batch": round(cs["completed"] / max(1, cs["batches"]), 2),
+                      "jobs_measured": cs["completed"], "ntt_per_s": round(cs["ntts"] / max(cs["wall_s"], 1e-9), 1),
+                      "max_inflight_batches": cs["max_inflight_batches"]})
         log(f"serving at {r:.0f} jobs/s ({frac:.0%} of the burst rate): p50 {curve[-1]['p50_us']} us "
             f"p99 {curve[-1]['p99_us']} us, {curve[-1]['mean_jobs_per_batch']} jobs per batch")
 
@@ -740,7 +981,9 @@ def bench_serving(ntt, si, torch, n_jobs=3000, warm=300, rate=15000.0):
         server.close()
         budgets.append({"hbm_budget_GiB": gib, "offered_jobs_per_s": round(0.7 * sat_jobs_s, 1), "p50_us": round(bs["p50_us"], 1), "p99_us": round(bs["p99_us"], 1),
                         "admission_stalls": bs["admission_stalls"],
-                        "max_inflight_batches": bs["max_inflight_batches"]})
+                        "max_inflight_batches": bs["max_inflight_batches"],
+                        "mean_jobs_per_batch": round(bs["completed"] / max(1, bs["batches"]), 2),
+                        "peak_bytes": bs["peak_bytes"]})
         log(f"serving, {gib} GiB budget: p50 {budgets[-1]['p50_us']} us p99 {budgets[-1]['p99_us']} us, "
             f"{bs['admission_stalls']} admission stalls")
 
@@ -937,6 +1180,47 @@ def main():
 
     ms_wall_1, ms_event_1 = timed_steps(1)
     ms_wall, ms_event = timed_steps(len(streams)) if len(streams) > 1 else (ms_wall_1, ms_event_1)
+
+    # ---- the timed configuration's output: steps on every stream at once, each
+    # on its own buffer set, then each stream's first two components against
+    # the oracle on 3 of the 24 limbs (the product of the two ciphertexts)
+    import oracle
+    chk_sets = [base.clone() for _ in streams]
+    torch.cuda.synchronize()
+    for st, buf in zip(streams, chk_sets):
+        step(buf, st)
+    torch.cuda.synchronize()
+    limbs = [0, 11, L - 1]
+    sub = host[:, limbs]
+    spec, _ = oracle.ntt_forward_batch(np.ascontiguousarray(sub), [moduli[l] for l in limbs])
+    want, _ = oracle.ntt_inverse_batch(oracle.pointwise_batch(spec[:2], spec[2:], [moduli[l] for l in limbs])[0],
+                                       [moduli[l] for l in limbs])
+    for buf in chk_sets:
+        got = buf.cpu().numpy().view(np.uint64).reshape(host.shape)[:2, limbs]
+        assert (got == want).all(), "a timed stream's step differs from the oracle"
+    del chk_sets
+    log(f"timed configuration checked: {len(streams)} concurrent streams, limbs {limbs} bit-exact vs the oracle")
+
+    # ---- per-step distribution over at least 100 steps (apart from the timed
+    # steps above): one stream, events around each step; and with the streams
+    # alternating, the intervals between consecutive steps' completions
+    n_dist = max(100, args.steps)
+    one_dist = dist_us(per_run_us(torch, lambda r: step(sets[r % n_sets], stream), n_dist, stream))
+    done_ev = [torch.cuda.Event(enable_timing=True) for _ in range(n_dist + 1)]
+    done_ev[0].record(stream)
+    for st in streams[1:]:
+        st.wait_event(done_ev[0])
+    for r in range(n_dist):
+        st = streams[r % len(streams)]
+        step(sets[r % n_sets], st)
+        done_ev[r + 1].record(st)
+    torch.cuda.synchronize()
+    ends = [done_ev[0].elapsed_time(e) * 1e3 for e in done_ev[1:]]
+    ends.sort()
+    multi_dist = dist_us([b - a for a, b in zip([0.0] + ends[:-1], ends)])
+    log(f"step distribution over {n_dist} steps: one stream mean {one_dist['mean_us']:.1f} p50 {one_dist['p50_us']:.1f} "
+        f"p99 {one_dist['p99_us']:.1f} min {one_dist['min_us']:.1f} us; {len(streams)} streams (completion "
+        f"intervals) mean {multi_dist['mean_us']:.1f} p50 {multi_dist['p50_us']:.1f} p99 {multi_dist['p99_us']:.1f} us")
     ntts_per_step = polys * L + 2 * L               # 96 forward + 48 inverse
     value = ntts_per_step / (ms_wall / 1e3)
     log(f"step: {ms_wall * 1e3:.1f} us wall, {ms_event * 1e3:.1f} us events on {len(streams)} streams; "
@@ -971,20 +1255,28 @@ def main():
         return evs[0].elapsed_time(evs[1]) / reps * 1e3   # us per launch
 
     kernels = {}
+    # Algorithmic bytes of a transform are 16N (read N words once, write them
+    # once), plus each limb's twiddle entries read once per launch (16 B each).
+    # The four-step intermediate is not algorithmic: the column pass is credited
+    # with the transform's reads, the row pass with its writes (forward), and
+    # the fused product + inverse with reading both spectra (its row pass) and
+    # writing the product (its column pass). Counter bytes (traffic) beside.
     if path == ntt.NTT_PATH_FOURSTEP:
         logn2 = int(math.log2(N)) - logn1
-        # twiddle tables read once per limb per launch: the column pass uses the
-        # first N1 entries of each limb's table, the row pass all N (16 B each)
+        # column passes read table slots [0, N1) of each limb; the merged row
+        # pass reads all N slots; the twisted inverse row pass reads its N
+        # twist entries and N2 cyclic entries
         tw_col, tw_row = L * 16 * (1 << logn1), L * 16 * N
+        tw_twist = L * 16 * (N + (1 << logn2))
         kernels["fwd_col_pass"] = dict(fn=lambda b: plan.forward_stage(b, 0, batch=4), items=polys * L,
-                                       stages=logn1, extra_muls=0, words_in=1, words_out=1, tw_bytes=tw_col)
+                                       stages=logn1, extra_muls=0, words_in=1, words_out=0, tw_bytes=tw_col)
         kernels["fwd_row_pass"] = dict(fn=lambda b: plan.forward_stage(b, 1, batch=4), items=polys * L,
-                                       stages=logn2, extra_muls=0, words_in=1, words_out=1, tw_bytes=tw_row)
+                                       stages=logn2, extra_muls=0, words_in=0, words_out=1, tw_bytes=tw_row)
         kernels["inv_row_pass_mul"] = dict(fn=lambda b: plan.pointwise_inverse_stage(b[:2], b[2:], b[:2], 0, batch=2),
-                                           items=2 * L, stages=logn2, extra_muls=0, words_in=2, words_out=1,
-                                           general_muls=N, tw_bytes=tw_row)
+                                           items=2 * L, stages=logn2, extra_muls=N, words_in=2, words_out=0,
+                                           general_muls=N, tw_bytes=tw_twist)
         kernels["inv_col_pass"] = dict(fn=lambda b: plan.inverse_stage(b[:2], 1, batch=2), items=2 * L,
-                                       stages=logn1, extra_muls=N // 2, words_in=1, words_out=1, tw_bytes=tw_col)
+                                       stages=logn1, extra_muls=N // 2, words_in=0, words_out=1, tw_bytes=tw_col)
     else:
         kernels["pointwise"] = dict(fn=lambda b: plan.pointwise(b[:2], b[2:], b[:2], batch=2), items=2 * L,
                                     stages=0, extra_muls=0, words_in=2, words_out=1)
@@ -996,12 +1288,30 @@ def main():
                              + k.get("general_muls", 0) * MULS_PER_GENERAL)
         gbs = bytes_alg / (us * 1e-6) / 1e9
         tops = muls / (us * 1e-6) / 1e12
+        traffic = counter_traffic(name)
         per_kernel[name] = dict(us=round(us, 2), alg_bytes=bytes_alg, alg_int32_muls=muls,
                                 hbm_GBs=round(gbs, 1), hbm_frac=round(gbs / HBM_PEAK_GBS, 4),
-                                mul_TOPs=round(tops, 3), mul_frac=round(tops / INT32_MUL_PEAK_TOPS, 4))
-        log(f"  {name}: {us:.1f} us  {gbs:.0f} GB/s ({gbs / HBM_PEAK_GBS:.1%} HBM)  "
+                                mul_TOPs=round(tops, 3), mul_frac=round(tops / INT32_MUL_PEAK_TOPS, 4),
+                                counter_bytes=traffic,
+                                counter_over_alg=round(traffic / bytes_alg, 2) if traffic else None)
+        log(f"  {name}: {us:.1f} us  {gbs:.0f} GB/s algorithmic ({gbs / HBM_PEAK_GBS:.1%} of HBM peak)  "
             f"{tops:.2f} TOP/s int32 mul ({tops / INT32_MUL_PEAK_TOPS:.1%})")
-    # time share per step: forward passes run on 4 polys, inverse on 2
+    # whole transforms: the forward (column + row pass) and the fused product +
+    # inverse, each credited 16N (24N with the product) per transform + tables
+    transforms = {}
+    if path == ntt.NTT_PATH_FOURSTEP:
+        for tname, parts in (("forward", ("fwd_col_pass", "fwd_row_pass")),
+                             ("product_inverse", ("inv_row_pass_mul", "inv_col_pass"))):
+            us = sum(per_kernel[p_]["us"] for p_ in parts)
+            b_ = sum(per_kernel[p_]["alg_bytes"] for p_ in parts)
+            gbs = b_ / (us * 1e-6) / 1e9
+            transforms[tname] = {"us": round(us, 2), "alg_bytes": b_, "hbm_GBs": round(gbs, 1),
+                                 "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "kernels": list(parts)}
+            log(f"  {tname} transform: {us:.1f} us, {gbs:.0f} GB/s algorithmic ({gbs / HBM_PEAK_GBS:.1%})")
+    # the step: 96 forward (16N) + 48 fused product + inverse (24N) + each
+    # limb's tables once per direction and pass
+    step_bytes = sum(k["alg_bytes"] for k in per_kernel.values())
+    step_gbs = step_bytes / (ms_wall * 1e-3) / 1e9
     dominant = max(per_kernel, key=lambda n: per_kernel[n]["us"])
     dk = per_kernel[dominant]
     if dk["mul_frac"] >= dk["hbm_frac"] and dk["alg_int32_muls"] > 0:
@@ -1010,11 +1320,17 @@ def main():
     else:
         roofline = {"bound": "hbm", "achieved": dk["hbm_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": dk["hbm_frac"], "traffic": None}
-    roofline["traffic"] = counter_traffic(dominant)
+    roofline["traffic"] = dk["counter_bytes"]
     roofline["traffic_unit"] = "bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by a 1 GiB copy)"
+    roofline["alg_bytes"] = dk["alg_bytes"]
     roofline["kernel"] = dominant
     roofline["avg_launch_us"] = dk["us"]
     roofline["valu_busy"] = counter_valu_busy(dominant)
+    roofline["transforms"] = transforms
+    roofline["step"] = {"alg_bytes": step_bytes, "hbm_GBs": round(step_gbs, 1),
+                        "hbm_frac": round(step_gbs / HBM_PEAK_GBS, 4), "us": round(ms_wall * 1e3, 2)}
+    log(f"roofline: {dominant} at {dk['hbm_frac']:.3f} of 8 TB/s (algorithmic bytes); the step at "
+        f"{step_gbs / HBM_PEAK_GBS:.3f}")
 
     # ---- per-call baseline: the same step as one call per (polynomial, limb)
     per_call = None
@@ -1046,37 +1362,14 @@ def main():
         for p_ in plans:
             p_.close()
 
-    # ---- CPU oracle on a bounded sample of the same step (and a bit-exact
-    # comparison of the GPU's product on that sample)
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle
-        sub = 4                                     # limbs in the sample
-        a = host[:, :sub].copy()
-        ref_in = np.ascontiguousarray(a)
-        done_ntts, t_cpu, threads = 0, 0.0, 0
-        out = None
-        while t_cpu < args.cpu_seconds:
-            t0 = time.perf_counter()
-            spec, threads = oracle.ntt_forward_batch(ref_in, moduli[:sub])
-            prod, _ = oracle.pointwise_batch(spec[:2], spec[2:], moduli[:sub])
-            out, _ = oracle.ntt_inverse_batch(prod, moduli[:sub])
-            t_cpu += time.perf_counter() - t0
-            done_ntts += polys * sub + 2 * sub
-        gpu_buf = base.clone()
-        step(gpu_buf)
-        torch.cuda.synchronize()
-        gpu_out = gpu_buf.cpu().numpy().view(np.uint64).reshape(host.shape)[:2, :sub]
-        exact = bool((gpu_out == out).all())
-        cpu = {"value": round(done_ntts / t_cpu, 2), "unit": "NTT/s", "cores": int(threads), "kind": "oracle",
-               "sample": f"the step restricted to limbs 0..{sub - 1} ({polys * sub} forward + {2 * sub} inverse "
-                         f"NTTs + {2 * sub} pointwise), repeated for {t_cpu:.1f} s; OpenMP over (poly, limb)",
-               "gpu_matches_oracle_on_sample": exact}
-        log(f"cpu oracle: {cpu['value']:.1f} NTT/s on {threads} threads; GPU sample bit-exact: {exact}")
-        assert exact, "GPU result differs from the oracle on the CPU sample"
-
+    # ---- CPU oracle on bounded samples of the workloads (and a bit-exact
+    # comparison of the GPU's product on the headline sample)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(ntt, si, torch, host, base, step,
+                                                         seconds=args.cpu_seconds)
+    latency = None if args.no_latency else bench_latency(ntt, si, torch)
     batched = None if args.no_batched else bench_batched(ntt, si, torch)
-    serving = None if args.no_serving else bench_serving(ntt, si, torch, n_jobs=args.serving_jobs, rate=args.serving_rate)
+    serving = None if args.no_serving else bench_serving(ntt, si, torch, n_jobs=args.serving_jobs,
+                                                         warm=args.serving_warmup, rate=args.serving_rate)
     paper_sizes = None if args.no_paper_sizes else bench_paper_sizes(ntt, si, torch)
     he_steps = None if args.no_he else bench_he_steps(ntt, si, torch)
     ablations = None if args.no_ablations else bench_ablations(ntt, si, torch)
@@ -1105,6 +1398,9 @@ def main():
         "per_call": per_call,
         "cpu_baseline": cpu,
         "ms_per_step_events": round(ms_event, 5),
+        "step_latency": {"one_stream": one_dist, "streams_completion_interval": multi_dist,
+                         "streams": len(streams)},
+        "latency": latency,
         "one_stream": {"ms_per_step": round(ms_wall_1, 5), "ms_per_step_events": round(ms_event_1, 5),
                        "value": round(ntts_per_step / (ms_wall_1 / 1e3), 1)},
         "batched": batched,
