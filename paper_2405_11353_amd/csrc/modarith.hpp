@@ -84,6 +84,27 @@ NTT_HD uint64_t shoup_r(uint64_t y, uint64_t w, uint64_t Q, uint64_t nq) {
   return ((uint64_t)hi << 32) | lo32(lo);
 }
 
+// x + y*w - Q*q mod 2^64: the remainder above with its multiply-add chain
+// seeded by x, so that a butterfly's sum x + (y*w mod q) costs no add of its
+// own. Any x < 2^64; the caller knows the true value is below 2^64.
+NTT_HD uint64_t shoup_r_plus(uint64_t y, uint64_t w, uint64_t Q, uint64_t nq, uint64_t x) {
+  uint32_t y0 = lo32(y), y1 = hi32(y), w0 = lo32(w), w1 = hi32(w);
+  uint32_t Q0 = lo32(Q), Q1 = hi32(Q), n0 = lo32(nq), n1 = hi32(nq);
+  uint64_t lo = mad32(Q0, n0, mad32(y0, w0, x));
+  uint32_t hi = hi32(lo) + y1 * w0 + y0 * w1 + Q1 * n0 + Q0 * n1;
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm("" : "+v"(hi));  // keep the 32-bit add, as in shoup_r
+#endif
+  return ((uint64_t)hi << 32) | lo32(lo);
+}
+
+// 1: the CT butterfly takes its sum from shoup_r_plus and its difference as
+// 2 x + L - sum (one 64-bit shift-add and a subtraction); 0: from the product
+// T, as x + T and x + L - T
+#ifndef NTT_CT_FOLD
+#define NTT_CT_FOLD 1
+#endif
+
 template <bool EXACT>
 struct Arith64 {
   using word = uint64_t;
@@ -112,9 +133,18 @@ struct Arith64 {
   // Cooley-Tukey butterfly (x, y) -> (x + w y, x - w y); values in [0, 2L)
   NTT_HD void ct(uint64_t& x, uint64_t& y, const Tw64& t) const {
     uint64_t xr = csub(x, L, nL);
+#if NTT_CT_FOLD
+    // s = xr + T with T = y w mod q in [0, L); the difference xr + L - T is
+    // 2 xr + L - s, exact mod 2^64 since its true value is in (0, 2L)
+    uint64_t Q = EXACT ? shoup_q_exact(y, t.wp) : shoup_q_approx(y, t.wp);
+    uint64_t s = shoup_r_plus(y, t.w, Q, nq, xr);
+    y = (xr << 1) + L - s;
+    x = s;
+#else
     uint64_t T = mul(y, t);
     x = xr + T;
     y = xr + L - T;
+#endif
   }
   // Gentleman-Sande butterfly (x, y) -> (x + y, (x - y) w); values in [0, L)
   NTT_HD void gs(uint64_t& x, uint64_t& y, const Tw64& t) const {
