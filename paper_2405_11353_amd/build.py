@@ -27,7 +27,7 @@ DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",
           "-I", os.path.join(ROOT, "include"), "-I", CSRC] + DEVICE_FLAGS + os.environ.get("NTT_HIPCC_FLAGS", "").split()
 
-KERNEL_UNITS = ["k_u64.hip", "k_u64x.hip", "k_u32.hip", "k_pointwise.hip", "k_batch.hip", "k_paper.hip", "k_he.hip", "k_polymul.hip",
+KERNEL_UNITS = ["k_u64.hip", "k_u64w.hip", "k_u64x.hip", "k_u32.hip", "k_pointwise.hip", "k_batch.hip", "k_paper.hip", "k_he.hip", "k_polymul.hip",
                 "noalloc.hip"]
 HOST_UNITS = ["params.cpp", "capi.cpp", "pool.cpp", "tune.cpp", "batch.cpp", "serve.cpp", "he.cpp"]
 

@@ -190,6 +190,11 @@ ntt_plan* ntt_plan_create_ex(uint32_t N, const uint64_t* moduli, uint32_t L, uin
   p->word = word;
   p->moduli.assign(moduli, moduli + L);
   p->psi = roots;
+#ifndef NTT_WIDE_RANGE
+#define NTT_WIDE_RANGE 1
+#endif
+  p->wide = NTT_WIDE_RANGE && word == 64 &&
+            std::all_of(p->moduli.begin(), p->moduli.end(), [](uint64_t q) { return q < (1ull << 60); });
   if (hipGetDevice(&p->device) != hipSuccess) {
     release(p);
     fail(NTT_ERR_HIP);
@@ -454,6 +459,7 @@ static int run_ntt(const ntt_plan* pc, void* data, uint32_t batch, void* stream,
   nttk::Launch c;
   c.word = p->word;
   c.exact = exact;
+  c.wide = p->wide && !exact;
   c.path = path == NTT_PATH_TINY ? nttk::PATH_TINY : path == NTT_PATH_LDS ? nttk::PATH_LDS : nttk::PATH_TWO;
   c.logN = (int)p->logN;
   c.logN1 = logN1;
@@ -597,6 +603,7 @@ static int run_polymul(const ntt_plan* pc, const void* a, const void* b, void* c
   nttk::Launch L;
   L.word = p->word;
   L.exact = 0;  // one quotient flavour for every pass, so the lazy ranges agree
+  L.wide = 0;   // and the narrow range: the fused row kernel reads the column passes' output
   L.logN = (int)p->logN;
   L.logN1 = logN1;
   L.natural = 1;

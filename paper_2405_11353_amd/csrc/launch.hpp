@@ -27,6 +27,7 @@ enum { IO_DATA_DATA = 0, IO_DATA_SCRATCH = 1, IO_SCRATCH_DATA = 2 };
 struct Launch {
   int word = 64;      // 32 or 64-bit coefficients
   int exact = 0;      // 64-bit: exact Shoup quotient (lazy bound 2q) instead of approx (4q)
+  int wide = 0;       // 64-bit approx, every q < 2^60: forward values in [0, 16q)
   int path = PATH_LDS;
   int logN = 0;
   int logN1 = 0;      // PATH_TWO: column length 2^logN1, row length 2^(logN-logN1)
@@ -81,14 +82,19 @@ hipError_t launch_paper(const PaperLaunch& c, bool forward);
 
 // Each returns hipErrorNotSupported for a shape it has no kernel for.
 hipError_t launch_u64(const Launch& c, bool forward);
+hipError_t launch_u64w(const Launch& c, bool forward);
 hipError_t launch_u64x(const Launch& c, bool forward);
 hipError_t launch_u32(const Launch& c, bool forward);
 hipError_t launch_pointwise(int word, const void* a, const void* b, void* out, const void* mods,
                             uint32_t L, uint32_t logN, uint32_t items, hipStream_t s);
 
+// The wide range changes only the forward kernels (both passes of a forward
+// transform run in it, the column pass's output feeding the row pass); the
+// inverse kernels are the same in either, and run from launch_u64.
 inline hipError_t launch_ntt(const Launch& c, bool forward) {
   if (c.word == 32) return launch_u32(c, forward);
-  return c.exact ? launch_u64x(c, forward) : launch_u64(c, forward);
+  if (c.exact) return launch_u64x(c, forward);
+  return c.wide && forward ? launch_u64w(c, forward) : launch_u64(c, forward);
 }
 
 // shape support, kept next to the instantiation lists in the .hip files

@@ -33,7 +33,7 @@ NTT_HD uint32_t umulhi32(uint32_t a, uint32_t b) {
 // ---------------------------------------------------------------- 64-bit
 struct ModInfo64 {
   uint64_t q;     // modulus, q < 2^62
-  uint64_t rsv;   // reserved (the lazy bound 4q or 2q is derived from the flavour)
+  uint64_t n8q;   // 2^64 - 8q: the wide range's reduction (q < 2^60)
   uint64_t nq;    // 2^64 - q, so that lo64(Q*q) is subtracted by an add
   uint64_t qinv;  // q^-1 mod 2^64 (Montgomery reduction in the pointwise product)
   uint64_t r1;    // 2^64 mod q
@@ -98,6 +98,21 @@ NTT_HD uint64_t shoup_r_plus(uint64_t y, uint64_t w, uint64_t Q, uint64_t nq, ui
   return ((uint64_t)hi << 32) | lo32(lo);
 }
 
+// Which forward stages reduce x before the CT butterfly, by the stage's index
+// j within its pass. Outside the wide range every stage does. In the wide
+// range ([0, 16q), q < 2^60) a butterfly may skip the reduction while x is
+// below 12q, each skipped stage adding 4q to the bound and each reducing one
+// leaving it at 12q:
+//  RP_FRESH, a pass whose input is below 4q (coefficients, or twisted rows):
+//    bounds 8q, 12q, 16q after stages 0..2 skip, then stages 3, 5, 7, ...
+//    reduce and the even ones after them skip;
+//  RP_LAZY, a pass whose input is anywhere in [0, 16q) (the row pass after the
+//    column pass): stages 0, 2, 4, ... reduce and the odd ones skip.
+enum { RP_ALL = 0, RP_FRESH = 1, RP_LAZY = 2 };
+NTT_HD constexpr bool reduces_x(int rp, int j) {
+  return rp == RP_ALL ? true : rp == RP_FRESH ? (j >= 3 && ((j - 3) & 1) == 0) : ((j & 1) == 0);
+}
+
 // 1: the CT butterfly takes its sum from shoup_r_plus and its difference as
 // 2 x + L - sum (one 64-bit shift-add and a subtraction); 0: from the product
 // T, as x + T and x + L - T
@@ -105,12 +120,21 @@ NTT_HD uint64_t shoup_r_plus(uint64_t y, uint64_t w, uint64_t Q, uint64_t nq, ui
 #define NTT_CT_FOLD 1
 #endif
 
-template <bool EXACT>
+// WIDE (approximate quotient, every q < 2^60): forward values live in
+// [0, 16q) instead of [0, 8q). A CT butterfly whose x is below 12q needs no
+// reduction (x + T and x + 4q - T stay below 16q), and one that reduces
+// subtracts 8q from x < 16q and leaves both outputs below 12q; so the stages
+// of a forward pass can alternate between reducing and not (see
+// reduces_x in ntt_core.hpp), and about half the reductions go away. The
+// inverse (GS) butterflies are the same as without WIDE.
+template <bool EXACT, bool WIDE = false>
 struct Arith64 {
+  static_assert(!(EXACT && WIDE), "the wide range is for the approximate quotient");
   using word = uint64_t;
   using tw_t = Tw64;
   static constexpr bool kExact = EXACT;
-  uint64_t q, L, nq, nL, n2q;
+  static constexpr bool kWide = WIDE;
+  uint64_t q, L, nq, nL, n2q, n4q, R, nR;
 
   NTT_HD void load(const ModInfo64& m) {
     q = m.q;
@@ -118,6 +142,9 @@ struct Arith64 {
     nq = m.nq;
     nL = EXACT ? m.n2q : m.n4q;
     n2q = m.n2q;
+    n4q = m.n4q;
+    R = WIDE ? 8 * m.q : L;     // what a reducing CT butterfly subtracts from x
+    nR = WIDE ? m.n8q : nL;
   }
 
   // y * w mod q, result in [0, L) (L = 4q approx, 2q exact), any y < 2^64
@@ -130,9 +157,13 @@ struct Arith64 {
   // costs wait states before the select can read it
   NTT_HD static uint64_t csub(uint64_t x, uint64_t m, uint64_t nm) { return x >= m ? x + nm : x; }
 
-  // Cooley-Tukey butterfly (x, y) -> (x + w y, x - w y); values in [0, 2L)
+  // Cooley-Tukey butterfly (x, y) -> (x + w y, x - w y); values in [0, 2L),
+  // or with WIDE in [0, 16q): RED reduces x from [0, 16q) (outputs below 12q),
+  // !RED needs x below 12q
+  template <bool RED = true>
   NTT_HD void ct(uint64_t& x, uint64_t& y, const Tw64& t) const {
-    uint64_t xr = csub(x, L, nL);
+    static_assert(RED || WIDE, "every butterfly reduces outside the wide range");
+    uint64_t xr = RED ? csub(x, R, nR) : x;
 #if NTT_CT_FOLD
     // s = xr + T with T = y w mod q in [0, L); the difference xr + L - T is
     // 2 xr + L - s, exact mod 2^64 since its true value is in (0, 2L)
@@ -154,9 +185,13 @@ struct Arith64 {
     y = mul(d, t);
   }
   // butterflies whose twiddle is 1 (group 0 of a cyclic transform): both
-  // inputs are reduced instead of multiplied, same ranges as ct / gs
+  // inputs are reduced instead of multiplied, same ranges as ct / gs (with
+  // WIDE, y is brought below 4q, where a product would leave it)
+  template <bool RED = true>
   NTT_HD void ct1(uint64_t& x, uint64_t& y) const {
-    uint64_t xr = csub(x, L, nL), yr = csub(y, L, nL);
+    static_assert(RED || WIDE, "every butterfly reduces outside the wide range");
+    uint64_t xr = RED ? csub(x, R, nR) : x;
+    uint64_t yr = WIDE ? csub(csub(y, R, nR), L, nL) : csub(y, L, nL);
     x = xr + yr;
     y = xr + L - yr;
   }
@@ -173,8 +208,9 @@ struct Arith64 {
     x = mul(s, t0);
     y = mul(d, t1);
   }
-  // canonical from [0, 2L) (forward) or [0, L) (inverse)
+  // canonical from [0, 2L) (forward; [0, 16q) with WIDE) or [0, L) (inverse)
   NTT_HD uint64_t canon_fwd(uint64_t x) const {
+    if (WIDE) x = csub(x, R, nR);
     x = csub(x, L, nL);
     if (!EXACT) x = csub(x, 2 * q, n2q);
     return csub(x, q, nq);
@@ -242,7 +278,10 @@ struct Arith32 {
     return y * t.w - Q * q;
   }
   NTT_HD static uint32_t csub(uint32_t x, uint32_t m) { return x >= m ? x - m : x; }
+  static constexpr bool kWide = false;
+  template <bool RED = true>
   NTT_HD void ct(uint32_t& x, uint32_t& y, const Tw32& t) const {
+    static_assert(RED, "every butterfly reduces");
     uint32_t xr = csub(x, L);
     uint32_t T = mul(y, t);
     x = xr + T;
@@ -254,7 +293,9 @@ struct Arith32 {
     x = csub(s, L);
     y = mul(d, t);
   }
+  template <bool RED = true>
   NTT_HD void ct1(uint32_t& x, uint32_t& y) const {
+    static_assert(RED, "every butterfly reduces");
     uint32_t xr = csub(x, L), yr = csub(y, L);
     x = xr + yr;
     y = xr + L - yr;

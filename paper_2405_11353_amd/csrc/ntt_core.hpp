@@ -55,7 +55,7 @@ __device__ __forceinline__ void static_for_down(F&& f) {
 }
 
 template <class A> struct ModOf;
-template <bool E> struct ModOf<Arith64<E>> { using type = ModInfo64; };
+template <bool E, bool W> struct ModOf<Arith64<E, W>> { using type = ModInfo64; };
 template <> struct ModOf<Arith32> { using type = ModInfo32; };
 
 __device__ __forceinline__ uint32_t brv(uint32_t x, uint32_t bits) {
@@ -95,13 +95,20 @@ __device__ __forceinline__ uint32_t pos(int p, uint32_t t, int i) {
 template <int LOGN, int LV = 4>
 __device__ __forceinline__ uint32_t grp(int p, uint32_t t) { return t >> Sched<LOGN, LV>::lgs(p); }
 
+// which forward stages reduce x: RP_* and reduces_x in modarith.hpp
+template <class A>
+constexpr int rp_of(int wide_rp) { return A::kWide ? wide_rp : RP_ALL; }
+
 // ----------------------------------------------------------- register phases
-// RS stages starting at global stage S0; Hg = global group index at S0.
-template <class A, int RS, int V>
+// RS stages starting at global stage S0; Hg = global group index at S0. RP
+// and J0 (the pass-relative index of the phase's first stage) decide which
+// stages reduce x.
+template <class A, int RS, int RP = RP_ALL, int J0 = 0, int V>
 __device__ __forceinline__ void ct_phase(const A& a, typename A::word (&v)[V],
                                          const typename A::tw_t* __restrict__ tw, uint32_t S0, uint32_t Hg) {
-#pragma unroll
-  for (int k = 0; k < RS; ++k) {
+  static_for<0, RS>([&](auto K_) {
+    constexpr int k = decltype(K_)::value;
+    constexpr bool RED = reduces_x(RP, J0 + k);
     const typename A::tw_t* tk = tw + (1u << (S0 + k)) + (Hg << k);
 #pragma unroll
     for (int j = 0; j < (1 << k); ++j) {
@@ -109,10 +116,10 @@ __device__ __forceinline__ void ct_phase(const A& a, typename A::word (&v)[V],
 #pragma unroll
       for (int m = 0; m < ((V / 2) >> k); ++m) {
         const int i0 = j * (V >> k) + m;
-        a.ct(v[i0], v[i0 + ((V / 2) >> k)], w);
+        a.template ct<RED>(v[i0], v[i0 + ((V / 2) >> k)], w);
       }
     }
-  }
+  });
 }
 
 // Inverse: the same pairs, stages in reverse order. HAS0: this phase contains
@@ -200,7 +207,7 @@ k_lds(typename A::word* __restrict__ data, const typename A::tw_t* __restrict__ 
       }
       // phase 0 has one group per transform: its twiddle addresses are
       // uniform and the compiler reads them with scalar loads
-      ct_phase<A, S::rs(p)>(a, v, tw, S::s0(p), p == 0 ? 0u : grp<LOGN>(p, t));
+      ct_phase<A, S::rs(p), rp_of<A>(RP_FRESH), S::s0(p)>(a, v, tw, S::s0(p), p == 0 ? 0u : grp<LOGN>(p, t));
     });
     if (S::NPH > 1) __syncthreads();
 #pragma unroll
@@ -338,9 +345,9 @@ k_col(const typename A::word* in, typename A::word* out, const typename A::tw_t*
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < V; ++i) v[i] = lds[pos<LOGN1, LV>(p, t, i) * LD + c];
-        ct_phase<A, S::rs(p)>(a, v, twl, S::s0(p), grp<LOGN1, LV>(p, t));
+        ct_phase<A, S::rs(p), rp_of<A>(RP_FRESH), S::s0(p)>(a, v, twl, S::s0(p), grp<LOGN1, LV>(p, t));
       } else {
-        ct_phase<A, S::rs(p)>(a, v, tw, 0u, 0u);
+        ct_phase<A, S::rs(p), rp_of<A>(RP_FRESH), 0>(a, v, tw, 0u, 0u);
       }
     });
 #pragma unroll
@@ -486,9 +493,10 @@ k_row(const typename A::word* in, typename A::word* out, const typename A::tw_t*
         wave_lds_sync();
 #pragma unroll
         for (int i = 0; i < V; ++i) v[i] = sh[pad16(pos<LOGN2, LV>(p, t, i))];
-        ct_phase<A, S::rs(p)>(a, v, tw, logN1 + S::s0(p), (r << S::s0(p)) + grp<LOGN2, LV>(p, t));
+        ct_phase<A, S::rs(p), rp_of<A>(RP_LAZY), S::s0(p)>(a, v, tw, logN1 + S::s0(p),
+                                                           (r << S::s0(p)) + grp<LOGN2, LV>(p, t));
       } else {
-        ct_phase<A, S::rs(p)>(a, v, &tw0[rl][0], 0u, 0u);
+        ct_phase<A, S::rs(p), rp_of<A>(RP_LAZY), 0>(a, v, &tw0[rl][0], 0u, 0u);
       }
     });
     if constexpr (NATURAL) {
@@ -607,26 +615,27 @@ __device__ __forceinline__ uint32_t cyc_pos(uint32_t m) {
   return (1u << s) + ((g & ((1u << k) - 1u)) << S0) + (g >> k);
 }
 
-template <class A, int RS, bool FIRST, int V>
+template <class A, int RS, bool FIRST, int RP = RP_ALL, int J0 = 0, int V>
 __device__ __forceinline__ void ct_phase_cyc(const A& a, typename A::word (&v)[V], const typename A::tw_t* tw,
                                              uint32_t S0, uint32_t Hg) {
-#pragma unroll
-  for (int k = 0; k < RS; ++k) {
+  static_for<0, RS>([&](auto K_) {
+    constexpr int k = decltype(K_)::value;
+    constexpr bool RED = reduces_x(RP, J0 + k);
 #pragma unroll
     for (int j = 0; j < (1 << k); ++j) {
       if (FIRST && j == 0) {
 #pragma unroll
-        for (int m = 0; m < ((V / 2) >> k); ++m) a.ct1(v[m], v[m + ((V / 2) >> k)]);
+        for (int m = 0; m < ((V / 2) >> k); ++m) a.template ct1<RED>(v[m], v[m + ((V / 2) >> k)]);
       } else {
         const typename A::tw_t w = tw[(1u << (S0 + k)) + ((uint32_t)j << S0) + Hg];  // see cyc_pos
 #pragma unroll
         for (int m = 0; m < ((V / 2) >> k); ++m) {
           const int i0 = j * (V >> k) + m;
-          a.ct(v[i0], v[i0 + ((V / 2) >> k)], w);
+          a.template ct<RED>(v[i0], v[i0 + ((V / 2) >> k)], w);
         }
       }
     }
-  }
+  });
 }
 template <class A, int RS, bool FIRST, int V>
 __device__ __forceinline__ void gs_phase_cyc(const A& a, typename A::word (&v)[V], const typename A::tw_t* tw,
@@ -700,7 +709,7 @@ k_row_tw(const typename A::word* in, typename A::word* out, const typename A::tw
 #pragma unroll
         for (int i = 0; i < V; ++i) v[i] = sh[pad16(pos<LOGN2, LV>(p, t, i))];
       }
-      ct_phase_cyc<A, S::rs(p), p == 0>(a, v, cyc, S::s0(p), grp<LOGN2, LV>(p, t));
+      ct_phase_cyc<A, S::rs(p), p == 0, rp_of<A>(RP_FRESH), S::s0(p)>(a, v, cyc, S::s0(p), grp<LOGN2, LV>(p, t));
     });
     if constexpr (NATURAL) {
       if (S::NPH > 1) wave_lds_sync();
@@ -809,7 +818,7 @@ k_tiny(typename A::word* __restrict__ data, const typename A::tw_t* __restrict__
       for (uint32_t g = 0; g < (1u << s); ++g) {
         const typename A::tw_t w = tw[(1u << s) + g];
 #pragma unroll
-        for (uint32_t m = 0; m < h; ++m) a.ct(v[g * 2 * h + m], v[g * 2 * h + m + h], w);
+        for (uint32_t m = 0; m < h; ++m) a.template ct<!A::kWide>(v[g * 2 * h + m], v[g * 2 * h + m + h], w);
       }
     }
 #pragma unroll

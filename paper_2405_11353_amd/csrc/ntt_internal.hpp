@@ -29,6 +29,9 @@ struct ntt_plan {
   int path = NTT_PATH_LDS;
   int logN1 = 0;
   int exact = 0;
+  // every modulus below 2^60 (64-bit words): the forward kernels keep values in
+  // [0, 16q) and skip about half of their reductions (approximate quotient)
+  bool wide = false;
   std::mutex mu;  // guards scratch and the paper-variant tables
   std::vector<ScratchSlot> scratch;
   // tables of the paper's algorithm variants (cyclic plans), built on first use

@@ -186,6 +186,7 @@ void modinfo(uint64_t q, int word, void* out) {
     for (int i = 0; i < 6; ++i) inv *= 2u - q * inv;
     const uint64_t r1 = (uint64_t)(((u128)1 << 64) % q);
     m[0] = q;
+    m[1] = 0 - 8 * q;  // wraps for q >= 2^61, where the wide range is not used
     m[2] = 0 - q;
     m[3] = inv;
     m[4] = r1;

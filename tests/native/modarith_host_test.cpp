@@ -105,6 +105,88 @@ static int test64(uint64_t q) {
   return 0;
 }
 
+// the wide range (q < 2^60, forward values in [0, 16q)): a reducing CT
+// butterfly takes x anywhere below 16q and leaves both outputs below 12q; a
+// skipping one needs x below 12q and leaves them below 16q. Then whole
+// chains of stages under the two reduction patterns, from inputs at the top
+// of their ranges, against the 128-bit value of each output.
+static int test_wide(uint64_t q) {
+  ModInfo64 m{};
+  m.q = q;
+  m.nq = 0 - q;
+  m.n2q = 0 - 2 * q;
+  m.n4q = 0 - 4 * q;
+  m.n8q = 0 - 8 * q;
+  Arith64<false, true> W;
+  W.load(m);
+  for (int it = 0; it < 200000; ++it) {
+    const uint64_t w = rnd() % q;
+    const Tw64 t{w, (uint64_t)(((u128)w << 64) / q)};
+    const uint64_t y = it & 1 ? rnd() : rnd() % (16 * q);
+    const uint64_t x16 = it < 4 ? 16 * q - 1 - it : rnd() % (16 * q);
+    const uint64_t x12 = it < 4 ? 12 * q - 1 - it : rnd() % (12 * q);
+    const uint64_t T = mulm(y % q, w, q);
+    uint64_t a = x16, b = y;
+    W.ct<true>(a, b, t);
+    CHECK(a < 12 * q && b < 12 * q, "wide reducing ct range");
+    CHECK(a % q == (x16 % q + T) % q && b % q == (x16 % q + q - T) % q, "wide reducing ct value");
+    a = x12;
+    b = y;
+    W.ct<false>(a, b, t);
+    CHECK(a < 16 * q && b < 16 * q, "wide skipping ct range");
+    CHECK(a % q == (x12 % q + T) % q && b % q == (x12 % q + q - T) % q, "wide skipping ct value");
+    const uint64_t y16 = rnd() % (16 * q);
+    a = x16;
+    b = y16;
+    W.ct1<true>(a, b);
+    CHECK(a < 12 * q && b < 12 * q && a % q == (x16 % q + y16 % q) % q && b % q == (x16 % q + q - y16 % q) % q,
+          "wide reducing ct1");
+    a = x12;
+    b = y16;
+    W.ct1<false>(a, b);
+    CHECK(a < 16 * q && b < 16 * q && a % q == (x12 % q + y16 % q) % q && b % q == (x12 % q + q - y16 % q) % q,
+          "wide skipping ct1");
+    CHECK(W.canon_fwd(x16) == x16 % q, "wide canonical");
+  }
+  // chains: stage j of a pass reduces iff reduces_x(pattern, j); every value
+  // meets the precondition of the butterfly it enters (checked inside by the
+  // ranges above: here the bound before each stage and the final values)
+  for (int pat = RP_FRESH; pat <= RP_LAZY; ++pat) {
+    for (int trial = 0; trial < 2000; ++trial) {
+      uint64_t v[2], ref[2];
+      for (int i = 0; i < 2; ++i) {
+        v[i] = pat == RP_FRESH ? (trial < 2 ? 4 * q - 1 : rnd() % (4 * q)) : (trial < 2 ? 16 * q - 1 : rnd() % (16 * q));
+        ref[i] = v[i] % q;
+      }
+      for (int j = 0; j < 20; ++j) {
+        const uint64_t w = rnd() % q;
+        const Tw64 t{w, (uint64_t)(((u128)w << 64) / q)};
+        const bool red = reduces_x(pat, j);
+        CHECK(v[0] < 16 * q && v[1] < 16 * q, "chain bound before stage %d", j);
+        CHECK(red || v[0] < 12 * q, "chain: stage %d skips with x >= 12q", j);
+        if (red) W.ct<true>(v[0], v[1], t);
+        else W.ct<false>(v[0], v[1], t);
+        const uint64_t T = mulm(ref[1], w, q);
+        const uint64_t r0 = (ref[0] + T) % q, r1 = (ref[0] + q - T) % q;
+        ref[0] = r0;
+        ref[1] = r1;
+        CHECK(v[0] % q == ref[0] && v[1] % q == ref[1], "chain value at stage %d", j);
+        // the next stage's x is either output: alternate which one continues
+        if (trial & 1) {
+          const uint64_t s = v[0];
+          v[0] = v[1];
+          v[1] = s;
+          const uint64_t sr = ref[0];
+          ref[0] = ref[1];
+          ref[1] = sr;
+        }
+      }
+      CHECK(W.canon_fwd(v[0]) == ref[0] && W.canon_fwd(v[1]) == ref[1], "chain canonical");
+    }
+  }
+  return 0;
+}
+
 static int test32(uint32_t q) {
   uint32_t inv = q;
   for (int i = 0; i < 5; ++i) inv *= 2u - q * inv;
@@ -153,6 +235,11 @@ int main() {
                           1152921504606748673ull, 1152921504605798401ull, 998244353ull, 12289ull};
   for (uint64_t q : q64)
     if (test64(q)) return 1;
+  // the wide range: the largest prime below 2^60, the workload primes, small ones
+  const uint64_t qw[] = {1152921504606846883ull, 1152921504606584833ull, 1152921504605798401ull, 998244353ull,
+                         12289ull};
+  for (uint64_t q : qw)
+    if (test_wide(q)) return 1;
   const uint32_t q32[] = {998244353u, 469762049u, 167772161u, 1073479681u /* < 2^30 */, 12289u};
   for (uint32_t q : q32)
     if (test32(q)) return 1;
