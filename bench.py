@@ -442,6 +442,8 @@ def bench_batched(ntt, si, torch, reps=10):
     inv = ntt.Batch([(j.N, primes[:j.L], ntt.NTT_JOB_INVERSE, t) for j, t in zip(jobs, tensors)])
     eager = ntt.Batch([(j.N, primes[:j.L], ntt.NTT_JOB_FORWARD, t) for j, t in zip(jobs, tensors)],
                       flags=ntt.NTT_BATCH_NO_GRAPH)
+    branches = ntt.Batch([(j.N, primes[:j.L], ntt.NTT_JOB_FORWARD, t) for j, t in zip(jobs, tensors)],
+                         flags=ntt.NTT_BATCH_BRANCHES)
     import oracle
     # the oracle's forward of the first and last limb of every job
     chk_limbs = [sorted({0, j.L - 1}) for j in jobs]
@@ -478,8 +480,12 @@ def bench_batched(ntt, si, torch, reps=10):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / n * 1e3
 
+    reload()
+    branches.run()
+    check_forward("graph batch with parallel branches")
     us_graph = timed(fwd.run, reps)
     us_eager = timed(eager.run, reps)
+    us_branches = timed(branches.run, reps)
     # autotuned: every bucket size is tuned at its own item count, then the
     # batch is rebuilt (buckets pick their variants from the tuning table). The
     # process's table (the shipped one) is saved first and restored after, so
@@ -520,7 +526,7 @@ def bench_batched(ntt, si, torch, reps=10):
 
     us_call = timed(per_call, max(2, reps // 2))
     info = fwd.info
-    for b in (fwd, inv, eager):
+    for b in (fwd, inv, eager, branches):
         b.close()
     for p_ in plans.values():
         p_.close()
@@ -529,14 +535,15 @@ def bench_batched(ntt, si, torch, reps=10):
            "tuned_graph_us": round(us_tuned, 1), "tuned_ntt_per_s": round(n_ntt / (us_tuned * 1e-6), 1),
            "tuned_choices": choices,
            "graph_alg_GBs": round(16 * words / (us_graph * 1e-6) / 1e9, 1),
-           "eager_us": round(us_eager, 1), "per_call_us": round(us_call, 1),
+           "eager_us": round(us_eager, 1), "branches_graph_us": round(us_branches, 1),
+           "per_call_us": round(us_call, 1),
            "per_call_ntt_per_s": round(n_ntt / (us_call * 1e-6), 1),
            "graph_speedup_vs_per_call": round(us_call / us_graph, 2),
            "buckets": info["buckets"], "kernels": info["kernels"], "round_trip_exact": bool(exact),
            "checked": "forward of every job (first and last limb) vs the oracle, for the default and the tuned "
                       "batch; forward + inverse of every job is the identity"}
     log(f"batched: autotuned graph {us_tuned:.0f} us; choices {choices}")
-    log(f"batched: {n_ntt} NTTs in {us_graph:.0f} us (graph), {us_eager:.0f} us (eager), "
+    log(f"batched: {n_ntt} NTTs in {us_graph:.0f} us (graph), {us_branches:.0f} us (graph of parallel branches), {us_eager:.0f} us (eager), "
         f"{us_call:.0f} us (per-call) -> {res['graph_ntt_per_s'] / 1e6:.2f} M NTT/s")
     return res
 

@@ -250,8 +250,8 @@ int ntt_tune_clear(void);
  * contiguous 64-bit words at d_data, limb l reduced mod moduli[l] (q < 2^61,
  * prime, 2N | q-1). Items (polynomial, limb) are bucketed by (N, op); each
  * bucket runs the tuned (or default) variant; the buckets' kernels are
- * captured once, at creation, as parallel branches of one hipGraph, so a run
- * is a single hipGraphLaunch. Twiddle tables come from a process-wide pool
+ * captured once, at creation, into one hipGraph (one bucket after another,
+ * the largest first), so a run is a single hipGraphLaunch. Twiddle tables come from a process-wide pool
  * keyed by (device, q, N) and stay resident. The batch owns its descriptor
  * table, four-step scratch and graph; the caller owns the job buffers, which
  * must stay valid (the graph holds their addresses). Natural-order spectra. */
@@ -271,6 +271,8 @@ typedef struct {
   uint64_t scratch_bytes, twiddle_pool_bytes;
 } ntt_batch_info;
 #define NTT_BATCH_NO_GRAPH 0x1u  /* launch the kernels directly on each run */
+#define NTT_BATCH_BRANCHES 0x2u  /* the graph holds the buckets as parallel branches
+                                    instead of one after another, largest first */
 ntt_batch* ntt_batch_create(const ntt_job_desc* jobs, uint32_t n_jobs, uint32_t flags);
 int ntt_batch_run(ntt_batch* batch, void* stream);
 int ntt_batch_get_info(const ntt_batch* batch, ntt_batch_info* info);

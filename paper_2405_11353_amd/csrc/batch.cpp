@@ -3,7 +3,8 @@
 // twiddle tables (from the process-wide pool) and modulus constants; items
 // are bucketed by (N, direction), each bucket runs the variant the tuning
 // table (or the default) picks for its size, and the buckets are captured as
-// parallel branches of one graph.
+// one graph: one bucket after another (largest first), or as parallel
+// branches.
 #include <algorithm>
 #include <map>
 #include <new>
@@ -14,6 +15,7 @@
 namespace {
 struct Bucket {
   int logN, op, path, logN1;
+  bool wide = true;         // every item's modulus below 2^60 (forward: values in [0, 16q))
   std::vector<nttk::ItemDesc> items;
   size_t desc_off = 0;      // index of the first descriptor in the device table
   void* scratch = nullptr;  // four-step intermediate for all items of the bucket
@@ -56,6 +58,7 @@ static hipError_t launch_bucket(const ntt_batch* b, const Bucket& k, hipStream_t
   c.path = k.path == NTT_PATH_LDS ? nttk::PATH_LDS : nttk::PATH_TWO;
   c.logN = k.logN;
   c.logN1 = k.logN1;
+  c.wide = k.wide ? 1 : 0;
   c.desc = b->d_desc + k.desc_off;
   c.items = (uint32_t)k.items.size();
   c.stream = s;
@@ -83,6 +86,7 @@ static int build(ntt_batch* b, const ntt_job_desc* jobs, uint32_t n_jobs) {
       const uint64_t q = J.moduli[l];
       ntti::PoolEntry e;  // the pool validates (q, N) when it first builds its tables
       if ((err = ntti::pool_get(64, q, (uint32_t)lg, &e)) != NTT_OK) return err;
+      k.wide = k.wide && q < (1ull << 60);
       nttk::ItemDesc d{};
       d.data = (uint64_t*)J.d_data + ((size_t)l << lg);
       d.tw_fwd = e.tw_fwd;
@@ -96,9 +100,15 @@ static int build(ntt_batch* b, const ntt_job_desc* jobs, uint32_t n_jobs) {
     auto& v = kv.second.items;
     std::stable_sort(v.begin(), v.end(), [](const nttk::ItemDesc& x, const nttk::ItemDesc& y) { return x.mod < y.mod; });
   }
+  // largest buckets first (the graph then ends on the short ones)
+  std::vector<Bucket> order;
+  for (auto& kv : by) order.push_back(kv.second);
+  std::stable_sort(order.begin(), order.end(), [](const Bucket& x, const Bucket& y) {
+    return (x.items.size() << x.logN) > (y.items.size() << y.logN);
+  });
   size_t off = 0;
-  for (auto& kv : by) {
-    Bucket k = kv.second;
+  for (auto& ko : order) {
+    Bucket k = std::move(ko);
     const uint32_t n = (uint32_t)k.items.size();
     int path, logN1, exact = 0;
     if (!ntti::tune_lookup(64, k.logN, n, &path, &logN1, &exact) || exact ||
@@ -129,10 +139,27 @@ static int build(ntt_batch* b, const ntt_job_desc* jobs, uint32_t n_jobs) {
     return NTT_ERR_HIP;
   if (b->flags & NTT_BATCH_NO_GRAPH) return NTT_OK;
 
-  // one graph: fork from the capture stream to a branch per bucket, join back
+  // one graph: every bucket in turn on the capture stream; or with
+  // NTT_BATCH_BRANCHES, a fork from the capture stream to a branch per
+  // bucket, joined back
   if (hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess)
     return NTT_ERR_HIP;
+  if (!(b->flags & NTT_BATCH_BRANCHES)) {
+    if (hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal) != hipSuccess) return NTT_ERR_HIP;
+    hipError_t e = hipSuccess;
+    for (auto& k : b->buckets)
+      if (e == hipSuccess) e = launch_bucket(b, k, b->capture);
+    hipGraph_t g = nullptr;
+    const hipError_t ee = hipStreamEndCapture(b->capture, &g);
+    if (e != hipSuccess || ee != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return e == hipErrorNotSupported ? NTT_ERR_UNSUPPORTED : NTT_ERR_HIP;
+    }
+    b->graph = g;
+    if (hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess) return NTT_ERR_HIP;
+    return NTT_OK;
+  }
   for (auto& k : b->buckets)
     if (hipStreamCreateWithFlags(&k.branch, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&k.done, hipEventDisableTiming) != hipSuccess)
@@ -159,7 +186,7 @@ static int build(ntt_batch* b, const ntt_job_desc* jobs, uint32_t n_jobs) {
 extern "C" {
 
 ntt_batch* ntt_batch_create(const ntt_job_desc* jobs, uint32_t n_jobs, uint32_t flags) {
-  if (!jobs || n_jobs == 0 || (flags & ~NTT_BATCH_NO_GRAPH)) {
+  if (!jobs || n_jobs == 0 || (flags & ~(NTT_BATCH_NO_GRAPH | NTT_BATCH_BRANCHES))) {
     ntt_set_last_error(NTT_ERR_ARG);
     return nullptr;
   }

@@ -40,12 +40,16 @@ k_ind_pointwise(const ItemDesc* __restrict__ desc, uint32_t items, uint32_t max_
 
 namespace {
 
-using A = Arith64<false>;
-using W = A::word;
-using TW = A::tw_t;
+using W = uint64_t;
 using M = ModInfo64;
+using AN = Arith64<false>;        // narrow range: inverse, and forward items with some q >= 2^60
+using AW = Arith64<false, true>;  // wide range: forward items whose moduli are all below 2^60
 
-template <int LOGN>
+// values per thread as in the plan kernels (dispatch.inc): 8 in the column
+// passes and the inverse row pass, 16 in the forward row pass
+constexpr int lv_for(int want, int logn) { return (16 << (logn - want)) <= 1024 ? want : 4; }
+
+template <class A, int LOGN>
 hipError_t ind_lds(const BatchLaunch& c, bool fwd) {
   constexpr int T = (1 << LOGN) / 16;
   constexpr int P = T >= 256 ? 1 : 256 / T;
@@ -55,82 +59,102 @@ hipError_t ind_lds(const BatchLaunch& c, bool fwd) {
   return hipGetLastError();
 }
 
-template <int LOGN1>
+template <class A, int LOGN1>
 hipError_t ind_col(const BatchLaunch& c, bool fwd, int io) {
+  constexpr int LV = lv_for(3, LOGN1);
   const uint32_t tiles = (1u << (c.logN - LOGN1)) / 16;
-  const dim3 grid(c.items * tiles), block(16 << (LOGN1 - 4));
-  if (fwd) hipLaunchKernelGGL((k_col<A, LOGN1, 16, true, true>), grid, block, 0, c.stream, nullptr, nullptr, nullptr, nullptr, 1u, (uint32_t)c.logN, c.items, c.desc, io);
-  else hipLaunchKernelGGL((k_col<A, LOGN1, 16, false, true>), grid, block, 0, c.stream, nullptr, nullptr, nullptr, nullptr, 1u, (uint32_t)c.logN, c.items, c.desc, io);
+  const dim3 grid(c.items * tiles), block(16 << (LOGN1 - LV));
+  if (fwd) hipLaunchKernelGGL((k_col<A, LOGN1, 16, true, true, LV>), grid, block, 0, c.stream, nullptr, nullptr, nullptr, nullptr, 1u, (uint32_t)c.logN, c.items, c.desc, io);
+  else hipLaunchKernelGGL((k_col<A, LOGN1, 16, false, true, LV>), grid, block, 0, c.stream, nullptr, nullptr, nullptr, nullptr, 1u, (uint32_t)c.logN, c.items, c.desc, io);
   return hipGetLastError();
 }
 
-template <int LOGN2>
+template <class A, int LOGN2>
 hipError_t ind_row(const BatchLaunch& c, bool fwd, int io) {
   const uint32_t tiles = (1u << c.logN1) / 16;
-  const dim3 grid(c.items * tiles), block(16 << (LOGN2 - 4));
   const uint32_t lg = (uint32_t)c.logN;
-  if (fwd) hipLaunchKernelGGL((k_row<A, LOGN2, true, true, false, true>), grid, block, 0, c.stream, nullptr, nullptr, nullptr, nullptr, 1u, lg, c.items, c.items, nullptr, c.desc, io);
-  else hipLaunchKernelGGL((k_row<A, LOGN2, false, true, false, true>), grid, block, 0, c.stream, nullptr, nullptr, nullptr, nullptr, 1u, lg, c.items, c.items, nullptr, c.desc, io);
+  if (fwd) {
+    constexpr int LV = 4;
+    hipLaunchKernelGGL((k_row<A, LOGN2, true, true, false, true, LV>), dim3(c.items * tiles), dim3(16 << (LOGN2 - LV)), 0,
+                       c.stream, nullptr, nullptr, nullptr, nullptr, 1u, lg, c.items, c.items, nullptr, c.desc, io);
+  } else {
+    constexpr int LV = lv_for(3, LOGN2);
+    hipLaunchKernelGGL((k_row<A, LOGN2, false, true, false, true, LV>), dim3(c.items * tiles), dim3(16 << (LOGN2 - LV)), 0,
+                       c.stream, nullptr, nullptr, nullptr, nullptr, 1u, lg, c.items, c.items, nullptr, c.desc, io);
+  }
   return hipGetLastError();
 }
 
+template <class A>
 hipError_t col_sw(int lg1, const BatchLaunch& c, bool fwd, int io) {
   switch (lg1) {
-    case 6: return ind_col<6>(c, fwd, io);
-    case 7: return ind_col<7>(c, fwd, io);
-    case 8: return ind_col<8>(c, fwd, io);
-    case 9: return ind_col<9>(c, fwd, io);
+    case 6: return ind_col<A, 6>(c, fwd, io);
+    case 7: return ind_col<A, 7>(c, fwd, io);
+    case 8: return ind_col<A, 8>(c, fwd, io);
+    case 9: return ind_col<A, 9>(c, fwd, io);
     default: return hipErrorNotSupported;
   }
 }
+template <class A>
 hipError_t row_sw(int lg2, const BatchLaunch& c, bool fwd, int io) {
   switch (lg2) {
-    case 6: return ind_row<6>(c, fwd, io);
-    case 7: return ind_row<7>(c, fwd, io);
-    case 8: return ind_row<8>(c, fwd, io);
-    case 9: return ind_row<9>(c, fwd, io);
+    case 6: return ind_row<A, 6>(c, fwd, io);
+    case 7: return ind_row<A, 7>(c, fwd, io);
+    case 8: return ind_row<A, 8>(c, fwd, io);
+    case 9: return ind_row<A, 9>(c, fwd, io);
     default: return hipErrorNotSupported;
   }
+}
+
+template <class A>
+hipError_t lds_sw(const BatchLaunch& c, bool fwd) {
+  switch (c.logN) {
+    case 4: return ind_lds<A, 4>(c, fwd);
+    case 5: return ind_lds<A, 5>(c, fwd);
+    case 6: return ind_lds<A, 6>(c, fwd);
+    case 7: return ind_lds<A, 7>(c, fwd);
+    case 8: return ind_lds<A, 8>(c, fwd);
+    case 9: return ind_lds<A, 9>(c, fwd);
+    case 10: return ind_lds<A, 10>(c, fwd);
+    case 11: return ind_lds<A, 11>(c, fwd);
+    case 12: return ind_lds<A, 12>(c, fwd);
+    case 13: return ind_lds<A, 13>(c, fwd);
+    case 14: return ind_lds<A, 14>(c, fwd);
+    default: return hipErrorNotSupported;
+  }
+}
+
+template <class A>
+hipError_t run_batch(const BatchLaunch& c, bool fwd) {
+  if (c.path == PATH_LDS) return lds_sw<A>(c, fwd);
+  if (c.path == PATH_TWO) {
+    if (!shape_supported(64, 0, PATH_TWO, c.logN, c.logN1)) return hipErrorNotSupported;
+    const int lg2 = c.logN - c.logN1;
+    hipError_t e;
+    if (fwd) {
+      if ((e = col_sw<A>(c.logN1, c, true, IO_DATA_SCRATCH)) != hipSuccess) return e;
+      return row_sw<A>(lg2, c, true, IO_SCRATCH_DATA);
+    }
+    if ((e = row_sw<A>(lg2, c, false, IO_DATA_SCRATCH)) != hipSuccess) return e;
+    return col_sw<A>(c.logN1, c, false, IO_SCRATCH_DATA);
+  }
+  return hipErrorNotSupported;
 }
 
 }  // namespace
 
 hipError_t launch_batch_u64(const BatchLaunch& c, bool fwd) {
   if (c.items == 0) return hipSuccess;
-  if (c.path == PATH_LDS) {
-    switch (c.logN) {
-      case 4: return ind_lds<4>(c, fwd);
-      case 5: return ind_lds<5>(c, fwd);
-      case 6: return ind_lds<6>(c, fwd);
-      case 7: return ind_lds<7>(c, fwd);
-      case 8: return ind_lds<8>(c, fwd);
-      case 9: return ind_lds<9>(c, fwd);
-      case 10: return ind_lds<10>(c, fwd);
-      case 11: return ind_lds<11>(c, fwd);
-      case 12: return ind_lds<12>(c, fwd);
-      case 13: return ind_lds<13>(c, fwd);
-      case 14: return ind_lds<14>(c, fwd);
-      default: return hipErrorNotSupported;
-    }
-  }
-  if (c.path == PATH_TWO) {
-    if (!shape_supported(64, 0, PATH_TWO, c.logN, c.logN1)) return hipErrorNotSupported;
-    const int lg2 = c.logN - c.logN1;
-    hipError_t e;
-    if (fwd) {
-      if ((e = col_sw(c.logN1, c, true, IO_DATA_SCRATCH)) != hipSuccess) return e;
-      return row_sw(lg2, c, true, IO_SCRATCH_DATA);
-    }
-    if ((e = row_sw(lg2, c, false, IO_DATA_SCRATCH)) != hipSuccess) return e;
-    return col_sw(c.logN1, c, false, IO_SCRATCH_DATA);
-  }
-  return hipErrorNotSupported;
+  // the wide range changes the forward kernels only (see launch_ntt)
+  return c.wide && fwd ? run_batch<AW>(c, true) : run_batch<AN>(c, fwd);
 }
 
+// a column pass alone (the server's products feed it to the fused row
+// kernel, which takes the narrow range)
 hipError_t launch_batch_col_u64(const BatchLaunch& c, bool fwd, int io) {
   if (c.items == 0) return hipSuccess;
-  if (c.path != PATH_TWO || !shape_supported(64, 0, PATH_TWO, c.logN, c.logN1)) return hipErrorNotSupported;
-  return col_sw(c.logN1, c, fwd, io);
+  if (c.path != PATH_TWO || c.wide || !shape_supported(64, 0, PATH_TWO, c.logN, c.logN1)) return hipErrorNotSupported;
+  return col_sw<AN>(c.logN1, c, fwd, io);
 }
 
 hipError_t launch_ind_copy(const ItemDesc* desc, uint32_t items, uint32_t max_logn, hipStream_t s) {

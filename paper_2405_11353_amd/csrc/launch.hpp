@@ -52,6 +52,7 @@ struct Launch {
 struct BatchLaunch {
   int path = PATH_LDS;
   int logN = 0, logN1 = 0;
+  int wide = 0;  // forward only: every item's q < 2^60 (values in [0, 16q))
   const ItemDesc* desc = nullptr;  // device pointer, items entries
   uint32_t items = 0;
   hipStream_t stream = nullptr;

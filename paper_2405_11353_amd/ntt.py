@@ -26,6 +26,7 @@ _lib = None
 
 NTT_JOB_FORWARD, NTT_JOB_INVERSE = 0, 1
 NTT_BATCH_NO_GRAPH = 0x1
+NTT_BATCH_BRANCHES = 0x2
 
 
 class JobDesc(ctypes.Structure):
@@ -373,13 +374,33 @@ class Server:
 
     def __init__(self, hbm_budget_bytes=4 << 30, n_streams=4, max_batch_items=2048, flags=0,
                  simulate_ns_per_item=0.0):
+        self.simulate = bool(flags & NTT_SERVER_SIMULATE)
         cfg = ServerConfig(hbm_budget_bytes, n_streams, max_batch_items, flags, 0, simulate_ns_per_item)
         self.handle = lib().ntt_server_create(ctypes.byref(cfg))
         if not self.handle:
             raise NttError(ntt_last_error(), "ntt_server_create")
         self._keep = {}
 
+    def _check_buffers(self, op, N, moduli, a, out, b):
+        """Each buffer must be a contiguous GPU tensor of 64-bit words holding
+        at least L*N of them (b only for products): the kernels index L*N
+        words of each, so anything smaller is refused before the C call. A
+        simulating server never touches its buffers and takes anything (the
+        C call still checks what it can)."""
+        if self.simulate:
+            return
+        need = len(moduli) * int(N)
+        named = [("a", a), ("out", out)] + ([("b", b)] if op == NTT_REQ_POLYMUL or b is not None else [])
+        for name, t in named:
+            if t is None or not hasattr(t, "data_ptr"):
+                raise ValueError(f"{name} must be a GPU tensor of 64-bit words")
+            if not t.is_cuda or t.element_size() != 8:
+                raise ValueError(f"{name} must hold 64-bit words on the GPU")
+            if t.numel() < need:
+                raise ValueError(f"{name} holds {t.numel()} words, the request needs L*N = {need}")
+
     def submit(self, op, N, moduli, a, out, b=None) -> int:
+        self._check_buffers(op, N, moduli, a, out, b)
         mods = _u64_array(moduli)
         req = Request(op, N, len(moduli), 0, mods, _ptr(a), _ptr(b) if b is not None else None, _ptr(out))
         t = ctypes.c_uint64()
@@ -390,6 +411,7 @@ class Server:
     def make_request(self, op, N, moduli, a, out, b=None):
         """A prepared request (ctypes struct) for submit_request: builds the
         moduli array and resolves the device pointers once."""
+        self._check_buffers(op, N, moduli, a, out, b)
         mods = _u64_array(moduli)
         req = Request(op, N, len(moduli), 0, mods, _ptr(a), _ptr(b) if b is not None else None, _ptr(out))
         return (req, mods, a, b, out)

@@ -43,7 +43,7 @@ SPECS = [(4, 3, 0), (8, 1, 0), (12, 2, 0), (13, 4, 0), (14, 3, 0), (15, 2, 0), (
          (12, 5, 1), (16, 2, 1), (10, 2, 0), (16, 1, 0), (12, 1, 0)]
 
 
-@pytest.mark.parametrize("flags", [0, 1])
+@pytest.mark.parametrize("flags", [0, 1, 2])
 def test_batch_mixed_jobs_match_oracle(ntt, flags):
     log(f"case batch mixed flags={flags}")
     jobs = make_jobs(1, SPECS)
@@ -51,7 +51,7 @@ def test_batch_mixed_jobs_match_oracle(ntt, flags):
     with ntt.Batch([(N, m, op, t) for (N, m, op, _), t in zip(jobs, tensors)], flags=flags) as b:
         info = b.info
         assert info["items"] == sum(L for (_, L, _) in SPECS)
-        assert info["uses_graph"] == (0 if flags else 1)
+        assert info["uses_graph"] == (0 if flags == 1 else 1)
         b.run()
         for job, t in zip(jobs, tensors):
             np.testing.assert_array_equal(from_dev(t).reshape(job[3].shape), expected(job))

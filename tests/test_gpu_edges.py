@@ -169,7 +169,7 @@ def _uneven_batch():
     return jobs, primes, hosts
 
 
-@pytest.mark.parametrize("flags", [0, 1])
+@pytest.mark.parametrize("flags", [0, 1, 2])
 def test_uneven_batch_full_size_every_item(ntt, flags):
     """256 polynomials (4100 transforms, about 105 M coefficients): the
     forward batch (one graph launch, or eager launches with flags = 1) against
@@ -236,3 +236,24 @@ def test_server_requests_up_to_40_limbs(ntt):
             want = oracle_inv(prod, moduli)
         np.testing.assert_array_equal(from_dev(dout).reshape(a.shape), want,
                                       err_msg=f"op={op} N={N} L={len(moduli)}")
+
+
+@pytest.mark.parametrize("flags", [0, 2])
+def test_61bit_batch_jobs(ntt, flags):
+    """Batch jobs whose moduli reach 2^61 (the narrow range) beside jobs of
+    60-bit primes (the wide one), forward and inverse, against the oracle."""
+    P60 = si.ntt_primes(60, 18, 4)
+    s = si.Stream(si.BASE_SEED + 51)
+    specs = [(12, P61[:3], 0), (16, P61[:2], 0), (17, P61[:1], 1), (14, P60[:3], 0), (16, P60[:2] + P61[:1], 0),
+             (13, P61[:2], 1), (10, P61[:2], 0)]
+    jobs = []
+    for logn, moduli, op in specs:
+        N = 1 << logn
+        jobs.append((N, moduli, op, np.stack([s.uniform_mod(q, N) for q in moduli])))
+    log(f"case 61-bit batch jobs flags={flags}")
+    tensors = [to_dev(x) for (_, _, _, x) in jobs]
+    with ntt.Batch([(N, m, op, t) for (N, m, op, _), t in zip(jobs, tensors)], flags=flags) as b:
+        b.run()
+        for (N, m, op, x), t in zip(jobs, tensors):
+            want = (oracle_fwd if op == 0 else oracle_inv)(x[None], m)[0]
+            np.testing.assert_array_equal(from_dev(t).reshape(x.shape), want, err_msg=f"N={N} op={op}")

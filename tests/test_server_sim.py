@@ -108,3 +108,47 @@ def test_destroy_drains_queued_work(ntt):
     for _ in range(10):
         s.submit(ntt.NTT_REQ_NTT, 1024, P18[:2], FAKE, FAKE)
     s.close()   # returns only after the queue is empty
+
+
+class _FakeTensor:
+    """Looks like a GPU tensor to the binding's checks; never dereferenced."""
+
+    def __init__(self, numel, cuda=True, width=8):
+        self._n, self.is_cuda, self._w = numel, cuda, width
+
+    def numel(self):
+        return self._n
+
+    def element_size(self):
+        return self._w
+
+    def is_contiguous(self):
+        return True
+
+    def data_ptr(self):
+        return FAKE
+
+
+def test_undersized_buffers_are_refused_before_submit(ntt):
+    """The binding checks every buffer of a request against L*N 64-bit words
+    before the C call: nothing reaches the server (its counters stay at 0)."""
+    N, mods = 1 << 12, P18[:3]
+    with sim(ntt, n_streams=1) as s:
+        s.simulate = False  # check as a real server would
+        ok = _FakeTensor(3 * N)
+        bad = [(_FakeTensor(3 * N - 1), ok, None, ntt.NTT_REQ_NTT),      # a too small
+               (ok, _FakeTensor(N), None, ntt.NTT_REQ_INTT),              # out too small
+               (ok, ok, _FakeTensor(2 * N), ntt.NTT_REQ_POLYMUL),         # b too small
+               (ok, ok, None, ntt.NTT_REQ_POLYMUL),                       # product without b
+               (_FakeTensor(3 * N, cuda=False), ok, None, ntt.NTT_REQ_NTT),
+               (_FakeTensor(3 * N, width=4), ok, None, ntt.NTT_REQ_NTT),
+               (FAKE, ok, None, ntt.NTT_REQ_NTT)]                         # a bare address
+        for a, out, b, op in bad:
+            with pytest.raises(ValueError):
+                s.submit(op, N, mods, a, out, b=b)
+            with pytest.raises(ValueError):
+                s.make_request(op, N, mods, a, out, b=b)
+        assert s.stats()["submitted"] == 0
+        s.simulate = True
+        t = s.submit(ntt.NTT_REQ_POLYMUL, N, mods, ok, ok, b=ok)
+        assert s.wait(t) == 0
