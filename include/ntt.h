@@ -30,7 +30,8 @@
  * enqueue work on `stream` (a hipStream_t; NULL is the default stream) and
  * return NTT_OK; argument errors are detected before anything is enqueued and
  * returned as negative codes. Inputs must be canonical (in [0, q_l)); other
- * values give unspecified (but in-bounds) results. The functions are
+ * values give unspecified (but in-bounds) results, or NTT_ERR_RANGE with
+ * NTT_DEBUG_CHECK. The functions are
  * thread-safe for concurrent use of one plan on different streams.
  */
 #ifndef NTT_H
@@ -56,6 +57,8 @@ extern "C" {
 #define NTT_ERR_TIMEOUT (-9)     /* wait timed out; the job is still pending   */
 #define NTT_ERR_SCRATCH (-10)    /* ntt_forward_noalloc: the call needs more   */
                                  /* scratch than NTT_NOALLOC_SCRATCH_BYTES     */
+#define NTT_ERR_RANGE (-11)      /* NTT_DEBUG_CHECK: an input word is not      */
+                                 /* canonical (not below its limb's modulus)   */
 
 /* ---- plan flags ---------------------------------------------------------- */
 #define NTT_WORD32 0x1u          /* uint32_t words, every q_l < 2^30            */
@@ -63,6 +66,15 @@ extern "C" {
 #define NTT_CYCLIC 0x4u          /* the cyclic transform of Eq. 3 instead:      */
                                  /*   X_k = sum_j x_j omega^(jk), omega = c^((q-1)/N), */
                                  /*   inverse with N^-1; needs N | q-1          */
+#define NTT_DEBUG_CHECK 0x8u     /* check the canonical-input precondition: each */
+                                 /*   call first scans its inputs, synchronizes */
+                                 /*   the stream and returns NTT_ERR_RANGE (with */
+                                 /*   nothing else enqueued) if a word is not    */
+                                 /*   below its modulus. Also turned on for every */
+                                 /*   plan by the environment variable           */
+                                 /*   NTT_DEBUG_CHECK=1. For debugging: it makes  */
+                                 /*   the calls synchronous and is not for graph */
+                                 /*   capture.                                    */
 
 /* ---- kernel variants (for tuning and measurement) ------------------------- */
 #define NTT_PATH_AUTO 0          /* library default for (N, word)               */

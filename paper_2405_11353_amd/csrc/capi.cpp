@@ -1,6 +1,7 @@
 // C ABI of libntt.so: plans (parameters and resident twiddle tables),
 // argument checking, variant dispatch and per-stream scratch.
 #include <hip/hip_runtime.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -79,6 +80,18 @@ void for_limbs(uint32_t L, const std::function<void(uint32_t)>& f) {
   for (auto& t : th) t.join();
 }
 
+int debug_range(const ntt_plan* p, const void* d, uint32_t batch, void* stream) {
+  if (!p->debug_check) return NTT_OK;
+  const hipStream_t s = (hipStream_t)stream;
+  uint32_t bad = 0;
+  if (hipMemsetAsync(p->d_flag, 0, sizeof(uint32_t), s) != hipSuccess ||
+      nttk::launch_check_range(p->word, d, p->d_mod, p->L, p->logN, batch * p->L, p->d_flag, s) != hipSuccess ||
+      hipMemcpyAsync(&bad, p->d_flag, sizeof bad, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return NTT_ERR_HIP;
+  return bad ? NTT_ERR_RANGE : NTT_OK;
+}
+
 int check_modulus(uint64_t q, uint32_t N, int word) {
   const uint64_t qmax = word == 32 ? (1ull << 30) : (1ull << 61);
   if (q < 3 || q >= qmax || (q - 1) % (2ull * N) || !nttp::is_prime(q)) return NTT_ERR_MODULUS;
@@ -112,6 +125,7 @@ static void release(ntt_plan* p) {
   if (p->d_tw_inv) (void)hipFree(p->d_tw_inv);
   if (p->d_mod) (void)hipFree(p->d_mod);
   if (p->d_paper) (void)hipFree(p->d_paper);
+  if (p->d_flag) (void)hipFree(p->d_flag);
   for (auto& dir : p->d_rowtw)
     for (void* t : dir)
       if (t) (void)hipFree(t);
@@ -137,6 +151,7 @@ const char* ntt_strerror(int code) {
     case NTT_ERR_STATE: return "unknown ticket or object shut down";
     case NTT_ERR_TIMEOUT: return "timed out";
     case NTT_ERR_SCRATCH: return "workspace larger than the fixed scratch of the no-allocation entry point";
+    case NTT_ERR_RANGE: return "input word not below its modulus (NTT_DEBUG_CHECK)";
     default: return "unknown error";
   }
 }
@@ -144,7 +159,7 @@ const char* ntt_strerror(int code) {
 ntt_plan* ntt_plan_create_ex(uint32_t N, const uint64_t* moduli, uint32_t L, uint32_t flags,
                              const uint64_t* psi) {
   g_last_error = NTT_OK;
-  if (!moduli || L == 0 || (flags & ~(NTT_WORD32 | NTT_ORDER_BITREV | NTT_CYCLIC))) {
+  if (!moduli || L == 0 || (flags & ~(NTT_WORD32 | NTT_ORDER_BITREV | NTT_CYCLIC | NTT_DEBUG_CHECK))) {
     fail(NTT_ERR_ARG);
     return nullptr;
   }
@@ -222,6 +237,13 @@ ntt_plan* ntt_plan_create_ex(uint32_t N, const uint64_t* moduli, uint32_t L, uin
       hipMemcpy(p->d_mod, mod.data(), mod.size(), hipMemcpyHostToDevice) != hipSuccess) {
     release(p);
     fail(NTT_ERR_HIP);
+    return nullptr;
+  }
+  const char* dbg = getenv("NTT_DEBUG_CHECK");
+  p->debug_check = (flags & NTT_DEBUG_CHECK) || (dbg && *dbg && strcmp(dbg, "0") != 0);
+  if (p->debug_check && hipMalloc(&p->d_flag, 256) != hipSuccess) {
+    release(p);
+    fail(NTT_ERR_NOMEM);
     return nullptr;
   }
   const int rc = prepare_row_tables(p);
@@ -449,6 +471,8 @@ static int run_ntt(const ntt_plan* pc, void* data, uint32_t batch, void* stream,
   int rc = check_common(pc, batch);
   if (rc != NTT_OK) return rc;
   if (!data) return NTT_ERR_ARG;
+  // the input of a whole transform, or of its first kernel, is canonical
+  if ((stage_mask & 1) && (rc = ntti::debug_range(pc, data, batch, stream)) != NTT_OK) return rc;
   ntt_plan* p = const_cast<ntt_plan*>(pc);
   int path, logN1, exact;
   select_variant(p, batch * p->L, &path, &logN1, &exact);
@@ -536,6 +560,9 @@ static int run_mul_inverse(const ntt_plan* pc, const void* a, const void* b, voi
   int rc = check_common(pc, batch);
   if (rc != NTT_OK) return rc;
   if (!a || !b || !c) return NTT_ERR_ARG;
+  if ((stage_mask & 1) && ((rc = ntti::debug_range(pc, a, batch, stream)) != NTT_OK ||
+                           (rc = ntti::debug_range(pc, b, batch, stream)) != NTT_OK))
+    return rc;
   ntt_plan* p = const_cast<ntt_plan*>(pc);
   int path, logN1, exact;
   select_variant(p, batch * p->L, &path, &logN1, &exact);
@@ -578,6 +605,8 @@ int ntt_pointwise_mul(const ntt_plan* p, const void* a, const void* b, void* c, 
   int rc = check_common(p, batch);
   if (rc != NTT_OK) return rc;
   if (!a || !b || !c) return NTT_ERR_ARG;
+  if ((rc = ntti::debug_range(p, a, batch, stream)) != NTT_OK || (rc = ntti::debug_range(p, b, batch, stream)) != NTT_OK)
+    return rc;
   const hipError_t e = nttk::launch_pointwise(p->word, a, b, c, p->d_mod, p->L, p->logN, batch * p->L,
                                               (hipStream_t)stream);
   return e == hipSuccess ? NTT_OK : NTT_ERR_HIP;
@@ -589,6 +618,8 @@ static int run_polymul(const ntt_plan* pc, const void* a, const void* b, void* c
   int rc = check_common(pc, batch);
   if (rc != NTT_OK) return rc;
   if (!a || !b || !c) return NTT_ERR_ARG;
+  if ((rc = ntti::debug_range(pc, a, batch, stream)) != NTT_OK || (rc = ntti::debug_range(pc, b, batch, stream)) != NTT_OK)
+    return rc;
   ntt_plan* p = const_cast<ntt_plan*>(pc);
   int path, logN1, exact;
   select_variant(p, 2 * batch * p->L, &path, &logN1, &exact);

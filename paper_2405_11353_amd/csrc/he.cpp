@@ -55,6 +55,10 @@ int ntt_tensor_product(const ntt_plan* p, const void* a, const void* b, void* d,
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess) return fail(NTT_ERR_HIP);
   if (dev != p->device) return fail(NTT_ERR_ARG);
+  int rc;
+  if ((rc = ntti::debug_range(p, a, 2 * batch, stream)) != NTT_OK ||
+      (rc = ntti::debug_range(p, b, 2 * batch, stream)) != NTT_OK)
+    return fail(rc);
   const hipError_t e = nttk::launch_tensor(p->word, a, b, d, p->d_mod, p->L, p->logN, batch, (hipStream_t)stream);
   return e == hipSuccess ? NTT_OK : fail(NTT_ERR_HIP);
 }

@@ -86,6 +86,10 @@ hipError_t launch_u64(const Launch& c, bool forward);
 hipError_t launch_u64w(const Launch& c, bool forward);
 hipError_t launch_u64x(const Launch& c, bool forward);
 hipError_t launch_u32(const Launch& c, bool forward);
+// *flag (device) set to 1 if any of the items * 2^logN words is >= its limb's
+// modulus (the caller clears it first)
+hipError_t launch_check_range(int word, const void* x, const void* mods, uint32_t L, uint32_t logN,
+                              uint32_t items, uint32_t* flag, hipStream_t s);
 hipError_t launch_pointwise(int word, const void* a, const void* b, void* out, const void* mods,
                             uint32_t L, uint32_t logN, uint32_t items, hipStream_t s);
 

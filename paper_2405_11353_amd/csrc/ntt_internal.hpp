@@ -32,6 +32,10 @@ struct ntt_plan {
   // every modulus below 2^60 (64-bit words): the forward kernels keep values in
   // [0, 16q) and skip about half of their reductions (approximate quotient)
   bool wide = false;
+  // NTT_DEBUG_CHECK: every call first checks its inputs are canonical
+  // (d_flag: one device word for the result)
+  bool debug_check = false;
+  uint32_t* d_flag = nullptr;
   std::mutex mu;  // guards scratch and the paper-variant tables
   std::vector<ScratchSlot> scratch;
   // tables of the paper's algorithm variants (cyclic plans), built on first use
@@ -57,6 +61,11 @@ void tune_autoload();
 
 // validation shared by plans and batch jobs: 0 or an NTT_ERR_ code
 int check_modulus(uint64_t q, uint32_t N, int word);
+
+// With the plan's NTT_DEBUG_CHECK: NTT_ERR_RANGE if a word of the batch *
+// L * N words at d is not below its limb's modulus, after synchronizing the
+// stream; NTT_OK without the check
+int debug_range(const ntt_plan* p, const void* d, uint32_t batch, void* stream);
 
 // twiddle tables of one (word, q, N) on a device, created on first use and
 // kept for the life of the process

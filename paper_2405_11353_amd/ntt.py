@@ -17,6 +17,7 @@ NTT_OK = 0
 NTT_WORD32 = 0x1
 NTT_ORDER_BITREV = 0x2
 NTT_CYCLIC = 0x4
+NTT_DEBUG_CHECK = 0x8
 NTT_ROW_TWIST_FWD, NTT_ROW_TWIST_INV = 0x1, 0x2
 NTT_PATH_AUTO, NTT_PATH_TINY, NTT_PATH_LDS, NTT_PATH_FOURSTEP = 0, 1, 2, 3
 NTT_PATH_PAPER_DIT, NTT_PATH_PAPER_DIF, NTT_PATH_PAPER_PEASE, NTT_PATH_PAPER_PEASE_NC, NTT_PATH_PAPER_STOCKHAM = \
@@ -45,6 +46,7 @@ NTT_REQ_NTT, NTT_REQ_INTT, NTT_REQ_POLYMUL = 0, 1, 2
 NTT_SERVER_SIMULATE = 0x1
 NTT_ERR_TIMEOUT = -9
 NTT_ERR_SCRATCH = -10
+NTT_ERR_RANGE = -11
 NTT_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 

@@ -53,6 +53,7 @@ def test_plan_argument_validation(lib):
         ((1024, None, 1, 0, None), -1),
         ((1024, u64s([q]), 0, 0, None), -1),
         ((1024, u64s([q]), 1, 0x80, None), -1),       # unknown flag
+        ((1024, u64s([q]), 1, 0x10, None), -1),
         ((1024, u64s([q]), 1, 0, u64s([2])), -1),     # not a primitive 2N-th root
     ]
     for args, code in cases:
@@ -62,7 +63,7 @@ def test_plan_argument_validation(lib):
 
 def test_strerror_covers_codes(lib):
     lib.ntt_strerror.restype = ctypes.c_char_p
-    for c in range(0, -11, -1):
+    for c in range(0, -12, -1):
         assert lib.ntt_strerror(c) and lib.ntt_strerror(c) != b"unknown error"
 
 
