@@ -981,7 +981,8 @@ def bench_serving(ntt, si, torch, n_jobs=20000, warm=1000, rate=15000.0):
     # working memory does not fit beside the jobs in flight
     budgets = []
     hi = si.serving_trace(seed=si.BASE_SEED + 42, count=warm + n_jobs, rate_per_s=0.7 * sat_jobs_s)
-    for gib in (0.25, 1, 4, 16):
+    # (the job mix's 240 (q, N) table sets take 315 MiB of any budget)
+    for gib in (0.5, 1, 4, 16):
         server = ntt.Server(hbm_budget_bytes=int(gib * (1 << 30)), n_streams=4, max_batch_items=4096)
         replay_server(hi, prepare(hi))
         bs = server.stats()
@@ -990,7 +991,8 @@ def bench_serving(ntt, si, torch, n_jobs=20000, warm=1000, rate=15000.0):
                         "admission_stalls": bs["admission_stalls"],
                         "max_inflight_batches": bs["max_inflight_batches"],
                         "mean_jobs_per_batch": round(bs["completed"] / max(1, bs["batches"]), 2),
-                        "peak_bytes": bs["peak_bytes"]})
+                        "peak_bytes": bs["peak_bytes"], "table_bytes": bs["table_bytes"],
+                        "table_uploads": bs["table_uploads"], "table_evictions": bs["table_evictions"]})
         log(f"serving, {gib} GiB budget: p50 {budgets[-1]['p50_us']} us p99 {budgets[-1]['p99_us']} us, "
             f"{bs['admission_stalls']} admission stalls")
 
@@ -1039,6 +1041,7 @@ def bench_serving(ntt, si, torch, n_jobs=20000, warm=1000, rate=15000.0):
            "ntt_per_s": round(st["ntts"] / st["wall_s"], 1), "batches": st["batches"],
            "mean_jobs_per_batch": round(st["completed"] / max(1, st["batches"]), 2),
            "max_inflight_batches": st["max_inflight_batches"], "admission_stalls": st["admission_stalls"],
+           "table_bytes_resident": st["table_bytes"], "table_evictions": st["table_evictions"],
            "hbm_budget_GiB": 4, "load_curve": curve, "budget_sweep_at_70pct": budgets,
            "per_call_fifo": {"p50_us": round(float(fl[len(fl) // 2]), 1),
                              "p99_us": round(float(fl[int(0.99 * (len(fl) - 1))]), 1),

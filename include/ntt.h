@@ -301,7 +301,10 @@ void ntt_batch_destroy(ntt_batch* batch);
  * partial overlaps are not allowed. A scheduler thread admits queued jobs in
  * arrival order whenever one of n_streams device streams is free and the
  * job's working memory (an operand copy for POLYMUL, four-step scratch for
- * N >= 2^14) fits in the server's hbm_budget_bytes arena; jobs admitted
+ * N >= 2^14) and the twiddle tables of its (q, N) pairs that are not resident
+ * yet (32N + 64 bytes each) fit in the server's hbm_budget_bytes arena, after
+ * evicting resident tables no admitted job uses (least recently used first);
+ * a job that cannot fit alone is refused with NTT_ERR_BUDGET; jobs admitted
  * together run as one batch (descriptor table + one launch per (phase, N)),
  * up to max_batch_items (polynomial, limb) transforms per batch. Latency is
  * measured from submit to the scheduler observing completion. With
@@ -337,6 +340,9 @@ typedef struct {
   uint32_t max_inflight_batches, reserved;
   double p50_us, p99_us, mean_us, max_us;
   double wall_s, busy_s;           /* since creation or reset; busy = a batch in flight */
+  uint64_t table_bytes;            /* twiddle tables resident in the arena now      */
+  uint64_t table_uploads;          /* tables made resident (uploaded)               */
+  uint64_t table_evictions;        /* unreferenced tables evicted for space         */
 } ntt_server_stats;
 typedef struct ntt_server ntt_server;
 ntt_server* ntt_server_create(const ntt_server_config* cfg);

@@ -76,6 +76,15 @@ struct PoolEntry {
 };
 int pool_get(int word, uint64_t q, uint32_t logN, PoolEntry* out);
 size_t pool_bytes();
+// the host copy of those tables (forward [N] pairs, inverse [N] pairs, the
+// modulus constants), built and validated on first use and kept for the life
+// of the process; pool_table_bytes is its size
+struct HostTables {
+  const unsigned char* data;  // pinned when a device was present to pin it
+  size_t bytes;
+};
+int pool_host(int word, uint64_t q, uint32_t logN, HostTables* out);
+size_t pool_table_bytes(int word, uint32_t logN);
 
 // a prime q < 2^bits with q = 1 mod 2N (the largest one), for tuning runs
 uint64_t tuning_prime(uint32_t N, int word);

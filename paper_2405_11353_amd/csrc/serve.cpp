@@ -9,9 +9,16 @@
 // and records an event. Jobs that arrive while earlier batches run are
 // admitted as soon as a slot and arena space free up, so their work overlaps
 // on the device. Completion is detected by polling the slots' events; latency
-// is measured from submit to detected completion. Twiddle tables stay resident
-// in the process-wide pool. With NTT_SERVER_SIMULATE no device is touched and a
-// batch completes after a modelled time (scheduler tests without a GPU).
+// is measured from submit to detected completion.
+//
+// Twiddle tables live in the same arena and count against the same budget:
+// each (q, N) a job needs is made resident when the job is admitted (uploaded
+// from the process-wide host copy by the first batch that uses it) and stays
+// resident after its jobs finish; when an admission needs space, resident
+// tables that no queued or running job references are evicted, least
+// recently used first. With NTT_SERVER_SIMULATE no device is touched and a
+// batch completes after a modelled time (scheduler tests without a GPU); the
+// arena accounting, tables included, is the same.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -24,6 +31,7 @@
 #include <vector>
 
 #include "ntt_internal.hpp"
+#include "params.hpp"
 #include "polymul.hpp"
 
 namespace {
@@ -33,11 +41,29 @@ double now_s() {
   return duration<double>(steady_clock::now().time_since_epoch()).count();
 }
 
+// one resident (q, N) table set in the arena: forward and inverse twiddles
+// and the modulus constants (ntti::pool_table_bytes)
+struct Table {
+  uint64_t q = 0;
+  uint32_t logN = 0;
+  size_t off = 0, bytes = 0;
+  uint32_t refs = 0;           // queued-and-admitted or running jobs using it
+  uint64_t last_use = 0;
+  bool resident = false;       // holds arena space
+  bool uploaded = false;       // an upload has been enqueued since it became resident
+  hipStream_t up_stream = nullptr;
+  hipEvent_t ready = nullptr;  // recorded after the upload on up_stream
+  ntti::HostTables host{};
+};
+
 struct Job {
   uint64_t ticket = 0;
   uint32_t op = 0, N = 0, logN = 0, L = 0;
   bool fourstep = false;
-  std::vector<ntti::PoolEntry> tw;
+  std::vector<uint64_t> moduli;
+  std::vector<Table*> tw;       // per limb (set at admission)
+  std::vector<ntti::HostTables> host;  // per limb (real mode)
+  size_t table_need = 0;        // bytes of the job's distinct tables
   const uint64_t* a = nullptr;
   const uint64_t* b = nullptr;
   uint64_t* out = nullptr;
@@ -139,6 +165,11 @@ struct ntt_server {
   bool stop = false;
   uint64_t next_ticket = 1;
   Arena arena;
+  // resident twiddle tables, keyed by (q, logN); touched by the scheduler
+  // thread only (admission, upload, completion)
+  std::map<std::pair<uint64_t, uint32_t>, Table> tables;
+  uint64_t use_clock = 0;
+  size_t table_bytes = 0;
   // statistics since the last reset
   ntt_server_stats st{};
   std::vector<float> lat_us;
@@ -170,9 +201,11 @@ static int launch_batch(ntt_server* s, Slot& slot) {
     for (uint32_t l = 0; l < j->L; ++l) {
       ItemDesc d{};
       d.logN = j->logN;
-      d.tw_fwd = j->tw[l].tw_fwd;
-      d.tw_inv = j->tw[l].tw_inv;
-      d.mod = j->tw[l].mod;
+      const char* tb = (const char*)s->base + j->tw[l]->off;
+      const size_t half = n * nttp::tw_entry_bytes(64);
+      d.tw_fwd = tb;
+      d.tw_inv = tb + half;
+      d.mod = tb + 2 * half;
       uint64_t* out_l = j->out + l * n;
       if (j->op == NTT_REQ_POLYMUL && j->fourstep) {
         uint64_t* sa = ws + l * n;
@@ -252,9 +285,25 @@ static int launch_batch(ntt_server* s, Slot& slot) {
   }
   append(pm_inv, pm_inv_runs, false);
   if (all.size() > slot.cap) return NTT_ERR_ARG;
+  hipError_t e = hipSuccess;
+  // tables: the first batch that uses a newly resident table uploads it;
+  // later batches on other streams wait for that upload
+  for (Job* j : slot.jobs)
+    for (Table* t : j->tw) {
+      if (e != hipSuccess) break;
+      if (!t->uploaded) {
+        e = hipMemcpyAsync((char*)s->base + t->off, t->host.data, t->bytes, hipMemcpyHostToDevice, slot.stream);
+        if (e == hipSuccess && !t->ready) e = hipEventCreateWithFlags(&t->ready, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(t->ready, slot.stream);
+        t->uploaded = true;
+        t->up_stream = slot.stream;
+      } else if (t->up_stream != slot.stream) {
+        e = hipStreamWaitEvent(slot.stream, t->ready, 0);
+      }
+    }
   std::copy(all.begin(), all.end(), slot.h_desc);
-  hipError_t e = hipMemcpyAsync(slot.d_desc, slot.h_desc, all.size() * sizeof(ItemDesc), hipMemcpyHostToDevice,
-                                slot.stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(slot.d_desc, slot.h_desc, all.size() * sizeof(ItemDesc), hipMemcpyHostToDevice, slot.stream);
   if (e == hipSuccess) e = nttk::launch_ind_copy(slot.d_desc, (uint32_t)copy.size(), max_logn, slot.stream);
   auto col_launch = [&](const Run& r, bool f, int io) {
     nttk::BatchLaunch c;
@@ -311,6 +360,7 @@ static void finish_slot(ntt_server* s, Slot& slot, double t) {
       s->st.failed++;
     }
     s->arena.release(j->arena_off, j->ws_bytes);
+    for (Table* t : j->tw) t->refs--;
     delete j;
   }
   slot.jobs.clear();
@@ -321,6 +371,67 @@ static void finish_slot(ntt_server* s, Slot& slot, double t) {
     s->busy_acc += t - s->busy_since;
     s->busy_since = -1;
   }
+}
+
+// Reserves j's working memory, then makes its tables resident, evicting
+// resident tables that no admitted job references (least recently used
+// first) when the arena is full. The working memory goes first, as the
+// largest block; a table of this job already placed is never evicted for the
+// next one, so an admission ends. When nothing runs, every table is
+// unreferenced and can go, so a job that fits the budget alone (checked at
+// submit) is always admitted once the device drains. On failure the working
+// memory is released; tables made resident on the way stay, evictable.
+static bool admit(ntt_server* s, Job* j) {
+  std::vector<Table*> mine(j->L);
+  for (uint32_t l = 0; l < j->L; ++l) {
+    Table& t = s->tables[{j->moduli[l], j->logN}];
+    if (!t.bytes) {
+      t.q = j->moduli[l];
+      t.logN = j->logN;
+      t.bytes = ntti::pool_table_bytes(64, j->logN);
+      if (!s->simulate) t.host = j->host[l];
+    }
+    mine[l] = &t;
+  }
+  std::vector<Table*> placed;  // this job's tables resident so far
+  auto alloc = [&](size_t bytes, size_t* off) {
+    while (!s->arena.alloc(bytes, off)) {
+      Table* lru = nullptr;
+      for (auto& kv : s->tables) {
+        Table& t = kv.second;
+        if (t.resident && t.refs == 0 && std::find(placed.begin(), placed.end(), &t) == placed.end() &&
+            (!lru || t.last_use < lru->last_use))
+          lru = &t;
+      }
+      if (!lru) return false;
+      s->arena.release(lru->off, lru->bytes);
+      lru->resident = false;
+      lru->uploaded = false;
+      s->table_bytes -= lru->bytes;
+      s->st.table_evictions++;
+    }
+    return true;
+  };
+  if (!alloc(j->ws_bytes, &j->arena_off)) return false;
+  for (Table* t : mine) {
+    if (!t->resident) {
+      if (!alloc(t->bytes, &t->off)) {
+        s->arena.release(j->arena_off, j->ws_bytes);
+        return false;
+      }
+      t->resident = true;
+      t->uploaded = s->simulate;
+      s->table_bytes += t->bytes;
+      s->st.table_uploads++;
+    }
+    placed.push_back(t);
+  }
+  for (Table* t : mine) {
+    t->refs++;
+    t->last_use = ++s->use_clock;
+  }
+  j->tw = std::move(mine);
+  return true;
 }
 
 static void scheduler(ntt_server* s) {
@@ -353,7 +464,7 @@ static void scheduler(ntt_server* s) {
       while (!s->pending.empty()) {
         Job* j = s->pending.front();
         if (!slot.jobs.empty() && items + j->items() > s->cfg.max_batch_items) break;
-        if (!s->arena.alloc(j->ws_bytes, &j->arena_off)) {
+        if (!admit(s, j)) {
           if (slot.jobs.empty()) s->st.admission_stalls++;
           break;
         }
@@ -369,6 +480,7 @@ static void scheduler(ntt_server* s) {
       s->st.items += items;
       s->st.max_inflight_batches = std::max<uint32_t>(s->st.max_inflight_batches, s->inflight);
       s->st.peak_bytes = std::max<uint64_t>(s->st.peak_bytes, s->arena.used());
+      s->st.table_bytes = s->table_bytes;
       lk.unlock();
       const int rc = launch_batch(s, slot);
       lk.lock();
@@ -401,6 +513,8 @@ static void server_free(ntt_server* s) {
       if (sl.d_desc) (void)hipFree(sl.d_desc);
       if (sl.h_desc) (void)hipHostFree(sl.h_desc);
     }
+    for (auto& kv : s->tables)
+      if (kv.second.ready) (void)hipEventDestroy(kv.second.ready);
     if (s->base) (void)hipFree(s->base);
   }
   delete s;
@@ -472,19 +586,22 @@ int ntt_server_submit(ntt_server* s, const ntt_request* r, uint64_t* ticket) {
   // (four-step sizes); transforms: the four-step intermediate
   j->ws_bytes = j->op == NTT_REQ_POLYMUL ? poly * (j->fourstep ? 2 : 1) : (j->fourstep ? poly : 0);
   int rc = NTT_OK;
-  // simulate mode validates here; otherwise the pool validates a modulus the
-  // first time it sees (q, N) and later submits only look the tables up
-  if (s->simulate)
+  j->moduli.assign(r->moduli, r->moduli + r->L);
+  // simulate mode validates here; otherwise the host copy of the tables is
+  // built (and the modulus validated) the first time the process sees (q, N)
+  if (s->simulate) {
     for (uint32_t l = 0; l < j->L && rc == NTT_OK; ++l) rc = ntti::check_modulus(r->moduli[l], r->N, 64);
-  if (rc == NTT_OK && j->ws_bytes > s->cfg.hbm_budget_bytes) rc = NTT_ERR_BUDGET;
-  if (rc == NTT_OK && !s->simulate) {
-    int cur = 0;
-    (void)hipGetDevice(&cur);
-    (void)hipSetDevice(s->device);
-    j->tw.resize(j->L);
-    for (uint32_t l = 0; l < j->L && rc == NTT_OK; ++l) rc = ntti::pool_get(64, r->moduli[l], j->logN, &j->tw[l]);
-    (void)hipSetDevice(cur);
+  } else {
+    j->host.resize(j->L);
+    for (uint32_t l = 0; l < j->L && rc == NTT_OK; ++l) rc = ntti::pool_host(64, r->moduli[l], j->logN, &j->host[l]);
   }
+  // the job alone must fit: its working memory and its distinct tables
+  std::vector<uint64_t> distinct(j->moduli);
+  std::sort(distinct.begin(), distinct.end());
+  distinct.erase(std::unique(distinct.begin(), distinct.end()), distinct.end());
+  j->table_need = distinct.size() * ntti::pool_table_bytes(64, j->logN);
+  const size_t pad = 256 * (distinct.size() + 1);  // the arena's 256-byte granules
+  if (rc == NTT_OK && j->ws_bytes + j->table_need + pad > s->cfg.hbm_budget_bytes) rc = NTT_ERR_BUDGET;
   std::lock_guard<std::mutex> g(s->mu);
   if (rc == NTT_OK && s->stop) rc = NTT_ERR_STATE;
   if (rc != NTT_OK) {
@@ -523,6 +640,7 @@ int ntt_server_get_stats(ntt_server* s, ntt_server_stats* out) {
   out->wall_s = t - s->t0;
   out->busy_s = s->busy_acc + (s->busy_since >= 0 ? t - s->busy_since : 0);
   out->queued = s->pending.size();
+  out->table_bytes = s->table_bytes;
   if (!s->lat_us.empty()) {
     std::vector<float> v = s->lat_us;
     std::sort(v.begin(), v.end());

@@ -69,7 +69,8 @@ class ServerStats(ctypes.Structure):
                 ("peak_bytes", ctypes.c_uint64), ("max_inflight_batches", ctypes.c_uint32),
                 ("reserved", ctypes.c_uint32), ("p50_us", ctypes.c_double), ("p99_us", ctypes.c_double),
                 ("mean_us", ctypes.c_double), ("max_us", ctypes.c_double), ("wall_s", ctypes.c_double),
-                ("busy_s", ctypes.c_double)]
+                ("busy_s", ctypes.c_double), ("table_bytes", ctypes.c_uint64), ("table_uploads", ctypes.c_uint64),
+                ("table_evictions", ctypes.c_uint64)]
 
 
 class TuneChoice(ctypes.Structure):

@@ -50,8 +50,9 @@ def test_overlapping_batches_use_several_streams(ntt):
 def test_budget_admission_and_rejection(ntt):
     N, L = 1 << 16, 4
     poly = L * N * 8
-    # a POLYMUL at N = 2^16 holds the column-pass outputs of both operands
-    budget = 2 * poly
+    # a POLYMUL at N = 2^16 holds the column-pass outputs of both operands,
+    # beside the twiddle tables of its L (q, N) pairs
+    budget = 2 * poly + L * (32 * N + 64) + (64 << 10)
     with sim(ntt, hbm_budget_bytes=budget, n_streams=4, simulate_ns_per_item=50000.0) as s:
         with pytest.raises(ntt.NttError) as e:
             s.submit(ntt.NTT_REQ_POLYMUL, N, P18[:L + 1], FAKE, FAKE, b=FAKE)   # > budget
@@ -152,3 +153,66 @@ def test_undersized_buffers_are_refused_before_submit(ntt):
         s.simulate = True
         t = s.submit(ntt.NTT_REQ_POLYMUL, N, mods, ok, ok, b=ok)
         assert s.wait(t) == 0
+
+
+def test_twiddle_tables_count_against_the_budget(ntt):
+    """A job's tables (32N + 64 bytes per (q, N)) and its working memory must
+    fit the budget together; tables stay resident across jobs and are
+    evicted, least recently used first, when space is needed."""
+    N = 1 << 17
+    table = 32 * N + 64
+    ws = 8 * N                              # four-step intermediate of one limb
+    with sim(ntt, hbm_budget_bytes=ws + table - 1, n_streams=1) as s:
+        with pytest.raises(ntt.NttError):   # fits the arena only without its table
+            s.submit(ntt.NTT_REQ_NTT, N, P18[:1], FAKE, FAKE)
+    budget = ws + 2 * table + (64 << 10)    # room for two tables beside one job
+    with sim(ntt, hbm_budget_bytes=budget, n_streams=1, simulate_ns_per_item=1000.0) as s:
+        for q in P18[:2]:
+            assert s.wait(s.submit(ntt.NTT_REQ_NTT, N, [q], FAKE, FAKE)) == 0
+        st = s.stats()
+        assert st["table_uploads"] == 2 and st["table_evictions"] == 0 and st["table_bytes"] == 2 * table
+        assert s.wait(s.submit(ntt.NTT_REQ_NTT, N, [P18[0]], FAKE, FAKE)) == 0   # resident: no upload
+        assert s.stats()["table_uploads"] == 2
+        assert s.wait(s.submit(ntt.NTT_REQ_NTT, N, [P18[2]], FAKE, FAKE)) == 0   # evicts the LRU (P18[1])
+        st = s.stats()
+        assert st["table_uploads"] == 3 and st["table_evictions"] == 1 and st["table_bytes"] == 2 * table
+        assert st["peak_bytes"] <= budget
+        assert s.wait(s.submit(ntt.NTT_REQ_NTT, N, [P18[0]], FAKE, FAKE)) == 0   # still resident
+        assert s.stats()["table_uploads"] == 3
+
+
+def test_many_tables_under_a_small_budget(ntt):
+    """A stream of jobs over more (q, N) pairs than the budget can hold at once
+    all complete: admission waits for tables to become unreferenced and
+    evicts them."""
+    mods = si.ntt_primes(60, 18, 8)
+    with sim(ntt, hbm_budget_bytes=24 << 20, n_streams=3, max_batch_items=16, simulate_ns_per_item=200.0) as s:
+        s_ = si.Stream(5)
+        tickets = []
+        for i in range(200):
+            lg = s_.uniform_int(12, 17)
+            L = s_.uniform_int(1, 3)
+            op = s_.uniform_int(0, 2)
+            first = s_.uniform_int(0, 8 - L)
+            tickets.append(s.submit(op, 1 << lg, mods[first:first + L], FAKE, FAKE, b=FAKE))
+        for t in tickets:
+            assert s.wait(t) == 0
+        st = s.stats()
+        assert st["completed"] == 200 and st["failed"] == 0
+        assert st["table_evictions"] > 0 and st["peak_bytes"] <= 24 << 20 and st["table_bytes"] <= 24 << 20
+
+
+def test_admission_is_not_blocked_by_its_own_resident_tables(ntt):
+    """A job whose tables are already resident but split the free space so
+    that its working memory does not fit between them is still admitted
+    once the device drains: working memory is placed first and any
+    unreferenced table may move."""
+    mods = si.serving_primes()            # 40 primes, 1 mod 2^18
+    N = 1 << 14
+    with sim(ntt, hbm_budget_bytes=32 << 20, n_streams=1, simulate_ns_per_item=100.0) as s:
+        # an NTT job: 5 MiB of working memory, then its 40 tables (20 MiB) behind it
+        assert s.wait(s.submit(ntt.NTT_REQ_NTT, N, mods, FAKE, FAKE)) == 0
+        # a product over the same primes: 10 MiB of working memory and the same tables
+        assert s.wait(s.submit(ntt.NTT_REQ_POLYMUL, N, mods, FAKE, FAKE, b=FAKE), 5_000_000) == 0
+        st = s.stats()
+        assert st["completed"] == 2 and st["peak_bytes"] <= 32 << 20
