@@ -211,9 +211,10 @@ size_t ntt_workspace_bytes(const ntt_plan* plan, uint32_t batch);
  * makes no allocation of any kind. That is enough for natural-order spectra
  * of batch * L * N <= 2^23 words, e.g. 4 polynomials of 24 limbs at N = 2^16.
  * Errors: NTT_ERR_SCRATCH when ntt_workspace_bytes(plan, batch) exceeds the
- * array; NTT_ERR_UNSUPPORTED when the call would first have to build tables
- * (a twisted forward row pass for a split whose tables the plan has not built,
- * or the paper's per-stage variants); the argument errors of ntt_forward.
+ * array; NTT_ERR_UNSUPPORTED for the paper's per-stage variants (their tables
+ * are built on first use); the argument errors of ntt_forward. Where the
+ * twisted forward row pass would need tables the plan has not built, the
+ * merged one (the same transform) runs instead.
  * Calls that need no scratch (LDS-resident sizes, bit-reversed spectra) use
  * none. Every call on one GPU shares that GPU's array and the array keeps the
  * last call's contents (each call writes the whole intermediate before it
@@ -235,21 +236,26 @@ const char* ntt_strerror(int code);
 /* ---- autotuner ------------------------------------------------------------
  * Times every kernel variant the library has for (N, word size, `items`
  * transforms per call) on the current GPU: the LDS-resident kernel, each
- * four-step split N1 x N2, and for 64-bit words both quotient flavours;
- * `reps` timed calls each after two warm-up calls, with HIP events on a
- * private stream. The fastest goes into a process-wide table that plans in
- * automatic mode (the default) and batches consult per call, keyed by
- * (word, log2 N, log2 items). The table is saved and loaded as JSON tagged
- * with the GPU architecture. At its first plan, batch or server creation a
- * process loads the file named by NTT_TUNE_CACHE, or, if that variable is
- * unset, tune_<arch>.json next to libntt.so (an empty NTT_TUNE_CACHE loads
- * nothing).
+ * four-step split N1 x N2, and for 64-bit words both quotient flavours and 8
+ * or 16 values per thread (so 2 or 1 threads per 16 values of a column) in
+ * the column passes; `reps` timed calls each after two warm-up calls, with
+ * HIP events on a private stream. For a four-step winner it then times each
+ * direction's row pass merged and twisted and keeps the faster. The winner
+ * goes into a process-wide table that plans in automatic mode (the default)
+ * and batches consult per call, keyed by (word, log2 N, log2 items); a plan
+ * uses the tuned row forms until ntt_plan_set_row_twist fixes its own. The
+ * table is saved and loaded as JSON tagged with the GPU architecture. At its
+ * first plan, batch or server creation a process loads the file named by
+ * NTT_TUNE_CACHE, or, if that variable is unset, tune_<arch>.json next to
+ * libntt.so (an empty NTT_TUNE_CACHE loads nothing).
  * Synchronous; allocates items*N words of device memory while it runs. */
 typedef struct {
   int32_t path;       /* NTT_PATH_* */
   int32_t log_n1;     /* four-step column length log2 */
   int32_t exact;      /* 64-bit quotient flavour */
   float us_per_call;  /* measured time of the winner */
+  int32_t row_twist;  /* four-step: NTT_ROW_TWIST_* mask of the faster row forms; -1 otherwise */
+  int32_t lv_col;     /* four-step, 64-bit: log2 values per thread of the column passes (4), 0 = default (3) */
 } ntt_tune_choice;
 int ntt_autotune(uint32_t N, uint32_t flags, uint32_t items, uint32_t reps, ntt_tune_choice* best);
 int ntt_tune_save(const char* path);

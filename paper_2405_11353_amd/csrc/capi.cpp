@@ -48,18 +48,28 @@ static void default_variant(ntt_plan* p) {
   p->auto_variant = true;
 }
 
-// the variant a call on `items` transforms runs with
-static void select_variant(const ntt_plan* p, uint32_t items, int* path, int* logN1, int* exact) {
+// the variant a call on `items` transforms runs with; twist (the row-form
+// mask) and lv_col (column passes' values per thread, 0 = default) as tuned
+// with it, or the plan's own
+static void select_variant(const ntt_plan* p, uint32_t items, int* path, int* logN1, int* exact,
+                           int* twist = nullptr, int* lv_col = nullptr) {
   *path = p->path;
   *logN1 = p->logN1;
   *exact = p->exact;
-  if (!p->auto_variant) return;
-  int tp, tn1, tex;
-  if (ntti::tune_lookup(p->word, (int)p->logN, items, &tp, &tn1, &tex) && variant_ok(p, tp, tn1, tex)) {
-    *path = tp;
-    *logN1 = tn1;
-    *exact = tex;
+  int tw = -1, lv = 0;
+  if (p->auto_variant) {
+    int tp, tn1, tex;
+    if (ntti::tune_lookup(p->word, (int)p->logN, items, &tp, &tn1, &tex, &tw, &lv) && variant_ok(p, tp, tn1, tex)) {
+      *path = tp;
+      *logN1 = tn1;
+      *exact = tex;
+    } else {
+      tw = -1;
+      lv = 0;
+    }
   }
+  if (twist) *twist = (p->auto_twist && tw >= 0) ? tw : p->row_twist;
+  if (lv_col) *lv_col = p->tune_lv_col ? p->tune_lv_col : (p->word == 64 ? lv : 0);
 }
 
 namespace ntti {
@@ -310,6 +320,7 @@ int ntt_plan_set_quotient(ntt_plan* p, int exact) {
 int ntt_plan_set_row_twist(ntt_plan* p, int mask) {
   if (!p || (mask & ~(NTT_ROW_TWIST_FWD | NTT_ROW_TWIST_INV))) return NTT_ERR_ARG;
   p->row_twist = mask;
+  p->auto_twist = false;
   return prepare_row_tables(p);
 }
 
@@ -474,8 +485,8 @@ static int run_ntt(const ntt_plan* pc, void* data, uint32_t batch, void* stream,
   // the input of a whole transform, or of its first kernel, is canonical
   if ((stage_mask & 1) && (rc = ntti::debug_range(pc, data, batch, stream)) != NTT_OK) return rc;
   ntt_plan* p = const_cast<ntt_plan*>(pc);
-  int path, logN1, exact;
-  select_variant(p, batch * p->L, &path, &logN1, &exact);
+  int path, logN1, exact, twist_mask, lv_col;
+  select_variant(p, batch * p->L, &path, &logN1, &exact, &twist_mask, &lv_col);
   if (is_paper_path(path)) {
     if (stage_mask != 3 || fixed_scratch) return NTT_ERR_UNSUPPORTED;
     return run_paper(p, data, batch, stream, fwd, path);
@@ -496,16 +507,19 @@ static int run_ntt(const ntt_plan* pc, void* data, uint32_t batch, void* stream,
   c.items = batch * p->L;
   c.stream = (hipStream_t)stream;
   c.stage_mask = stage_mask;
+  c.lv_col = lv_col;
   if (stage_mask != 3 && c.path != nttk::PATH_TWO) return NTT_ERR_UNSUPPORTED;
-  const bool twisted = c.path == nttk::PATH_TWO && (p->row_twist & (fwd ? NTT_ROW_TWIST_FWD : NTT_ROW_TWIST_INV));
+  bool twisted = c.path == nttk::PATH_TWO && (twist_mask & (fwd ? NTT_ROW_TWIST_FWD : NTT_ROW_TWIST_INV));
   if (fixed_scratch) {
     if (c.path == nttk::PATH_TWO && c.natural) {
       if (ntt_workspace_bytes(p, batch) > fixed_bytes) return NTT_ERR_SCRATCH;
       c.scratch = fixed_scratch;
     }
     if (twisted) {
+      // without the split's twisted tables, the merged row pass (the same
+      // transform) instead of building them
       std::lock_guard<std::mutex> g(p->mu);
-      if (!p->d_rowtw[fwd ? 0 : 1][logN1]) return NTT_ERR_UNSUPPORTED;
+      if (!p->d_rowtw[fwd ? 0 : 1][logN1]) twisted = false;
     }
   } else if (c.path == nttk::PATH_TWO && c.natural) {
     rc = get_scratch(p, stream, ntt_workspace_bytes(p, batch), &c.scratch);
@@ -564,8 +578,8 @@ static int run_mul_inverse(const ntt_plan* pc, const void* a, const void* b, voi
                            (rc = ntti::debug_range(pc, b, batch, stream)) != NTT_OK))
     return rc;
   ntt_plan* p = const_cast<ntt_plan*>(pc);
-  int path, logN1, exact;
-  select_variant(p, batch * p->L, &path, &logN1, &exact);
+  int path, logN1, exact, twist_mask, lv_col;
+  select_variant(p, batch * p->L, &path, &logN1, &exact, &twist_mask, &lv_col);
   if (path != NTT_PATH_FOURSTEP) {
     if (stage_mask != 3) return NTT_ERR_UNSUPPORTED;
     // no fused kernel for this shape: the two steps, still on the device
@@ -589,11 +603,12 @@ static int run_mul_inverse(const ntt_plan* pc, const void* a, const void* b, voi
   L.items = batch * p->L;
   L.stream = (hipStream_t)stream;
   L.stage_mask = stage_mask;
+  L.lv_col = lv_col;
   if (L.natural) {
     rc = get_scratch(p, stream, ntt_workspace_bytes(p, batch), &L.scratch);
     if (rc != NTT_OK) return rc;
   }
-  if ((p->row_twist & NTT_ROW_TWIST_INV) && (rc = row_tables(p, logN1, false, &L)) != NTT_OK) return rc;
+  if ((twist_mask & NTT_ROW_TWIST_INV) && (rc = row_tables(p, logN1, false, &L)) != NTT_OK) return rc;
   const hipError_t e = nttk::launch_ntt(L, false);
   if (e == hipErrorNotSupported) return NTT_ERR_UNSUPPORTED;
   return e == hipSuccess ? NTT_OK : NTT_ERR_HIP;

@@ -39,6 +39,7 @@ struct Launch {
   uint32_t L = 0, items = 0, batch = 0;  // items = batch * L
   hipStream_t stream = nullptr;
   int stage_mask = 3;       // PATH_TWO: bit 0 runs the first kernel, bit 1 the second
+  int lv_col = 0;           // PATH_TWO, 64-bit: values per thread (log2, 3 or 4) of the column passes; 0 = default
   const void* mul_a = nullptr;  // PATH_TWO inverse: if set, transform mul_a * mul_b into data
   const void* mul_b = nullptr;
   // PATH_TWO: if set, the row pass is the twisted one (k_row_tw) with these

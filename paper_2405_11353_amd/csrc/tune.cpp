@@ -26,6 +26,8 @@ struct TKey {
 struct TVal {
   int path, logN1, exact;
   float us;
+  int twist = -1;  // row-form mask tuned with the variant, -1: none
+  int lv_col = 0;  // column passes' values per thread (log2), 0: default
 };
 std::mutex g_mu;
 std::map<TKey, TVal> g_table;
@@ -65,7 +67,7 @@ void default_variant(int word, int logN, int* path, int* logN1) {
   }
 }
 
-bool tune_lookup(int word, int logN, uint32_t items, int* path, int* logN1, int* exact) {
+bool tune_lookup(int word, int logN, uint32_t items, int* path, int* logN1, int* exact, int* twist, int* lv_col) {
   std::lock_guard<std::mutex> g(g_mu);
   if (g_table.empty()) return false;
   const int b = items_bucket(items);
@@ -84,12 +86,15 @@ bool tune_lookup(int word, int logN, uint32_t items, int* path, int* logN1, int*
   *path = best->path;
   *logN1 = best->logN1;
   *exact = best->exact;
+  if (twist) *twist = best->twist;
+  if (lv_col) *lv_col = best->lv_col;
   return true;
 }
 
-void tune_store(int word, int logN, uint32_t items, int path, int logN1, int exact, float us) {
+void tune_store(int word, int logN, uint32_t items, int path, int logN1, int exact, float us, int twist,
+                int lv_col) {
   std::lock_guard<std::mutex> g(g_mu);
-  g_table[TKey{word, logN, items_bucket(items)}] = TVal{path, logN1, exact, us};
+  g_table[TKey{word, logN, items_bucket(items)}] = TVal{path, logN1, exact, us, twist, lv_col};
 }
 
 uint64_t tuning_prime(uint32_t N, int word) {
@@ -150,48 +155,79 @@ int ntt_autotune(uint32_t N, uint32_t flags, uint32_t items, uint32_t reps, ntt_
   if (rc == NTT_OK && (hipMemset(buf, 0, bytes) != hipSuccess || hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess ||
                        hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
     rc = NTT_ERR_HIP;
+  // candidates: the LDS kernel, and every four-step split with either
+  // quotient flavour (64-bit) and 8 or 16 values per thread in the column
+  // passes (64-bit), all timed as forward transforms with merged row passes;
+  // then, for a four-step winner, the row form of each direction
   struct Cand {
-    int path, logN1, exact;
+    int path, logN1, exact, lv;
   };
   std::vector<Cand> cands;
   const int lg = ilog2(N);
-  if (lg <= 3) cands.push_back({NTT_PATH_TINY, 0, 0});
-  if (lg >= 4 && lg <= nttk::lds_max_logn(word)) cands.push_back({NTT_PATH_LDS, 0, 0});
+  if (lg <= 3) cands.push_back({NTT_PATH_TINY, 0, 0, 0});
+  if (lg >= 4 && lg <= nttk::lds_max_logn(word)) cands.push_back({NTT_PATH_LDS, 0, 0, 0});
   for (int a = nttk::kTwoPassMinLog; a <= nttk::kTwoPassMaxLog; ++a)
     if (nttk::shape_supported(word, 0, nttk::PATH_TWO, lg, a)) {
-      cands.push_back({NTT_PATH_FOURSTEP, a, 0});
-      if (word == 64) cands.push_back({NTT_PATH_FOURSTEP, a, 1});
+      cands.push_back({NTT_PATH_FOURSTEP, a, 0, 0});
+      if (word == 64) {
+        cands.push_back({NTT_PATH_FOURSTEP, a, 1, 0});
+        cands.push_back({NTT_PATH_FOURSTEP, a, 0, 4});
+      }
     }
-  Cand best{-1, 0, 0};
+  // one timed configuration: `reps` calls after two warm-up calls
+  auto time_us = [&](bool fwd, float* us) {
+    bool ok = true;
+    for (uint32_t r = 0; r < 2 && ok; ++r) ok = (fwd ? ntt_forward : ntt_inverse)(plan, buf, items, s) == NTT_OK;
+    if (!ok || hipStreamSynchronize(s) != hipSuccess) return false;
+    (void)hipEventRecord(e0, s);
+    for (uint32_t r = 0; r < reps && ok; ++r) ok = (fwd ? ntt_forward : ntt_inverse)(plan, buf, items, s) == NTT_OK;
+    (void)hipEventRecord(e1, s);
+    if (!ok || hipEventSynchronize(e1) != hipSuccess) return false;
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    *us = ms * 1000.f / reps;
+    return true;
+  };
+  Cand best{-1, 0, 0, 0};
   float best_us = 1e30f;
   for (const Cand& c : cands) {
     if (rc != NTT_OK) break;
     if (ntt_plan_set_variant(plan, c.path, c.logN1) != NTT_OK) continue;
     if (c.exact && ntt_plan_set_quotient(plan, 1) != NTT_OK) continue;
-    // items as batch of a one-limb plan
-    bool ok = true;
-    for (uint32_t r = 0; r < 2 && ok; ++r) ok = ntt_forward(plan, buf, items, s) == NTT_OK;
-    if (!ok || hipStreamSynchronize(s) != hipSuccess) continue;
-    (void)hipEventRecord(e0, s);
-    for (uint32_t r = 0; r < reps && ok; ++r) ok = ntt_forward(plan, buf, items, s) == NTT_OK;
-    (void)hipEventRecord(e1, s);
-    if (!ok || hipEventSynchronize(e1) != hipSuccess) continue;
-    float ms = 0;
-    (void)hipEventElapsedTime(&ms, e0, e1);
-    const float us = ms * 1000.f / reps;
-    if (us < best_us) {
+    if (ntt_plan_set_row_twist(plan, 0) != NTT_OK) continue;
+    plan->tune_lv_col = c.lv;
+    float us;
+    if (time_us(true, &us) && us < best_us) {
       best_us = us;
       best = c;
     }
   }
+  plan->tune_lv_col = 0;
+  int twist = -1;
+  if (rc == NTT_OK && best.path == NTT_PATH_FOURSTEP && ntt_plan_set_variant(plan, best.path, best.logN1) == NTT_OK &&
+      (!best.exact || ntt_plan_set_quotient(plan, 1) == NTT_OK)) {
+    // each direction's row form, at the winning split: merged or twisted
+    plan->tune_lv_col = best.lv;
+    twist = 0;
+    for (int bit : {NTT_ROW_TWIST_FWD, NTT_ROW_TWIST_INV}) {
+      float merged, twisted;
+      if (ntt_plan_set_row_twist(plan, 0) == NTT_OK && time_us(bit == NTT_ROW_TWIST_FWD, &merged) &&
+          ntt_plan_set_row_twist(plan, bit) == NTT_OK && time_us(bit == NTT_ROW_TWIST_FWD, &twisted) &&
+          twisted < merged)
+        twist |= bit;
+    }
+    plan->tune_lv_col = 0;
+  }
   if (rc == NTT_OK && best.path < 0) rc = NTT_ERR_UNSUPPORTED;
   if (rc == NTT_OK) {
-    tune_store(word, lg, items, best.path, best.logN1, best.exact, best_us);
+    tune_store(word, lg, items, best.path, best.logN1, best.exact, best_us, twist, best.lv);
     if (best_out) {
       best_out->path = best.path;
       best_out->log_n1 = best.logN1;
       best_out->exact = best.exact;
       best_out->us_per_call = best_us;
+      best_out->row_twist = twist;
+      best_out->lv_col = best.lv;
     }
   }
   if (e0) (void)hipEventDestroy(e0);
@@ -210,9 +246,11 @@ int ntt_tune_save(const char* path) {
   fprintf(f, "{\"arch\": \"%s\", \"entries\": [", arch_name().c_str());
   bool first = true;
   for (auto& kv : g_table) {
-    fprintf(f, "%s\n  {\"word\": %d, \"log_n\": %d, \"items_log2\": %d, \"path\": %d, \"log_n1\": %d, \"exact\": %d, \"us\": %.3f}",
+    fprintf(f,
+            "%s\n  {\"word\": %d, \"log_n\": %d, \"items_log2\": %d, \"path\": %d, \"log_n1\": %d, "
+            "\"exact\": %d, \"us\": %.3f, \"row_twist\": %d, \"lv_col\": %d}",
             first ? "" : ",", kv.first.word, kv.first.logN, kv.first.items_log2, kv.second.path, kv.second.logN1,
-            kv.second.exact, kv.second.us);
+            kv.second.exact, kv.second.us, kv.second.twist, kv.second.lv_col);
     first = false;
   }
   fprintf(f, "\n]}\n");
@@ -262,8 +300,16 @@ int ntt_tune_load(const char* path) {
         field(b, e, "path", &pa) && field(b, e, "log_n1", &n1) && field(b, e, "exact", &ex) &&
         field(b, e, "us", &us) && (w == 32 || w == 64) && in(lg, 1, 17) && in(il, 0, 40) &&
         in(pa, NTT_PATH_TINY, NTT_PATH_FOURSTEP) && in(n1, 0, 9) && in(ex, 0, 1) && in(us, 0, 1e9)) {
+      // optional fields of later tables: the row form and the column passes'
+      // values per thread (an entry without them keeps the plan's own)
+      double tw = -1, lvc = 0;
+      const bool has_tw = field(b, e, "row_twist", &tw), has_lv = field(b, e, "lv_col", &lvc);
+      if ((has_tw && !in(tw, -1, 3)) || (has_lv && !(lvc == 0 || lvc == 3 || lvc == 4))) {
+        pos = e + 1;
+        continue;
+      }
       std::lock_guard<std::mutex> g(g_mu);
-      g_table[TKey{(int)w, (int)lg, (int)il}] = TVal{(int)pa, (int)n1, (int)ex, (float)us};
+      g_table[TKey{(int)w, (int)lg, (int)il}] = TVal{(int)pa, (int)n1, (int)ex, (float)us, (int)tw, (int)lvc};
       ++count;
     }
     pos = e + 1;

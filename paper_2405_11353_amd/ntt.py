@@ -75,7 +75,7 @@ class ServerStats(ctypes.Structure):
 
 class TuneChoice(ctypes.Structure):
     _fields_ = [("path", ctypes.c_int32), ("log_n1", ctypes.c_int32), ("exact", ctypes.c_int32),
-                ("us_per_call", ctypes.c_float)]
+                ("us_per_call", ctypes.c_float), ("row_twist", ctypes.c_int32), ("lv_col", ctypes.c_int32)]
 
 
 class NttError(RuntimeError):
@@ -308,7 +308,8 @@ def ntt_plan_get_variant_for(plan: int, batch: int) -> tuple[int, int, int]:
 def ntt_autotune(N: int, items: int, reps: int = 20, flags: int = 0) -> dict:
     out = TuneChoice()
     _check(lib().ntt_autotune(N, flags, items, reps, ctypes.byref(out)), "ntt_autotune")
-    return {"path": out.path, "log_n1": out.log_n1, "exact": out.exact, "us_per_call": out.us_per_call}
+    return {"path": out.path, "log_n1": out.log_n1, "exact": out.exact, "us_per_call": out.us_per_call,
+            "row_twist": out.row_twist, "lv_col": out.lv_col}
 
 
 def ntt_tune_save(path: str) -> None:

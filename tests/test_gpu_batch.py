@@ -1,5 +1,7 @@
 """Batched executor (one hipGraph launch for uneven jobs) and the autotuner,
 against the CPU oracle."""
+import os
+
 import numpy as np
 import pytest
 
@@ -117,6 +119,8 @@ def test_autotune_and_plan_selection(ntt, tmp_path):
     ntt.ntt_tune_clear()
     best = ntt.ntt_autotune(1 << 16, items=96, reps=5)
     assert best["path"] in (ntt.NTT_PATH_LDS, ntt.NTT_PATH_FOURSTEP) and best["us_per_call"] > 0
+    assert best["lv_col"] in (0, 4)
+    assert best["row_twist"] in ((0, 1, 2, 3) if best["path"] == ntt.NTT_PATH_FOURSTEP else (-1,))
     plan = ntt.Plan(1 << 16, P18[:2])
     assert plan.variant[0] == ntt.NTT_PATH_FOURSTEP  # stored default, unchanged
     assert ntt.ntt_plan_get_variant_for(plan.handle, 48)[:2] == (best["path"], best["log_n1"])
@@ -135,3 +139,42 @@ def test_autotune_and_plan_selection(ntt, tmp_path):
     ntt.ntt_tune_load(f)
     assert ntt.ntt_plan_get_variant_for(plan.handle, 48)[:2] == (best["path"], best["log_n1"])
     ntt.ntt_tune_clear()
+
+
+@pytest.mark.parametrize("logn,logn1,twist,lv", [(16, 8, 3, 4), (16, 7, 1, 4), (17, 9, 2, 4), (14, 6, 3, 0),
+                                                 (16, 8, 0, 4)])
+def test_tuned_row_form_and_values_per_thread(ntt, tmp_path, logn, logn1, twist, lv):
+    """A tuning table that picks the row form of each direction and 16 values
+    per thread in the column passes: a plan in automatic mode runs with them
+    and still matches the oracle (forward, fused product + inverse)."""
+    import ctypes
+    log(f"case tuned row form N=2^{logn} logn1={logn1} twist={twist} lv={lv}")
+    f = tmp_path / "arch.json"
+    ntt.ntt_tune_clear()
+    ntt.ntt_tune_save(str(f))
+    arch = f.read_text().split('"arch": "')[1].split('"')[0]
+    f.write_text('{"arch": "%s", "entries": [{"word": 64, "log_n": %d, "items_log2": 2, "path": 3, "log_n1": %d, '
+                 '"exact": 0, "us": 1, "row_twist": %d, "lv_col": %d}]}' % (arch, logn, logn1, twist, lv))
+    ntt.ntt_tune_load(str(f))
+    N, moduli = 1 << logn, P18[:2]
+    try:
+        plan = ntt.Plan(N, moduli)
+        assert ntt.ntt_plan_get_variant_for(plan.handle, 2)[:2] == (ntt.NTT_PATH_FOURSTEP, logn1)
+        a = si.poly_batch(logn + twist, 2, moduli, N)
+        b = si.poly_batch(logn + twist + 1, 2, moduli, N)
+        da, db = to_dev(a), to_dev(b)
+        plan.forward(da)
+        plan.forward(db)
+        A = oracle.ntt_forward_batch(a, moduli)[0]
+        np.testing.assert_array_equal(from_dev(da).reshape(a.shape), A)
+        dc = to_dev(np.zeros_like(a))
+        plan.pointwise_inverse(da, db, dc)
+        want = oracle.ntt_inverse_batch(oracle.pointwise_batch(A, oracle.ntt_forward_batch(b, moduli)[0],
+                                                               moduli)[0], moduli)[0]
+        np.testing.assert_array_equal(from_dev(dc).reshape(a.shape), want)
+        plan.inverse(db)
+        np.testing.assert_array_equal(from_dev(db).reshape(b.shape), b)
+        plan.close()
+    finally:
+        ntt.ntt_tune_clear()
+        ntt.ntt_tune_load(os.path.join(os.path.dirname(ntt.library_path()), "tune_gfx950.json"))
