@@ -792,6 +792,100 @@ k_row_tw(const typename A::word* in, typename A::word* out, const typename A::tw
   }
 }
 
+// ============================================================ split-twist row pass
+// The forward rows once more, with the twist of k_row_tw split in two. After
+// the first phase's stages, the twisted row's state is the merged row's state
+// times beta_r^(c mod 2^(LOGN2 - P)) at row position c (P: the stages done;
+// checked numerically for several splits). So the first phase runs merged,
+// with the row's own subtree of twiddles staged in LDS as in k_row; then each
+// value is multiplied by beta_r^t, t = c mod 2^(LOGN2 - P), which with the
+// first phase a full LV stages (LOGN2 % LV == 0) is the same for all of a
+// thread's values: one twist entry per thread, the first TPR entries of the
+// row's twist table; the later phases are the cyclic transform of k_row_tw,
+// its twiddles shared by every row and staged in LDS. No twiddle is read from
+// global memory between butterflies, and the twiddle bytes a row reads are 31
+// entries instead of the merged pass's N2 - 1 or the twisted pass's N2.
+template <class A, int LOGN2, bool NATURAL, int LV = 4>
+__global__ void __launch_bounds__(16 << (LOGN2 - LV))
+k_row_st(const typename A::word* in, typename A::word* out, const typename A::tw_t* __restrict__ tw_all,
+         const typename A::tw_t* __restrict__ twist_all, const typename A::tw_t* __restrict__ cyc_all,
+         const typename ModOf<A>::type* __restrict__ mods, uint32_t L, uint32_t logN, uint32_t batch) {
+  using W = typename A::word;
+  using TW = typename A::tw_t;
+  using S = Sched<LOGN2, LV>;
+  static_assert(S::R0 == 0, "the first phase must be a full LV stages");
+  constexpr int V = 1 << LV;
+  constexpr uint32_t N2 = 1u << LOGN2, TPR = N2 / V, RSTR = N2 + N2 / 16 + 1;
+  static_assert(TPR <= 64, "a row must fit in one wavefront");
+  __shared__ W lds[16 * RSTR];
+  __shared__ TW tw0[16][17];  // first-phase (merged) twiddles of the 16 rows
+  __shared__ TW cyc[N2];      // cyclic twiddles, entry k written by thread k
+  const uint32_t logN1 = logN - LOGN2, N1 = 1u << logN1;
+  const uint32_t tiles = N1 / 16;
+  const uint32_t bid = xcd_remap(blockIdx.x, gridDim.x);
+  const uint32_t b = bid % batch, rest = bid / batch;
+  const uint32_t tile = rest % tiles, l = rest / tiles;
+  if (l >= L) return;  // whole workgroup leaves together
+  const uint32_t item = b * L + l;
+  const uint32_t t = threadIdx.x % TPR, rl = threadIdx.x / TPR;
+  const uint32_t k1 = tile * 16 + rl;
+  const uint32_t r = NATURAL ? brv(k1, logN1) : k1;
+  A a;
+  a.load(mods[l]);
+  const TW* tw = tw_all + ((size_t)l << logN);
+  const bool has_entry = threadIdx.x < N2;
+  const TW cyc_entry = cyc_all[((size_t)l << LOGN2) + (has_entry ? threadIdx.x : 0u)];
+  const TW beta_t = twist_all[((size_t)l << logN) + (size_t)r * N2 + t];  // beta_r^t
+  FirstPhaseStage<LOGN2, LV, TW> first;
+  first.load(tw, logN1, [&](uint32_t row) { return NATURAL ? brv(tile * 16 + row, logN1) : tile * 16 + row; });
+  __builtin_amdgcn_sched_barrier(0);
+  const size_t pbase = (size_t)item << logN;
+  W* sh = lds + rl * RSTR;
+  W v[V];
+  const W* src = in + pbase + (size_t)r * N2;
+#pragma unroll
+  for (int i = 0; i < V; ++i) v[i] = ld_data<NT_LD_MID>(src + i * TPR + t);
+  first.put(tw0);
+  if (has_entry) cyc[cyc_pos<LOGN2, LV>(threadIdx.x)] = cyc_entry;
+  __syncthreads();
+  // the merged first phase (input anywhere in the column pass's output range)
+  ct_phase<A, LV, rp_of<A>(RP_LAZY), 0>(a, v, &tw0[rl][0], 0u, 0u);
+  // the rest of the twist: now below L
+#pragma unroll
+  for (int i = 0; i < V; ++i) v[i] = a.mul(v[i], beta_t);
+  static_for<1, S::NPH>([&](auto P_) {
+    constexpr int p = decltype(P_)::value;
+    if constexpr (p > 1) wave_lds_sync();
+#pragma unroll
+    for (int i = 0; i < V; ++i) sh[pad16(pos<LOGN2, LV>(p - 1, t, i))] = v[i];
+    wave_lds_sync();
+#pragma unroll
+    for (int i = 0; i < V; ++i) v[i] = sh[pad16(pos<LOGN2, LV>(p, t, i))];
+    ct_phase_cyc<A, S::rs(p), false, rp_of<A>(RP_FRESH), S::s0(p) - LV>(a, v, cyc, S::s0(p), grp<LOGN2, LV>(p, t));
+  });
+  if constexpr (NATURAL) {
+    if (S::NPH > 1) wave_lds_sync();
+#pragma unroll
+    for (int i = 0; i < V; ++i) sh[pad16(pos<LOGN2, LV>(S::NPH - 1, t, i))] = a.canon_fwd(v[i]);
+    __syncthreads();
+    const uint32_t rr = threadIdx.x % 16, cg = threadIdx.x / 16;
+    W* dst = out + pbase + tile * 16 + rr;
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      const uint32_t cc = cg + TPR * j;
+      st_data<NT_ST_OUT>(dst + (size_t)brv(cc, LOGN2) * N1, lds[rr * RSTR + pad16(cc)]);
+    }
+  } else {
+    if (S::NPH > 1) wave_lds_sync();
+#pragma unroll
+    for (int i = 0; i < V; ++i) sh[pad16(pos<LOGN2, LV>(S::NPH - 1, t, i))] = a.canon_fwd(v[i]);
+    wave_lds_sync();
+    W* dst = out + pbase + (size_t)r * N2;
+#pragma unroll
+    for (int i = 0; i < V; ++i) st_data<NT_ST_OUT>(dst + i * TPR + t, sh[pad16(i * TPR + t)]);
+  }
+}
+
 // ============================================================ tiny N
 // N in {2, 4, 8}: one thread per transform, the same stage structure.
 template <class A, int LOGN, bool FWD, bool NATURAL>
