@@ -36,14 +36,18 @@ def log(*a):
 # traffic is reported only while they are unchanged
 KERNEL_SOURCES = ["paper_2405_11353_amd/csrc/ntt_core.hpp", "paper_2405_11353_amd/csrc/modarith.hpp",
                   "paper_2405_11353_amd/csrc/dispatch.inc", "paper_2405_11353_amd/csrc/k_u64.hip",
-                  "paper_2405_11353_amd/csrc/k_pointwise.hip", "paper_2405_11353_amd/csrc/launch.hpp"]
+                  "paper_2405_11353_amd/csrc/k_u64w.hip", "paper_2405_11353_amd/csrc/k_pointwise.hip",
+                  "paper_2405_11353_amd/csrc/launch.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "polymul_n65536_l24_traffic.json")
 # rocprofv3 kernel names -> the names bench.py times them under
-KERNEL_KEYS = [("k_col<nttk::Arith64<false>, 8, 16, true", "fwd_col_pass"),
-               ("k_row<nttk::Arith64<false>, 8, true, true", "fwd_row_pass"),
-               ("k_row_tw<nttk::Arith64<false>, 8, false, true, true", "inv_row_pass_mul"),
-               ("k_row<nttk::Arith64<false>, 8, false, true, true", "inv_row_pass_mul"),
-               ("k_col<nttk::Arith64<false>, 8, 16, false", "inv_col_pass"),
+KERNEL_KEYS = [("k_col<nttk::Arith64<false, true>, 8, 16, true", "fwd_col_pass"),
+               ("k_col<nttk::Arith64<false, false>, 8, 16, true", "fwd_col_pass"),
+               ("k_row_st<nttk::Arith64<false, true>, 8, true", "fwd_row_pass"),
+               ("k_row<nttk::Arith64<false, true>, 8, true, true", "fwd_row_pass"),
+               ("k_row_st_inv<nttk::Arith64<false, false>, 8, true, true", "inv_row_pass_mul"),
+               ("k_row_tw<nttk::Arith64<false, false>, 8, false, true, true", "inv_row_pass_mul"),
+               ("k_row<nttk::Arith64<false, false>, 8, false, true, true", "inv_row_pass_mul"),
+               ("k_col<nttk::Arith64<false, false>, 8, 16, false", "inv_col_pass"),
                ("k_pointwise<nttk::ModInfo64", "pointwise")]
 
 
@@ -594,6 +598,7 @@ def bench_paper_sizes(ntt, si, torch, reps=100, batch=1024):
     (single_us_graph), which removes the per-launch overhead."""
     q = si.Q_SMALL
     stream = torch.cuda.current_stream()
+    TW = ntt.NTT_ROW_TWIST_FWD | ntt.NTT_ROW_TWIST_INV
     variants = [("fused", None), ("dit", ntt.NTT_PATH_PAPER_DIT), ("dif", ntt.NTT_PATH_PAPER_DIF),
                 ("pease", ntt.NTT_PATH_PAPER_PEASE), ("pease_nc", ntt.NTT_PATH_PAPER_PEASE_NC),
                 ("stockham", ntt.NTT_PATH_PAPER_STOCKHAM)]
@@ -769,14 +774,14 @@ def bench_ablations(ntt, si, torch, steps=100, warm=5):
         return e0.elapsed_time(e1) / n * 1e3
 
     variants = [
-        ("default: split 2^8 x 2^8, approximate quotient, fused product, twisted inverse rows", 8, False, True,
-         ntt.NTT_ROW_TWIST_INV),
+        ("default: split 2^8 x 2^8, approximate quotient, fused product, twisted (split-twist) rows both ways",
+         8, False, True, TW),
         ("merged-twiddle row passes", 8, False, True, 0),
-        ("twisted row passes in both directions", 8, False, True, ntt.NTT_ROW_TWIST_FWD | ntt.NTT_ROW_TWIST_INV),
-        ("split 2^7 x 2^9", 7, False, True, ntt.NTT_ROW_TWIST_INV),
-        ("split 2^9 x 2^7", 9, False, True, ntt.NTT_ROW_TWIST_INV),
-        ("exact quotient", 8, True, True, ntt.NTT_ROW_TWIST_INV),
-        ("separate pointwise pass", 8, False, False, ntt.NTT_ROW_TWIST_INV)]
+        ("merged forward rows, twisted inverse rows", 8, False, True, ntt.NTT_ROW_TWIST_INV),
+        ("split 2^7 x 2^9", 7, False, True, TW),
+        ("split 2^9 x 2^7", 9, False, True, TW),
+        ("exact quotient", 8, True, True, TW),
+        ("separate pointwise pass", 8, False, False, TW)]
     plans, steps_of = [], []
     for name, log_n1, exact, fused, twist in variants:
         plan = ntt.Plan(N, moduli)
@@ -1273,11 +1278,22 @@ def main():
     # writing the product (its column pass). Counter bytes (traffic) beside.
     if path == ntt.NTT_PATH_FOURSTEP:
         logn2 = int(math.log2(N)) - logn1
-        # column passes read table slots [0, N1) of each limb; the merged row
-        # pass reads all N slots; the twisted inverse row pass reads its N
-        # twist entries and N2 cyclic entries
-        tw_col, tw_row = L * 16 * (1 << logn1), L * 16 * N
-        tw_twist = L * 16 * (N + (1 << logn2))
+        twist_mask, _ = ntt.ntt_plan_get_row_form(plan.handle, 4)
+
+        def row_table_bytes(twisted, lv):
+            """Table bytes one launch reads per limb set: the merged row pass all N
+            slots; the split-twist pass each row's first-phase twiddles (2^P - 1),
+            its NF * TPR twist factors, and the N2 cyclic twiddles."""
+            if not twisted:
+                return L * 16 * N
+            n1, n2 = 1 << logn1, 1 << logn2
+            p_ = logn2 % lv or lv
+            return L * 16 * (n1 * ((1 << p_) - 1) + n1 * (1 << (lv - p_)) * (n2 >> lv) + n2)
+
+        # column passes read table slots [0, N1) of each limb
+        tw_col = L * 16 * (1 << logn1)
+        tw_row = row_table_bytes(twist_mask & ntt.NTT_ROW_TWIST_FWD, 4)
+        tw_twist = row_table_bytes(twist_mask & ntt.NTT_ROW_TWIST_INV, 3)
         kernels["fwd_col_pass"] = dict(fn=lambda b: plan.forward_stage(b, 0, batch=4), items=polys * L,
                                        stages=logn1, extra_muls=0, words_in=1, words_out=0, tw_bytes=tw_col)
         kernels["fwd_row_pass"] = dict(fn=lambda b: plan.forward_stage(b, 1, batch=4), items=polys * L,

@@ -174,20 +174,27 @@ int ntt_plan_set_quotient(ntt_plan* plan, int exact);
  * (the negacyclic NTT of Sec. 2, or the cyclic one of NTT_CYCLIC plans).
  * A twisted row pass: after the column stages, row r of the N1 x N2 matrix
  * is the residue of the input modulo x^N2 - b_r^N2, with b_r = psi^(2 brv(r)
- * + 1) (omega^brv(r) for cyclic plans). The forward row pass multiplies
- * element j by b_r^j and runs a cyclic NTT of length N2 whose twiddles are the
- * same for every row and are kept in LDS; the inverse runs the cyclic inverse
- * and then multiplies by b_r^-j. Its tables (N + N2 twiddle entries per limb,
- * direction and split) are built when the plan is created, or this call or
- * ntt_plan_set_variant selects them, for the plan's own split; a call that
- * the tuning table sends to another split builds that split's tables on its
- * first use (host work of about 10 ms per limb at N = 2^17, spread over up
- * to 16 threads). A merged row
- * pass runs the row stages of the merged-twiddle transform, whose twiddles
- * differ from row to row and are read from global memory.
+ * + 1) (omega^brv(r) for cyclic plans). The row's transform is then a cyclic
+ * NTT of length N2, whose twiddles are the same for every row and are kept
+ * in LDS, of the row multiplied elementwise by b_r^j (the twist). The library
+ * runs it split: the first register phase with the row's own twiddles (N2/16
+ * or fewer, staged in LDS), then the twist, which at that point takes one
+ * factor b_r^c per thread (a few when the first phase is short), then the
+ * cyclic phases; the inverse runs the same steps backwards. A row then reads
+ * about N2/8 table entries instead of N2. Its tables (N + N2 twiddle entries
+ * per limb, direction and split) are built when the plan is created, or this
+ * call or ntt_plan_set_variant selects them, for the plan's own split; a call
+ * that the tuning table sends to another split builds that split's tables on
+ * its first use (host work of about 10 ms per limb at N = 2^17, spread over
+ * up to 16 threads). A merged row pass runs the row stages of the
+ * merged-twiddle transform, whose twiddles differ from row to row and are read
+ * from global memory between butterflies.
  * mask: NTT_ROW_TWIST_FWD and/or NTT_ROW_TWIST_INV select the twisted form
- * for that direction, the rest are merged; the default is NTT_ROW_TWIST_INV
- * (the faster setting on MI355X). Applies to ntt_forward, ntt_inverse,
+ * for that direction, the rest are merged; the default is both
+ * (NTT_ROW_TWIST_DEFAULT): on MI355X the merged forward rows are a few
+ * percent faster alone, but the twisted ones move less memory and make a
+ * step of two ciphertexts' product on two streams about 6% faster.
+ * Applies to ntt_forward, ntt_inverse,
  * ntt_pointwise_mul_inverse and their _stage forms; a stage run in one
  * setting composes with the other stage run in another (the forward
  * intermediate is the same column pass output, and the inverse intermediates
@@ -196,6 +203,7 @@ int ntt_plan_set_quotient(ntt_plan* plan, int exact);
  * safe while other threads use the plan. */
 #define NTT_ROW_TWIST_FWD 1
 #define NTT_ROW_TWIST_INV 2
+#define NTT_ROW_TWIST_DEFAULT (NTT_ROW_TWIST_FWD | NTT_ROW_TWIST_INV)
 int ntt_plan_set_row_twist(ntt_plan* plan, int mask);
 
 /* Scratch a natural-order four-step call of `batch` polynomials needs (bytes;
@@ -223,6 +231,11 @@ size_t ntt_workspace_bytes(const ntt_plan* plan, uint32_t batch);
  * the caller. */
 #define NTT_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
 int ntt_forward_noalloc(const ntt_plan* plan, void* d_data, uint32_t batch, void* stream);
+
+/* The row forms (NTT_ROW_TWIST_* mask) and the column passes' values per
+ * thread (log2; 3 or 4 for 64-bit four-step calls, else 0) that a call with
+ * `batch` polynomials would run with (after tuning). */
+int ntt_plan_get_row_form(const ntt_plan* plan, uint32_t batch, int* row_twist, int* log_values);
 
 /* The variant a call with `batch` polynomials would run (after tuning). */
 int ntt_plan_get_variant_for(const ntt_plan* plan, uint32_t batch, int* path, int* log_n1, int* exact);

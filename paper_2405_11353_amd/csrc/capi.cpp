@@ -294,6 +294,15 @@ int ntt_plan_get_variant_for(const ntt_plan* p, uint32_t batch, int* path, int* 
   return NTT_OK;
 }
 
+int ntt_plan_get_row_form(const ntt_plan* p, uint32_t batch, int* row_twist, int* log_values) {
+  if (!p || batch == 0) return NTT_ERR_ARG;
+  int pa, n1, ex, tw, lv;
+  select_variant(p, batch * p->L, &pa, &n1, &ex, &tw, &lv);
+  if (row_twist) *row_twist = tw;
+  if (log_values) *log_values = pa == NTT_PATH_FOURSTEP && p->word == 64 ? (lv ? lv : 3) : 0;
+  return NTT_OK;
+}
+
 int ntt_plan_set_variant(ntt_plan* p, int path, int log_n1) {
   if (!p) return NTT_ERR_ARG;
   if (path == NTT_PATH_AUTO) {

@@ -792,19 +792,30 @@ k_row_tw(const typename A::word* in, typename A::word* out, const typename A::tw
   }
 }
 
-// ============================================================ split-twist row pass
-// The forward rows once more, with the twist of k_row_tw split in two. After
-// the first phase's stages, the twisted row's state is the merged row's state
-// times beta_r^(c mod 2^(LOGN2 - P)) at row position c (P: the stages done;
-// checked numerically for several splits). So the first phase runs merged,
-// with the row's own subtree of twiddles staged in LDS as in k_row; then each
-// value is multiplied by beta_r^t, t = c mod 2^(LOGN2 - P), which with the
-// first phase a full LV stages (LOGN2 % LV == 0) is the same for all of a
-// thread's values: one twist entry per thread, the first TPR entries of the
-// row's twist table; the later phases are the cyclic transform of k_row_tw,
-// its twiddles shared by every row and staged in LDS. No twiddle is read from
-// global memory between butterflies, and the twiddle bytes a row reads are 31
-// entries instead of the merged pass's N2 - 1 or the twisted pass's N2.
+// ============================================================ split-twist row passes
+// The rows of k_row_tw with the twist split in two. After the first P row
+// stages (P: those of the first register phase), the twisted row's state is
+// the merged row's state times beta_r^(c mod 2^(LOGN2 - P)) at row position c
+// (checked numerically for several splits). So the forward pass runs its
+// first phase merged, with the row's own subtree of twiddles staged in LDS as
+// in k_row; multiplies each value by beta_r^(c mod 2^(LOGN2 - P)); and runs
+// the later phases as the cyclic transform of k_row_tw, whose twiddles every
+// row shares and which sit in LDS. In the first phase's layout value i of
+// thread t is row position (i << lg) + t with lg = LOGN2 - LV, so its factor
+// is entry (f << lg) + t of the row's twist table, f = i mod NF, NF =
+// 2^(LV - P): one or a few entries per thread instead of one per value. The
+// inverse runs the same steps backwards: the cyclic inverse phases, the
+// factors beta_r^-(...), and the first phase merged. No twiddle is read from
+// global memory between butterflies, and a row reads 2^P - 1 + NF * TPR
+// table entries instead of N2.
+template <int LOGN2, int LV>
+struct SplitTwist {
+  using S = Sched<LOGN2, LV>;
+  static constexpr int P = S::rs(0);           // stages of the merged first phase
+  static constexpr int NF = 1 << (LV - P);     // distinct twist factors per thread
+  static constexpr uint32_t LG = LOGN2 - LV;   // log2 of the first phase's stride
+};
+
 template <class A, int LOGN2, bool NATURAL, int LV = 4>
 __global__ void __launch_bounds__(16 << (LOGN2 - LV))
 k_row_st(const typename A::word* in, typename A::word* out, const typename A::tw_t* __restrict__ tw_all,
@@ -813,7 +824,7 @@ k_row_st(const typename A::word* in, typename A::word* out, const typename A::tw
   using W = typename A::word;
   using TW = typename A::tw_t;
   using S = Sched<LOGN2, LV>;
-  static_assert(S::R0 == 0, "the first phase must be a full LV stages");
+  using ST = SplitTwist<LOGN2, LV>;
   constexpr int V = 1 << LV;
   constexpr uint32_t N2 = 1u << LOGN2, TPR = N2 / V, RSTR = N2 + N2 / 16 + 1;
   static_assert(TPR <= 64, "a row must fit in one wavefront");
@@ -835,7 +846,10 @@ k_row_st(const typename A::word* in, typename A::word* out, const typename A::tw
   const TW* tw = tw_all + ((size_t)l << logN);
   const bool has_entry = threadIdx.x < N2;
   const TW cyc_entry = cyc_all[((size_t)l << LOGN2) + (has_entry ? threadIdx.x : 0u)];
-  const TW beta_t = twist_all[((size_t)l << logN) + (size_t)r * N2 + t];  // beta_r^t
+  const TW* trow = twist_all + ((size_t)l << logN) + (size_t)r * N2 + t;
+  TW bt[ST::NF];  // beta_r^((f << lg) + t)
+#pragma unroll
+  for (int f = 0; f < ST::NF; ++f) bt[f] = trow[f << ST::LG];
   FirstPhaseStage<LOGN2, LV, TW> first;
   first.load(tw, logN1, [&](uint32_t row) { return NATURAL ? brv(tile * 16 + row, logN1) : tile * 16 + row; });
   __builtin_amdgcn_sched_barrier(0);
@@ -849,10 +863,10 @@ k_row_st(const typename A::word* in, typename A::word* out, const typename A::tw
   if (has_entry) cyc[cyc_pos<LOGN2, LV>(threadIdx.x)] = cyc_entry;
   __syncthreads();
   // the merged first phase (input anywhere in the column pass's output range)
-  ct_phase<A, LV, rp_of<A>(RP_LAZY), 0>(a, v, &tw0[rl][0], 0u, 0u);
+  ct_phase<A, ST::P, rp_of<A>(RP_LAZY), 0>(a, v, &tw0[rl][0], 0u, 0u);
   // the rest of the twist: now below L
 #pragma unroll
-  for (int i = 0; i < V; ++i) v[i] = a.mul(v[i], beta_t);
+  for (int i = 0; i < V; ++i) v[i] = a.mul(v[i], bt[i & (ST::NF - 1)]);
   static_for<1, S::NPH>([&](auto P_) {
     constexpr int p = decltype(P_)::value;
     if constexpr (p > 1) wave_lds_sync();
@@ -861,7 +875,8 @@ k_row_st(const typename A::word* in, typename A::word* out, const typename A::tw
     wave_lds_sync();
 #pragma unroll
     for (int i = 0; i < V; ++i) v[i] = sh[pad16(pos<LOGN2, LV>(p, t, i))];
-    ct_phase_cyc<A, S::rs(p), false, rp_of<A>(RP_FRESH), S::s0(p) - LV>(a, v, cyc, S::s0(p), grp<LOGN2, LV>(p, t));
+    ct_phase_cyc<A, S::rs(p), false, rp_of<A>(RP_FRESH), S::s0(p) - ST::P>(a, v, cyc, S::s0(p),
+                                                                           grp<LOGN2, LV>(p, t));
   });
   if constexpr (NATURAL) {
     if (S::NPH > 1) wave_lds_sync();
@@ -884,6 +899,118 @@ k_row_st(const typename A::word* in, typename A::word* out, const typename A::tw
 #pragma unroll
     for (int i = 0; i < V; ++i) st_data<NT_ST_OUT>(dst + i * TPR + t, sh[pad16(i * TPR + t)]);
   }
+}
+
+// Inverse: the spectrum rows (or with MULIN the product of two) through the
+// cyclic inverse phases, the factors beta_r^-(...), and the merged inverse
+// first phase; rows written in place, in the lazy range the column pass takes.
+template <class A, int LOGN2, bool NATURAL, bool MULIN, int LV = 3>
+__global__ void __launch_bounds__(16 << (LOGN2 - LV))
+k_row_st_inv(const typename A::word* in, typename A::word* out, const typename A::tw_t* __restrict__ tw_all,
+             const typename A::tw_t* __restrict__ twist_all, const typename A::tw_t* __restrict__ cyc_all,
+             const typename ModOf<A>::type* __restrict__ mods, uint32_t L, uint32_t logN, uint32_t batch,
+             const typename A::word* in2 = nullptr) {
+  using W = typename A::word;
+  using TW = typename A::tw_t;
+  using S = Sched<LOGN2, LV>;
+  using ST = SplitTwist<LOGN2, LV>;
+  constexpr int V = 1 << LV;
+  constexpr uint32_t N2 = 1u << LOGN2, TPR = N2 / V, RSTR = N2 + N2 / 16 + 1;
+  static_assert(TPR <= 64, "a row must fit in one wavefront");
+  static_assert(S::NPH > 1, "a cyclic phase before the merged one");
+  __shared__ W lds[16 * RSTR];
+  __shared__ TW tw0[16][17];
+  __shared__ TW cyc[N2];
+  const uint32_t logN1 = logN - LOGN2, N1 = 1u << logN1;
+  const uint32_t tiles = N1 / 16;
+  const uint32_t bid = xcd_remap(blockIdx.x, gridDim.x);
+  const uint32_t b = bid % batch, rest = bid / batch;
+  const uint32_t tile = rest % tiles, l = rest / tiles;
+  if (l >= L) return;  // whole workgroup leaves together
+  const uint32_t item = b * L + l;
+  const uint32_t t = threadIdx.x % TPR, rl = threadIdx.x / TPR;
+  const uint32_t k1 = tile * 16 + rl;
+  const uint32_t r = NATURAL ? brv(k1, logN1) : k1;
+  A a;
+  const auto* mi = mods + l;
+  a.load(*mi);
+  const TW* tw = tw_all + ((size_t)l << logN);
+  const bool has_entry = threadIdx.x < N2;
+  const TW cyc_entry = cyc_all[((size_t)l << LOGN2) + (has_entry ? threadIdx.x : 0u)];
+  FirstPhaseStage<LOGN2, LV, TW> first;
+  first.load(tw, logN1, [&](uint32_t row) { return NATURAL ? brv(tile * 16 + row, logN1) : tile * 16 + row; });
+  __builtin_amdgcn_sched_barrier(0);
+  const size_t pbase = (size_t)item << logN;
+  W* sh = lds + rl * RSTR;
+  W v[V];
+  if constexpr (NATURAL) {
+    const uint32_t rr = threadIdx.x % 16, cg = threadIdx.x / 16;
+    const size_t off = pbase + tile * 16 + rr;
+    const W* src = in + off;
+    W xa[V], xb[MULIN ? V : 1];
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      const size_t e = (size_t)brv(cg + TPR * j, LOGN2) * N1;
+      xa[j] = ld_data<NT_LD_IN>(src + e);
+      if constexpr (MULIN) xb[j] = ld_data<NT_LD_IN>(in2 + off + e);
+    }
+    first.put(tw0);
+    if (has_entry) cyc[cyc_pos<LOGN2, LV>(threadIdx.x)] = cyc_entry;
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      W val = xa[j];
+      if constexpr (MULIN) val = mulmod_general(val, xb[j], *mi);
+      lds[rr * RSTR + pad16(cg + TPR * j)] = val;
+    }
+  } else {
+    const size_t off = pbase + (size_t)r * N2;
+    const W* src = in + off;
+    W xa[V], xb[MULIN ? V : 1];
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      xa[i] = ld_data<NT_LD_IN>(src + i * TPR + t);
+      if constexpr (MULIN) xb[i] = ld_data<NT_LD_IN>(in2 + off + i * TPR + t);
+    }
+    first.put(tw0);
+    if (has_entry) cyc[cyc_pos<LOGN2, LV>(threadIdx.x)] = cyc_entry;
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      W val = xa[i];
+      if constexpr (MULIN) val = mulmod_general(val, xb[i], *mi);
+      sh[pad16(i * TPR + t)] = val;
+    }
+  }
+  __syncthreads();
+  // twist factors beta_r^-((f << lg) + t), read while the cyclic phases run
+  const TW* trow = twist_all + ((size_t)l << logN) + (size_t)r * N2 + t;
+  TW bt[ST::NF];
+#pragma unroll
+  for (int f = 0; f < ST::NF; ++f) bt[f] = trow[f << ST::LG];
+#pragma unroll
+  for (int i = 0; i < V; ++i) v[i] = sh[pad16(pos<LOGN2, LV>(S::NPH - 1, t, i))];
+  static_for_down<S::NPH - 1, 1>([&](auto P_) {
+    constexpr int p = decltype(P_)::value;
+    if constexpr (p < S::NPH - 1) {
+      wave_lds_sync();
+#pragma unroll
+      for (int i = 0; i < V; ++i) sh[pad16(pos<LOGN2, LV>(p + 1, t, i))] = v[i];
+      wave_lds_sync();
+#pragma unroll
+      for (int i = 0; i < V; ++i) v[i] = sh[pad16(pos<LOGN2, LV>(p, t, i))];
+    }
+    gs_phase_cyc<A, S::rs(p), false>(a, v, cyc, S::s0(p), grp<LOGN2, LV>(p, t));
+  });
+  wave_lds_sync();
+#pragma unroll
+  for (int i = 0; i < V; ++i) sh[pad16(pos<LOGN2, LV>(1, t, i))] = v[i];
+  wave_lds_sync();
+#pragma unroll
+  for (int i = 0; i < V; ++i) v[i] = a.mul(sh[pad16(pos<LOGN2, LV>(0, t, i))], bt[i & (ST::NF - 1)]);
+  gs_phase<A, ST::P, false>(a, v, &tw0[rl][0], 0u, 0u);
+  // first-phase layout: value i of thread t is row element i * TPR + t
+  W* dst = out + pbase + (size_t)r * N2;
+#pragma unroll
+  for (int i = 0; i < V; ++i) st_data<NT_ST_MID>(dst + i * TPR + t, v[i]);
 }
 
 // ============================================================ tiny N

@@ -45,7 +45,7 @@ struct ntt_plan {
   // default split is built at creation for the directions its mask selects,
   // other splits on first use.
   void* d_rowtw[2][10] = {};
-  int row_twist = NTT_ROW_TWIST_INV;  // directions whose four-step row pass is twisted
+  int row_twist = NTT_ROW_TWIST_DEFAULT;  // directions whose four-step row pass is twisted
   bool auto_twist = true;             // until set: the tuning table's row form, if it has one
   int tune_lv_col = 0;                // the autotuner's own override of the column passes' values per thread
 };

@@ -206,16 +206,22 @@ int ntt_autotune(uint32_t N, uint32_t flags, uint32_t items, uint32_t reps, ntt_
   int twist = -1;
   if (rc == NTT_OK && best.path == NTT_PATH_FOURSTEP && ntt_plan_set_variant(plan, best.path, best.logN1) == NTT_OK &&
       (!best.exact || ntt_plan_set_quotient(plan, 1) == NTT_OK)) {
-    // each direction's row form, at the winning split: merged or twisted
+    // each direction's row form, at the winning split: merged or twisted.
+    // The default form stays unless the other is more than 5% faster: the
+    // twisted rows move less memory, which pays when kernels overlap (calls
+    // on several streams) and which a call timed alone does not see.
     plan->tune_lv_col = best.lv;
-    twist = 0;
+    int mask = NTT_ROW_TWIST_DEFAULT;
     for (int bit : {NTT_ROW_TWIST_FWD, NTT_ROW_TWIST_INV}) {
       float merged, twisted;
       if (ntt_plan_set_row_twist(plan, 0) == NTT_OK && time_us(bit == NTT_ROW_TWIST_FWD, &merged) &&
-          ntt_plan_set_row_twist(plan, bit) == NTT_OK && time_us(bit == NTT_ROW_TWIST_FWD, &twisted) &&
-          twisted < merged)
-        twist |= bit;
+          ntt_plan_set_row_twist(plan, bit) == NTT_OK && time_us(bit == NTT_ROW_TWIST_FWD, &twisted)) {
+        const bool dflt_twisted = (NTT_ROW_TWIST_DEFAULT & bit) != 0;
+        const float dflt = dflt_twisted ? twisted : merged, other = dflt_twisted ? merged : twisted;
+        if (other < 0.95f * dflt) mask ^= bit;
+      }
     }
+    twist = mask == NTT_ROW_TWIST_DEFAULT ? -1 : mask;
     plan->tune_lv_col = 0;
   }
   if (rc == NTT_OK && best.path < 0) rc = NTT_ERR_UNSUPPORTED;

@@ -19,6 +19,7 @@ NTT_ORDER_BITREV = 0x2
 NTT_CYCLIC = 0x4
 NTT_DEBUG_CHECK = 0x8
 NTT_ROW_TWIST_FWD, NTT_ROW_TWIST_INV = 0x1, 0x2
+NTT_ROW_TWIST_DEFAULT = NTT_ROW_TWIST_FWD | NTT_ROW_TWIST_INV
 NTT_PATH_AUTO, NTT_PATH_TINY, NTT_PATH_LDS, NTT_PATH_FOURSTEP = 0, 1, 2, 3
 NTT_PATH_PAPER_DIT, NTT_PATH_PAPER_DIF, NTT_PATH_PAPER_PEASE, NTT_PATH_PAPER_PEASE_NC, NTT_PATH_PAPER_STOCKHAM = \
     4, 5, 6, 7, 8
@@ -125,6 +126,7 @@ def lib() -> ctypes.CDLL:
             "ntt_last_error": (i32, []),
             "ntt_set_last_error": (None, [i32]),
             "ntt_plan_get_variant_for": (i32, [vp, u32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+            "ntt_plan_get_row_form": (i32, [vp, u32, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
             "ntt_autotune": (i32, [u32, u32, u32, u32, ctypes.POINTER(TuneChoice)]),
             "ntt_tune_save": (i32, [ctypes.c_char_p]),
             "ntt_tune_load": (i32, [ctypes.c_char_p]),
@@ -303,6 +305,13 @@ def ntt_plan_get_variant_for(plan: int, batch: int) -> tuple[int, int, int]:
     _check(lib().ntt_plan_get_variant_for(plan, batch, ctypes.byref(p), ctypes.byref(n1), ctypes.byref(ex)),
            "ntt_plan_get_variant_for")
     return p.value, n1.value, ex.value
+
+
+def ntt_plan_get_row_form(plan: int, batch: int) -> tuple[int, int]:
+    """(row-twist mask, log2 values per thread of the column passes) a call runs with."""
+    tw, lv = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().ntt_plan_get_row_form(plan, batch, ctypes.byref(tw), ctypes.byref(lv)), "ntt_plan_get_row_form")
+    return tw.value, lv.value
 
 
 def ntt_autotune(N: int, items: int, reps: int = 20, flags: int = 0) -> dict:
