@@ -101,12 +101,21 @@ def summarize_counters(d: str, he: bool = False):
         md = os.path.join(ROOT, "profiles", "polymul_n65536_l24_counters.md")
         title = "# Counters and kernel trace: polymul_n65536_l24 (N=2^16, 24 limbs, 2 ciphertexts), MI355X"
         B = ("python3 bench.py --steps 2 --warmup 1 --kernel-reps 40 --streams 1 --no-cpu-baseline --no-per-call "
-             "--no-batched --no-serving --no-paper-sizes --no-he --no-ablations --no-polymul --no-batch-sweep")
+             "--no-batched --no-serving --no-paper-sizes --no-he --no-ablations --no-polymul --no-batch-sweep "
+             "--no-latency")
     copy_f = [v["FETCH_SIZE"] for k, v in pmc("pmc_copy_fetch").items() if "k_copy" in k][0]
     copy_w = [v["WRITE_SIZE"] for k, v in pmc("pmc_copy_write").items() if "k_copy" in k][0]
     gib_kib = float(1 << 20)
     f_scale, w_scale = gib_kib / copy_f, gib_kib / copy_w
     fetch, write, sq = pmc("pmc_fetch"), pmc("pmc_write"), pmc("pmc_sq")
+    # requests the L2 sends toward memory (the Infinity Cache sits behind this
+    # interface, so a request counted here may still hit there), per kernel and
+    # for the same 1 GiB copy
+    dram = pmc("pmc_dram") if os.path.isdir(os.path.join(d, "pmc_dram")) else {}
+    dcopy = pmc("pmc_copy_dram") if os.path.isdir(os.path.join(d, "pmc_copy_dram")) else {}
+    dc = [v for k, v in dcopy.items() if "k_copy" in k]
+    rd_per_gib = dc[0].get("TCC_EA0_RDREQ_DRAM_sum") if dc else None
+    wr_per_gib = dc[0].get("TCC_EA0_WRREQ_DRAM_sum") if dc else None
     stats = {}
     for f in glob.glob(os.path.join(d, "kt", "*kernel_stats.csv")):
         for r in csv.DictReader(open(f)):
@@ -122,12 +131,14 @@ def summarize_counters(d: str, he: bool = False):
              "    rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir>/pmc_copy_fetch -o run -- paper_2405_11353_amd/_build/ubench --copy-only",
              "    rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir>/pmc_copy_write -o run -- paper_2405_11353_amd/_build/ubench --copy-only",
              "    rocprofv3 --pmc SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT SQ_WAIT_INST_ANY SQ_WAVES --output-format csv -d <dir>/pmc_sq -o run -- $B",
+             "    rocprofv3 --pmc TCC_EA0_RDREQ_DRAM_sum TCC_EA0_WRREQ_DRAM_sum TCC_EA0_RDREQ_sum TCC_EA0_WRREQ_sum --output-format csv -d <dir>/pmc_dram -o run -- $B",
+             "    rocprofv3 --pmc TCC_EA0_RDREQ_DRAM_sum TCC_EA0_WRREQ_DRAM_sum TCC_EA0_RDREQ_sum TCC_EA0_WRREQ_sum --output-format csv -d <dir>/pmc_copy_dram -o run -- paper_2405_11353_amd/_build/ubench --copy-only",
              f"    python3 bench.py --summarize-{'he-' if he else ''}counters <dir>", "",
              f"Scale factors from the plain copy of 1 GiB (read 1 GiB, write 1 GiB per dispatch): "
              f"FETCH_SIZE reads {copy_f:.0f} KiB -> x{f_scale:.3f}; WRITE_SIZE reads {copy_w:.0f} KiB -> x{w_scale:.3f}.",
              f"Kernel source hash: {out['source_hash']}", "",
-             "| kernel | rocprof avg us | calls | scaled fetch MiB | scaled write MiB | VALU wave-instr | VALU busy | LDS bank conflicts |",
-             "|---|---|---|---|---|---|---|---|"]
+             "| kernel | rocprof avg us | calls | scaled fetch MiB | scaled write MiB | VALU wave-instr | VALU busy | LDS bank conflicts | DRAM-bound reads (copy-scaled MiB) | DRAM-bound writes (copy-scaled MiB) |",
+             "|---|---|---|---|---|---|---|---|---|---|"]
     for name in sorted(set(fetch) | set(stats)):
         key = bench_key(name, keys)
         if key is None:
@@ -139,11 +150,24 @@ def summarize_counters(d: str, he: bool = False):
         q = sq.get(name, {})
         valu = q.get("SQ_INSTS_VALU", float("nan"))
         busy = valu * 4 / (1024 * avg_us * 1e-6 * 2.4e9) if avg_us == avg_us else float("nan")
+        dk = dram.get(name, {})
+        dr = dk.get("TCC_EA0_RDREQ_DRAM_sum")
+        dw = dk.get("TCC_EA0_WRREQ_DRAM_sum")
+        dr_b = dr / rd_per_gib * (1 << 30) if dr is not None and rd_per_gib else None
+        dw_b = dw / wr_per_gib * (1 << 30) if dw is not None and wr_per_gib else None
         out["kernels"][key] = {"rocprof_avg_us": avg_us, "fetch_bytes": fb, "write_bytes": wb,
-                               "valu_wave_instr": valu, "lds_bank_conflicts": q.get("SQ_LDS_BANK_CONFLICT")}
+                               "valu_wave_instr": valu, "lds_bank_conflicts": q.get("SQ_LDS_BANK_CONFLICT"),
+                               "dram_read_bytes": dr_b, "dram_write_bytes": dw_b,
+                               "dram_read_requests": dr, "dram_write_requests": dw}
+        fmt = lambda v: f"{v / 2**20:.1f}" if v is not None else "-"  # noqa: E731
         lines.append(f"| {key} | {avg_us:.2f} | {calls} | {fb / 2**20:.1f} | {wb / 2**20:.1f} | {valu:.3g} | "
-                     f"{busy:.0%} | {q.get('SQ_LDS_BANK_CONFLICT', float('nan')):.3g} |")
+                     f"{busy:.0%} | {q.get('SQ_LDS_BANK_CONFLICT', float('nan')):.3g} | {fmt(dr_b)} | {fmt(dw_b)} |")
     lines += ["", "VALU busy = SQ_INSTS_VALU x 4 cycles / (1024 SIMDs x avg duration x 2.4 GHz)."]
+    if rd_per_gib:
+        lines += ["DRAM-bound columns: TCC_EA0_RDREQ_DRAM_sum / TCC_EA0_WRREQ_DRAM_sum, requests the L2 sends toward "
+                  f"memory, scaled by the same counters for the 1 GiB copy ({rd_per_gib:.4g} read and "
+                  f"{wr_per_gib:.4g} write requests per GiB). The Infinity Cache sits behind that interface, so these "
+                  "bound what reaches HBM from above; they cannot tell a hit there from HBM."]
     with open(traffic_file, "w") as fh:
         json.dump(out, fh, indent=1)
     with open(md, "w") as fh:
