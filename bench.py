@@ -1086,9 +1086,9 @@ def bench_serving(ntt, si, torch, n_jobs=20000, warm=1000, rate=15000.0):
     return res
 
 
-POLYMUL_TRACE_KEYS = [("k_col<nttk::Arith64<false>, 8, 16, true", "column passes of a and b (one launch)"),
-                      ("k_row_polymul<nttk::Arith64<false>, 8", "fused rows: both forward, product, first inverse"),
-                      ("k_col<nttk::Arith64<false>, 8, 16, false", "inverse column pass")]
+POLYMUL_TRACE_KEYS = [("k_col<nttk::Arith64<false, false>, 8, 16, true", "column passes of a and b (one launch)"),
+                      ("k_row_polymul<nttk::Arith64<false, false>, 8", "fused rows: both forward, product, first inverse"),
+                      ("k_col<nttk::Arith64<false, false>, 8, 16, false", "inverse column pass")]
 
 
 def summarize_polymul_trace(d: str):
