@@ -191,8 +191,8 @@ int ntt_plan_set_quotient(ntt_plan* plan, int exact);
  * from global memory between butterflies.
  * mask: NTT_ROW_TWIST_FWD and/or NTT_ROW_TWIST_INV select the twisted form
  * for that direction, the rest are merged; the default is both
- * (NTT_ROW_TWIST_DEFAULT): on MI355X the merged forward rows are a few
- * percent faster alone, but the twisted ones move less memory and make a
+ * (NTT_ROW_TWIST_DEFAULT): on MI355X the two forms are within a few percent
+ * of each other timed alone, but the twisted ones move less memory and make a
  * step of two ciphertexts' product on two streams about 6% faster.
  * Applies to ntt_forward, ntt_inverse,
  * ntt_pointwise_mul_inverse and their _stage forms; a stage run in one
