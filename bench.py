@@ -100,7 +100,7 @@ def summarize_counters(d: str, he: bool = False):
         keys, sources, traffic_file = KERNEL_KEYS, KERNEL_SOURCES, TRAFFIC_FILE
         md = os.path.join(ROOT, "profiles", "polymul_n65536_l24_counters.md")
         title = "# Counters and kernel trace: polymul_n65536_l24 (N=2^16, 24 limbs, 2 ciphertexts), MI355X"
-        B = ("python3 bench.py --steps 2 --warmup 1 --kernel-reps 40 --streams 1 --no-cpu-baseline --no-per-call "
+        B = ("python3 bench.py --steps 2 --warmup 1 --steady-ms 0 --kernel-reps 40 --streams 1 --no-cpu-baseline --no-per-call "
              "--no-batched --no-serving --no-paper-sizes --no-he --no-ablations --no-polymul --no-batch-sweep "
              "--no-latency")
     copy_f = [v["FETCH_SIZE"] for k, v in pmc("pmc_copy_fetch").items() if "k_copy" in k][0]
@@ -130,10 +130,11 @@ def summarize_counters(d: str, he: bool = False):
              "    rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir>/pmc_write -o run -- $B",
              "    rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir>/pmc_copy_fetch -o run -- paper_2405_11353_amd/_build/ubench --copy-only",
              "    rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir>/pmc_copy_write -o run -- paper_2405_11353_amd/_build/ubench --copy-only",
-             "    rocprofv3 --pmc SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT SQ_WAIT_INST_ANY SQ_WAVES --output-format csv -d <dir>/pmc_sq -o run -- $B",
-             "    rocprofv3 --pmc TCC_EA0_RDREQ_DRAM_sum TCC_EA0_WRREQ_DRAM_sum TCC_EA0_RDREQ_sum TCC_EA0_WRREQ_sum --output-format csv -d <dir>/pmc_dram -o run -- $B",
-             "    rocprofv3 --pmc TCC_EA0_RDREQ_DRAM_sum TCC_EA0_WRREQ_DRAM_sum TCC_EA0_RDREQ_sum TCC_EA0_WRREQ_sum --output-format csv -d <dir>/pmc_copy_dram -o run -- paper_2405_11353_amd/_build/ubench --copy-only",
-             f"    python3 bench.py --summarize-{'he-' if he else ''}counters <dir>", "",
+             "    rocprofv3 --pmc SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_INSTS_LDS SQ_LDS_BANK_CONFLICT SQ_WAIT_INST_ANY SQ_WAVES --output-format csv -d <dir>/pmc_sq -o run -- $B"]
+    if dram:
+        lines += ["    rocprofv3 --pmc TCC_EA0_RDREQ_DRAM_sum TCC_EA0_WRREQ_DRAM_sum TCC_EA0_RDREQ_sum TCC_EA0_WRREQ_sum --output-format csv -d <dir>/pmc_dram -o run -- $B",
+                  "    rocprofv3 --pmc TCC_EA0_RDREQ_DRAM_sum TCC_EA0_WRREQ_DRAM_sum TCC_EA0_RDREQ_sum TCC_EA0_WRREQ_sum --output-format csv -d <dir>/pmc_copy_dram -o run -- paper_2405_11353_amd/_build/ubench --copy-only"]
+    lines += [f"    python3 bench.py --summarize-{'he-' if he else ''}counters <dir>", "",
              f"Scale factors from the plain copy of 1 GiB (read 1 GiB, write 1 GiB per dispatch): "
              f"FETCH_SIZE reads {copy_f:.0f} KiB -> x{f_scale:.3f}; WRITE_SIZE reads {copy_w:.0f} KiB -> x{w_scale:.3f}.",
              f"Kernel source hash: {out['source_hash']}", "",
@@ -211,6 +212,12 @@ def parse():
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--streams", type=int, default=2,
                     help="streams that consecutive steps alternate between (1: all on one stream)")
+    ap.add_argument("--steady-ms", type=float, default=200.0,
+                    help="untimed steps for this long before the warm-up steps of each timed step loop (the "
+                         "clocks ramp up under sustained load); 0 turns it off")
+    ap.add_argument("--clock-warmup-ms", type=float, default=300.0,
+                    help="device copies for this long before the per-kernel timing and before each later "
+                         "section; 0 turns it off")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=3.0,
                     help="seconds per CPU-oracle leg (headline sample, all cores and one thread)")
@@ -257,6 +264,42 @@ def per_run_us(torch, fn, runs, stream):
         e1.record(stream)
     torch.cuda.synchronize()
     return [e0.elapsed_time(e1) * 1e3 for e0, e1 in evs]
+
+
+_EXTRA_STREAMS = []
+
+
+def extra_stream(torch, i):
+    """The i-th stream beside the current one, created once and shared by every
+    section that runs steps on several streams. HIP maps streams onto a few
+    hardware queues (4 here) as they are created; a stream created late in a
+    long run, after the library's and torch's other streams, can share a queue
+    with the current stream, and work on the two then runs one after the other
+    (measured: the fused product on two streams took 66 us per step with the
+    pair the headline uses, 81-83 us with a stream created at the end of the
+    full run)."""
+    while len(_EXTRA_STREAMS) <= i:
+        _EXTRA_STREAMS.append(torch.cuda.Stream())
+    return _EXTRA_STREAMS[i]
+
+
+def clock_warmup(torch, ms):
+    """Device copies (1 GiB each way) for `ms` milliseconds before a timed
+    section. From idle, the GPU's clocks ramp up over the first tens of
+    milliseconds of sustained load, and drop again within half a second of
+    idling. The copies are another kernel, so a kernel trace of the run holds
+    only the timed kernels' own launches."""
+    if ms <= 0:
+        return
+    a = torch.empty(128 << 20, dtype=torch.int64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while (time.perf_counter() - t0) * 1e3 < ms:
+        for _ in range(4):
+            b.copy_(a)
+        torch.cuda.synchronize()
+    del a, b
 
 
 def bench_latency(ntt, si, torch, runs=200, warm=20):
@@ -711,7 +754,7 @@ def bench_batch_sweep(ntt, si, torch, reps=30):
     return {"workload": w.name, "limbs": L, "N": N, "rows": rows}
 
 
-def bench_polymul(ntt, si, torch, steps=100, warm=10, stream_counts=(1, 2)):
+def bench_polymul(ntt, si, torch, steps=100, warm=10, stream_counts=(1, 2), steady_ms=200.0):
     """The headline product (2 ciphertexts, N = 2^16, 24 limbs) through
     ntt_polymul, which keeps the spectra on chip: c = a * b for the 2 pairs of
     components, coefficients in and out. Reported per step and as the
@@ -736,7 +779,15 @@ def bench_polymul(ntt, si, torch, steps=100, warm=10, stream_counts=(1, 2)):
     assert torch.equal(out, ref[:2]), "fused product differs from the unfused one"
     res = {"workload": w.name, "products_per_step": 2 * L, "ntt_equivalent_per_step": 144}
     for n_streams in stream_counts:
-        sts = [stream] + [torch.cuda.Stream() for _ in range(n_streams - 1)]
+        sts = [stream] + [extra_stream(torch, i) for i in range(n_streams - 1)]
+        # as for the headline step: untimed steps for steady_ms, then the warm-up
+        t_st, r = time.perf_counter(), 0
+        while (time.perf_counter() - t_st) * 1e3 < steady_ms:
+            for _ in range(32):
+                x, c = sets[r % n_sets]
+                plan.polymul(x[:2], x[2:], c, batch=2, stream=sts[r % n_streams])
+                r += 1
+            torch.cuda.synchronize()
         for s in range(warm):
             x, c = sets[s % n_sets]
             plan.polymul(x[:2], x[2:], c, batch=2, stream=sts[s % n_streams])
@@ -779,15 +830,17 @@ def bench_ablations(ntt, si, torch, steps=100, warm=5):
     sets = [base.clone() for _ in range(n_sets)]
     stream = torch.cuda.current_stream()
 
+    second = extra_stream(torch, 0)
+
     def make_step(plan, fused):
-        def step(buf):
-            plan.forward(buf, batch=4)
+        def step(buf, st=None):
+            plan.forward(buf, batch=4, stream=st)
             a, b = buf[:2], buf[2:]
             if fused:
-                plan.pointwise_inverse(a, b, a, batch=2)
+                plan.pointwise_inverse(a, b, a, batch=2, stream=st)
             else:
-                plan.pointwise(a, b, a, batch=2)
-                plan.inverse(a, batch=2)
+                plan.pointwise(a, b, a, batch=2, stream=st)
+                plan.inverse(a, batch=2, stream=st)
         return step
 
     def timed(step, n):
@@ -801,6 +854,19 @@ def bench_ablations(ntt, si, torch, steps=100, warm=5):
         e1.record(stream)
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / n * 1e3
+
+    def timed_two_streams(step, n):
+        # consecutive steps alternate between two streams, as in the headline;
+        # wall clock between two device synchronisations
+        sts = [stream, second]
+        for s in range(warm):
+            step(sets[s % n_sets], sts[s % 2])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(n):
+            step(sets[s % n_sets], sts[s % 2])
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / n * 1e6
 
     TW = ntt.NTT_ROW_TWIST_FWD | ntt.NTT_ROW_TWIST_INV
     variants = [
@@ -828,17 +894,29 @@ def bench_ablations(ntt, si, torch, steps=100, warm=5):
     # the variants take turns, round after round, and each reports its median
     # round: drift of the GPU's speed during the section then falls on all alike
     rounds = 5
+    # the row forms are also timed on two streams, where the headline runs and
+    # where they differ (the split-twist rows read fewer table bytes)
+    two = 3
     times = [[] for _ in variants]
+    times2 = [[] for _ in variants[:two]]
     for _ in range(rounds):
         for i, step in enumerate(steps_of):
             times[i].append(timed(step, max(1, steps // rounds)))
+            if i < two:
+                times2[i].append(timed_two_streams(step, max(2, 2 * (steps // rounds))))
     rows = []
-    for (name, log_n1, exact, fused, twist), ts in zip(variants, times):
+    for i, ((name, log_n1, exact, fused, twist), ts) in enumerate(zip(variants, times)):
         us = float(np.median(ts))
-        rows.append({"variant": name, "log_n1": log_n1, "exact_quotient": exact, "fused_product": fused,
-                     "row_twist_mask": twist, "us_per_step": round(us, 1), "ntt_per_s": round(144 / (us * 1e-6), 1),
-                     "rounds_us": [round(t, 1) for t in ts]})
-        log(f"ablation {name}: {us:.1f} us/step (median of {rounds} interleaved rounds)")
+        row = {"variant": name, "log_n1": log_n1, "exact_quotient": exact, "fused_product": fused,
+               "row_twist_mask": twist, "us_per_step": round(us, 1), "ntt_per_s": round(144 / (us * 1e-6), 1),
+               "rounds_us": [round(t, 1) for t in ts]}
+        msg = f"ablation {name}: {us:.1f} us/step"
+        if i < two:
+            us2 = float(np.median(times2[i]))
+            row.update({"us_per_step_two_streams": round(us2, 1), "rounds_two_streams_us": [round(t, 1) for t in times2[i]]})
+            msg += f", {us2:.1f} us/step on two streams"
+        rows.append(row)
+        log(msg + f" (medians of {rounds} interleaved rounds)")
     for plan in plans:
         plan.close()
     return {"workload": w.name, "streams": 1, "rounds": rounds, "rows": rows}
@@ -1102,7 +1180,7 @@ def summarize_polymul_trace(d: str):
     for f in glob.glob(os.path.join(d, "kt", "*kernel_stats.csv")):
         for r in csv.DictReader(open(f)):
             stats[r["Name"]] = r
-    cmd = "python3 bench.py --polymul-only --steps 20 --warmup 5"
+    cmd = "python3 bench.py --polymul-only --steps 20 --warmup 5 --steady-ms 0"
     lines = ["# Kernel trace: ntt_polymul at polymul_n65536_l24 (N=2^16, 24 limbs, 2 products of 2 components), "
              "MI355X", "",
              "Command (run from the repository root on an MI355X):", "",
@@ -1158,11 +1236,14 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     torch.cuda.set_device(0)
     if args.he_only:
+        clock_warmup(torch, args.clock_warmup_ms)
         print(json.dumps(bench_he_steps(ntt, si, torch)), flush=True)
         return
     if args.polymul_only:
         # one stream, so a kernel trace of this run holds unoverlapped launches
-        print(json.dumps(bench_polymul(ntt, si, torch, steps=args.steps, warm=args.warmup, stream_counts=(1,))),
+        clock_warmup(torch, args.clock_warmup_ms)
+        print(json.dumps(bench_polymul(ntt, si, torch, steps=args.steps, warm=args.warmup, stream_counts=(1,),
+                                       steady_ms=args.steady_ms)),
               flush=True)
         return
     w = si.workload_polymul_n16()
@@ -1200,7 +1281,7 @@ def main():
     # each step works on its own buffer set, so a step's inverse passes (48
     # transforms, too few to fill the GPU) overlap the next step's forward
     # passes. With one stream every launch pays its own ramp-up and drain.
-    streams = [stream] + [torch.cuda.Stream() for _ in range(n_streams - 1)]
+    streams = [stream] + [extra_stream(torch, i) for i in range(n_streams - 1)]
 
     def timed_steps(n_streams):
         sts = streams[:n_streams]
@@ -1223,7 +1304,22 @@ def main():
         t1 = time.perf_counter()
         return (t1 - t0) * 1e3 / args.steps, e0.elapsed_time(e1) / args.steps
 
+    def steady(n_streams):
+        # untimed steps for args.steady_ms before the warm-up steps: from idle,
+        # the clocks take tens of milliseconds of sustained load to ramp up, and
+        # they drop again within half a second of idling
+        sts = streams[:n_streams]
+        t0 = time.perf_counter()
+        r = 0
+        while (time.perf_counter() - t0) * 1e3 < args.steady_ms:
+            for _ in range(32):
+                step(sets[r % n_sets], sts[r % n_streams])
+                r += 1
+            torch.cuda.synchronize()
+
+    steady(1)
     ms_wall_1, ms_event_1 = timed_steps(1)
+    steady(len(streams))
     ms_wall, ms_event = timed_steps(len(streams)) if len(streams) > 1 else (ms_wall_1, ms_event_1)
 
     # ---- the timed configuration's output: steps on every stream at once, each
@@ -1272,20 +1368,9 @@ def main():
         f"{value / 1e6:.3f} M NTT/s (one stream: {ms_wall_1 * 1e3:.1f} us, "
         f"{ntts_per_step / (ms_wall_1 / 1e3) / 1e6:.3f} M NTT/s)")
 
-    # ---- per-kernel durations with HIP events on the launch stream. First about
-    # 50 ms of device copies (another kernel, so a kernel-trace summary of these
-    # passes holds only their own launches): clocks settle under load, and the
-    # short profiled run then times the same state as a full run does after its
-    # hundreds of steps.
-    warm_a = torch.empty(32 << 20, dtype=torch.int64, device="cuda")
-    warm_b = torch.empty_like(warm_a)
-    torch.cuda.synchronize()
-    t_warm = time.perf_counter()
-    while time.perf_counter() - t_warm < 0.05:
-        for _ in range(8):
-            warm_b.copy_(warm_a)
-        torch.cuda.synchronize()
-    del warm_a, warm_b
+    # ---- per-kernel durations with HIP events on the launch stream, after the
+    # same clock warm-up as the steps
+    clock_warmup(torch, args.clock_warmup_ms)
 
     def time_kernel(fn, reps):
         evs = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
@@ -1422,15 +1507,23 @@ def main():
     # comparison of the GPU's product on the headline sample)
     cpu = None if args.no_cpu_baseline else cpu_baseline(ntt, si, torch, host, base, step,
                                                          seconds=args.cpu_seconds)
-    latency = None if args.no_latency else bench_latency(ntt, si, torch)
-    batched = None if args.no_batched else bench_batched(ntt, si, torch)
-    serving = None if args.no_serving else bench_serving(ntt, si, torch, n_jobs=args.serving_jobs,
-                                                         warm=args.serving_warmup, rate=args.serving_rate)
-    paper_sizes = None if args.no_paper_sizes else bench_paper_sizes(ntt, si, torch)
-    he_steps = None if args.no_he else bench_he_steps(ntt, si, torch)
-    ablations = None if args.no_ablations else bench_ablations(ntt, si, torch)
-    polymul = None if args.no_polymul else bench_polymul(ntt, si, torch)
-    batch_sweep = None if args.no_batch_sweep else bench_batch_sweep(ntt, si, torch)
+    def section(skip, fn, *a, **kw):
+        # each GPU section starts from the same clock state (the CPU baseline
+        # and the host work between sections leave the GPU idle)
+        if skip:
+            return None
+        clock_warmup(torch, args.clock_warmup_ms)
+        return fn(ntt, si, torch, *a, **kw)
+
+    latency = section(args.no_latency, bench_latency)
+    batched = section(args.no_batched, bench_batched)
+    serving = section(args.no_serving, bench_serving, n_jobs=args.serving_jobs, warm=args.serving_warmup,
+                      rate=args.serving_rate)
+    paper_sizes = section(args.no_paper_sizes, bench_paper_sizes)
+    he_steps = section(args.no_he, bench_he_steps)
+    ablations = section(args.no_ablations, bench_ablations)
+    polymul = section(args.no_polymul, bench_polymul, steady_ms=args.steady_ms)
+    batch_sweep = section(args.no_batch_sweep, bench_batch_sweep)
 
     res = {
         "metric": "NTT/s at N=2^16 x 24 limbs (forward + inverse NTTs of a batched 2-ciphertext negacyclic product)",
@@ -1448,7 +1541,8 @@ def main():
         "config": {"workload": w.name, "N": N, "L": L, "polys": polys, "ntts_per_step": ntts_per_step,
                    "variant": {"path": "fourstep" if path == ntt.NTT_PATH_FOURSTEP else "lds", "log_n1": logn1},
                    "rotating_sets": n_sets, "footprint_MiB": n_sets * set_bytes >> 20,
-                   "streams": len(streams)},
+                   "streams": len(streams), "untimed_steady_ms": args.steady_ms,
+                   "clock_warmup_ms": args.clock_warmup_ms},
         "roofline": roofline,
         "kernels": per_kernel,
         "per_call": per_call,
