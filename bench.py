@@ -238,6 +238,8 @@ def parse():
     ap.add_argument("--no-batch-sweep", action="store_true")
     ap.add_argument("--polymul-only", action="store_true",
                     help="only the fused product (ntt_polymul) on one stream, --steps steps after --warmup")
+    ap.add_argument("--summarize-roctx", metavar="DIR", default=None,
+                    help="write profiles/roctx_ranges_polymul_n65536_l24.md from a marker trace of the headline run")
     ap.add_argument("--summarize-polymul-trace", metavar="DIR",
                     help="write profiles/polymul_fused_n65536_l24_trace.md from a kernel trace of --polymul-only")
     ap.add_argument("--serving-rate", type=float, default=15000.0,
@@ -1169,6 +1171,50 @@ POLYMUL_TRACE_KEYS = [("k_col<nttk::Arith64<false, false>, 8, 16, true", "column
                       ("k_col<nttk::Arith64<false, false>, 8, 16, false", "inverse column pass")]
 
 
+ROCTX_CMD = ("python3 bench.py --steps 20 --warmup 5 --steady-ms 0 --streams 1 --no-cpu-baseline --no-per-call "
+             "--no-batched --no-serving --no-paper-sizes --no-he --no-ablations --no-polymul --no-batch-sweep "
+             "--no-latency")
+
+
+def summarize_roctx(d: str):
+    """Writes profiles/roctx_ranges_polymul_n65536_l24.md from a rocprofv3
+    marker and kernel trace (rt/*marker_api_trace.csv, rt/*kernel_stats.csv
+    under d) of the headline run with NTT_ROCTX=1: the library's ranges per
+    call, with their host-side durations, beside the kernels they launched."""
+    import csv
+    import glob
+    ranges = {}
+    for f in glob.glob(os.path.join(d, "rt", "*marker_api_trace.csv")):
+        for r in csv.DictReader(open(f)):
+            msg = r.get("Function") or r.get("Message") or r.get("Name") or ""
+            if not msg.startswith("ntt_"):
+                continue
+            dur = (float(r["End_Timestamp"]) - float(r["Start_Timestamp"])) / 1e3
+            ranges.setdefault(msg, []).append(dur)
+    stats = {}
+    for f in glob.glob(os.path.join(d, "rt", "*kernel_stats.csv")):
+        for r in csv.DictReader(open(f)):
+            stats[r["Name"]] = r
+    lines = ["# roctx ranges: polymul_n65536_l24 (N=2^16, 24 limbs, 2 ciphertexts), MI355X", "",
+             "Command (run from the repository root on an MI355X, with the library's ranges switched on):", "",
+             "    export NTT_ROCTX=1",
+             f"    rocprofv3 --marker-trace --kernel-trace --stats --output-format csv -d <dir>/rt -o rt -- {ROCTX_CMD}",
+             "    python3 bench.py --summarize-roctx <dir>", "",
+             "Ranges cover the host side of each call (argument checks, variant choice, launches), not the kernels' "
+             "execution, which is asynchronous.", "",
+             "| range | calls | mean host us | median host us |", "|---|---|---|---|"]
+    for name in sorted(ranges):
+        v = sorted(ranges[name])
+        lines.append(f"| `{name}` | {len(v)} | {sum(v) / len(v):.2f} | {v[len(v) // 2]:.2f} |")
+    lines += ["", "| kernel | calls | rocprof avg us |", "|---|---|---|"]
+    for name, r in sorted(stats.items(), key=lambda kv: -float(kv[1]["TotalDurationNs"]))[:8]:
+        lines.append(f"| `{name.split('(')[0].replace('void ', '')}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} |")
+    out = os.path.join(ROOT, "profiles", "roctx_ranges_polymul_n65536_l24.md")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def summarize_polymul_trace(d: str):
     """Writes profiles/polymul_fused_n65536_l24_trace.md from the rocprofv3
     kernel trace (kt/*kernel_stats.csv under d) of `bench.py --polymul-only`:
@@ -1222,6 +1268,9 @@ def main():
         return
     if args.summarize_polymul_trace:
         summarize_polymul_trace(args.summarize_polymul_trace)
+        return
+    if args.summarize_roctx:
+        summarize_roctx(args.summarize_roctx)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

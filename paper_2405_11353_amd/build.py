@@ -50,7 +50,7 @@ def build(jobs: int = 8, verbose: bool = True) -> str:
     with cf.ThreadPoolExecutor(max_workers=max(1, min(jobs, len(units)))) as ex:
         objs = list(ex.map(_compile, units))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs + ["-lrocprofiler-sdk-roctx"]
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
     # the VALU/HBM microbenchmark (a standalone executable)

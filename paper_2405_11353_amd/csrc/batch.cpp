@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "ntt_internal.hpp"
+#include "trace.hpp"
 
 namespace {
 struct Bucket {
@@ -209,6 +210,7 @@ ntt_batch* ntt_batch_create(const ntt_job_desc* jobs, uint32_t n_jobs, uint32_t 
 }
 
 int ntt_batch_run(ntt_batch* b, void* stream) {
+  ntti::Range r("ntt_batch_run");
   if (!b) return NTT_ERR_ARG;
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess) return NTT_ERR_HIP;

@@ -16,6 +16,7 @@
 #include "ntt_internal.hpp"
 #include "params.hpp"
 #include "polymul.hpp"
+#include "trace.hpp"
 
 namespace {
 thread_local int g_last_error = NTT_OK;
@@ -544,14 +545,22 @@ static int run_ntt(const ntt_plan* pc, void* data, uint32_t batch, void* stream,
 
 extern "C" {
 
-int ntt_forward(const ntt_plan* p, void* d, uint32_t batch, void* stream) { return run_ntt(p, d, batch, stream, true); }
-int ntt_inverse(const ntt_plan* p, void* d, uint32_t batch, void* stream) { return run_ntt(p, d, batch, stream, false); }
+int ntt_forward(const ntt_plan* p, void* d, uint32_t batch, void* stream) {
+  ntti::Range r("ntt_forward");
+  return run_ntt(p, d, batch, stream, true);
+}
+int ntt_inverse(const ntt_plan* p, void* d, uint32_t batch, void* stream) {
+  ntti::Range r("ntt_inverse");
+  return run_ntt(p, d, batch, stream, false);
+}
 
 int ntt_forward_stage(const ntt_plan* p, void* d, uint32_t batch, int stage, void* stream) {
+  ntti::Range r("ntt_forward_stage");
   if (stage != 0 && stage != 1) return NTT_ERR_ARG;
   return run_ntt(p, d, batch, stream, true, 1 << stage);
 }
 int ntt_inverse_stage(const ntt_plan* p, void* d, uint32_t batch, int stage, void* stream) {
+  ntti::Range r("ntt_inverse_stage");
   if (stage != 0 && stage != 1) return NTT_ERR_ARG;
   return run_ntt(p, d, batch, stream, false, 1 << stage);
 }
@@ -561,11 +570,13 @@ static int run_mul_inverse(const ntt_plan* pc, const void* a, const void* b, voi
 
 int ntt_pointwise_mul_inverse(const ntt_plan* pc, const void* a, const void* b, void* c, uint32_t batch,
                               void* stream) {
+  ntti::Range r("ntt_pointwise_mul_inverse");
   return run_mul_inverse(pc, a, b, c, batch, stream, 3);
 }
 
 int ntt_pointwise_mul_inverse_stage(const ntt_plan* pc, const void* a, const void* b, void* c, uint32_t batch,
                                     int stage, void* stream) {
+  ntti::Range r("ntt_pointwise_mul_inverse_stage");
   if (stage != 0 && stage != 1) return NTT_ERR_ARG;
   return run_mul_inverse(pc, a, b, c, batch, stream, 1 << stage);
 }
@@ -626,6 +637,7 @@ static int run_mul_inverse(const ntt_plan* pc, const void* a, const void* b, voi
 extern "C" {
 
 int ntt_pointwise_mul(const ntt_plan* p, const void* a, const void* b, void* c, uint32_t batch, void* stream) {
+  ntti::Range r("ntt_pointwise_mul");
   int rc = check_common(p, batch);
   if (rc != NTT_OK) return rc;
   if (!a || !b || !c) return NTT_ERR_ARG;
@@ -719,5 +731,6 @@ static int run_polymul(const ntt_plan* pc, const void* a, const void* b, void* c
 }
 
 extern "C" int ntt_polymul(const ntt_plan* p, const void* a, const void* b, void* c, uint32_t batch, void* stream) {
+  ntti::Range r("ntt_polymul");
   return run_polymul(p, a, b, c, batch, stream);
 }

@@ -10,6 +10,7 @@
 #include "ntt.h"
 #include "ntt_internal.hpp"
 #include "params.hpp"
+#include "trace.hpp"
 
 typedef unsigned __int128 u128;
 
@@ -50,6 +51,7 @@ static uint64_t partial_product(const std::vector<uint64_t>& s, uint32_t skip, u
 extern "C" {
 
 int ntt_tensor_product(const ntt_plan* p, const void* a, const void* b, void* d, uint32_t batch, void* stream) {
+  ntti::Range r("ntt_tensor_product");
   if (!p || !a || !b || !d || batch == 0) return fail(NTT_ERR_ARG);
   if ((uint64_t)batch * p->L * p->N * 3 > (1ull << 40)) return fail(NTT_ERR_ARG);
   int dev = -1;
@@ -164,11 +166,13 @@ static int bconv_run(const ntt_bconv* c, const void* x, const void* y, void* out
 }
 
 int ntt_base_conv(const ntt_bconv* c, const void* d_x, void* d_out, uint32_t batch, void* stream) {
+  ntti::Range r("ntt_base_conv");
   return bconv_run(c, d_x, nullptr, d_out, batch, stream);
 }
 
 int ntt_mod_down(const ntt_bconv* c, const void* d_x, const void* d_y, void* d_out, uint32_t batch,
                  void* stream) {
+  ntti::Range r("ntt_mod_down");
   if (!d_y) return fail(NTT_ERR_ARG);
   return bconv_run(c, d_x, d_y, d_out, batch, stream);
 }

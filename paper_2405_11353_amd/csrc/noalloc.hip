@@ -12,6 +12,7 @@
 
 #include "ntt.h"
 #include "ntt_internal.hpp"
+#include "trace.hpp"
 
 static_assert(NTT_NOALLOC_SCRATCH_BYTES % 256 == 0, "whole 256-byte blocks");
 
@@ -39,6 +40,7 @@ int scratch_address(void** out) {
 }  // namespace
 
 extern "C" int ntt_forward_noalloc(const ntt_plan* plan, void* d_data, uint32_t batch, void* stream) {
+  ntti::Range r("ntt_forward_noalloc");
   if (!plan || !d_data || batch == 0) return NTT_ERR_ARG;
   void* s = nullptr;
   const int rc = scratch_address(&s);

@@ -33,6 +33,7 @@
 #include "ntt_internal.hpp"
 #include "params.hpp"
 #include "polymul.hpp"
+#include "trace.hpp"
 
 namespace {
 
@@ -178,6 +179,7 @@ struct ntt_server {
 };
 
 static int launch_batch(ntt_server* s, Slot& slot) {
+  ntti::Range r("ntt_server batch");
   if (s->simulate) {
     uint64_t items = 0;
     for (Job* j : slot.jobs) items += j->items();

@@ -14,6 +14,7 @@
 
 #include "ntt_internal.hpp"
 #include "params.hpp"
+#include "trace.hpp"
 
 namespace ntti {
 namespace {
@@ -137,6 +138,7 @@ using namespace ntti;
 extern "C" {
 
 int ntt_autotune(uint32_t N, uint32_t flags, uint32_t items, uint32_t reps, ntt_tune_choice* best_out) {
+  ntti::Range r("ntt_autotune");
   if (N < 2 || N > (1u << 17) || (N & (N - 1))) return NTT_ERR_N;
   if (items == 0 || reps == 0 || (flags & ~NTT_WORD32)) return NTT_ERR_ARG;
   const int word = (flags & NTT_WORD32) ? 32 : 64;

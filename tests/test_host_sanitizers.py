@@ -26,7 +26,7 @@ def build(tmp_path, name, sanitize, compiler=None):
     cmd = [gxx, "-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer", "-D__HIP_PLATFORM_AMD__",
            "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-I", os.path.join(ROCM, "include")] + sanitize + \
         srcs + ["-o", exe, "-L", os.path.join(ROCM, "lib"), "-Wl,-rpath," + os.path.join(ROCM, "lib"),
-                "-lamdhip64", "-lpthread", "-ldl"]
+                "-lamdhip64", "-lrocprofiler-sdk-roctx", "-lpthread", "-ldl"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         if "sanitizer" in r.stderr and ("cannot find" in r.stderr or "not found" in r.stderr):
