@@ -49,3 +49,22 @@ def test_job_mixes():
     assert all(b.arrival_s > a.arrival_s for a, b in zip(tr, tr[1:]))
     assert {j.op for j in tr} == {"ntt", "polymul"}
     assert all(j.N <= 1 << 17 and 1 <= j.L <= 40 for j in tr)
+
+
+def test_configs_match_the_generator():
+    """configs/*.json record the workloads the tests and bench.py draw; they
+    are written by seeded_inputs.configs and must not drift from it."""
+    import json
+    import os
+
+    from seeded_inputs.configs import CONFIG_DIR, workload_configs
+    want = workload_configs()
+    files = sorted(f for f in os.listdir(CONFIG_DIR) if f.endswith(".json"))
+    assert files == sorted(name + ".json" for name in want)
+    for name, cfg in want.items():
+        with open(os.path.join(CONFIG_DIR, name + ".json")) as fh:
+            assert json.load(fh) == json.loads(json.dumps(cfg)), name
+    # the primes in the files are the ones the plans are built with
+    head = want["polymul_n65536_l24"]
+    assert [int(q) for q in head["moduli"]] == si.workload_polymul_n16().moduli
+    assert all(int(q) % (1 << 17) == 1 for q in head["moduli"])
