@@ -815,6 +815,35 @@ k_row_tw(const typename A::word* in, typename A::word* out, const typename A::tw
   }
 }
 
+#ifndef NTT_ROW_SHUFFLE
+#define NTT_ROW_SHUFFLE 0
+#endif
+#if NTT_ROW_SHUFFLE
+// 32-bit value of lane (lane ^ m) within a row of 16 lanes
+template <int M>
+__device__ __forceinline__ uint32_t xor_lane32(uint32_t x) {
+  if constexpr (M == 1) return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, true);  // quad_perm 1,0,3,2
+  else if constexpr (M == 2) return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x4E, 0xF, 0xF, true);  // 2,3,0,1
+  else return (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, (M << 10) | 0x1F);  // bit mode, xor M
+}
+// the 16 x 16 transpose between phases done across lanes instead of through
+// LDS: lane t's value j becomes lane j's value t, in four swap stages
+__device__ __forceinline__ void transpose_lanes16(uint64_t (&v)[16], uint32_t t) {
+  static_for<0, 4>([&](auto K_) {
+    constexpr int m = 8 >> decltype(K_)::value;
+    const bool hi = (t & m) != 0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      if (j & m) continue;
+      const uint64_t send = hi ? v[j] : v[j | m];
+      const uint64_t recv = ((uint64_t)xor_lane32<m>((uint32_t)(send >> 32)) << 32) | xor_lane32<m>((uint32_t)send);
+      v[j] = hi ? recv : v[j];
+      v[j | m] = hi ? v[j | m] : recv;
+    }
+  });
+}
+#endif
+
 // ============================================================ split-twist row passes
 // The rows of k_row_tw with the twist split in two. After the first P row
 // stages (P: those of the first register phase), the twisted row's state is
@@ -893,12 +922,19 @@ k_row_st(const typename A::word* in, typename A::word* out, const typename A::tw
   for (int i = 0; i < V; ++i) v[i] = a.mul(v[i], bt[i & (ST::NF - 1)]);
   static_for<1, S::NPH>([&](auto P_) {
     constexpr int p = decltype(P_)::value;
-    if constexpr (p > 1) wave_lds_sync();
+#if NTT_ROW_SHUFFLE
+    if constexpr (p == 1 && S::NPH == 2 && V == 16 && TPR == 16 && sizeof(W) == 8) {
+      transpose_lanes16(v, t);
+    } else
+#endif
+    {
+      if constexpr (p > 1) wave_lds_sync();
 #pragma unroll
-    for (int i = 0; i < V; ++i) sh[pad16(pos<LOGN2, LV>(p - 1, t, i))] = v[i];
-    wave_lds_sync();
+      for (int i = 0; i < V; ++i) sh[pad16(pos<LOGN2, LV>(p - 1, t, i))] = v[i];
+      wave_lds_sync();
 #pragma unroll
-    for (int i = 0; i < V; ++i) v[i] = sh[pad16(pos<LOGN2, LV>(p, t, i))];
+      for (int i = 0; i < V; ++i) v[i] = sh[pad16(pos<LOGN2, LV>(p, t, i))];
+    }
     ct_phase_cyc<A, S::rs(p), false, rp_of<A>(RP_FRESH), S::s0(p) - ST::P>(a, v, cyc, S::s0(p),
                                                                            grp<LOGN2, LV>(p, t));
   });
