@@ -5,8 +5,12 @@ pointwise product of the components (48), inverse NTT of the products (48),
 all through libntt.so on one MI355X. Inputs are seeded synthetic residues,
 resident in HBM before timing; the step rotates over buffer sets totalling
 more than 1 GiB so each step reads data that is not in the 256 MB last-level
-cache. Prints one JSON line (metric, value in NTT/s, roofline of the dominant
-kernel measured with HIP events, per-call baseline, CPU oracle baseline).
+cache. Each timed step loop (one stream, then consecutive steps alternating
+between two streams) runs --steady-ms of untimed steps first, then the
+--warmup steps, then exactly --steps timed steps between two device
+synchronisations. Prints one JSON line (metric, value in NTT/s, roofline of
+the dominant kernel measured with HIP events, per-call baseline, CPU oracle
+baseline, and the other sections' results).
 """
 from __future__ import annotations
 
