@@ -909,7 +909,7 @@ def bench_ablations(ntt, si, torch, steps=100, warm=5):
         for i, step in enumerate(steps_of):
             times[i].append(timed(step, max(1, steps // rounds)))
             if i < two:
-                times2[i].append(timed_two_streams(step, max(2, 2 * (steps // rounds))))
+                times2[i].append(timed_two_streams(step, max(2, steps)))
     rows = []
     for i, ((name, log_n1, exact, fused, twist), ts) in enumerate(zip(variants, times)):
         us = float(np.median(ts))
