@@ -112,7 +112,10 @@ void ntt_plan_destroy(ntt_plan* plan);
  * ([batch][L][N] words on the plan's device). Asynchronous on stream. */
 int ntt_forward(const ntt_plan* plan, void* d_data, uint32_t batch, void* stream);
 
-/* Inverse NTT (including the N^-1 scaling), in place. Asynchronous. */
+/* Inverse NTT (including the N^-1 scaling), in place. Asynchronous. On the
+ * four-step path the result is written with streaming (nontemporal) stores,
+ * which do not keep it in the caches: nothing in the transform reads it again,
+ * and the caches stay with what the next kernels read. */
 int ntt_inverse(const ntt_plan* plan, void* d_data, uint32_t batch, void* stream);
 
 /* d_c = d_a * d_b elementwise mod q_l over [batch][L][N]; d_c may alias d_a
