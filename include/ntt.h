@@ -33,6 +33,14 @@
  * values give unspecified (but in-bounds) results, or NTT_ERR_RANGE with
  * NTT_DEBUG_CHECK. The functions are
  * thread-safe for concurrent use of one plan on different streams.
+ *
+ * Allocation failures: every device and pinned-host allocation the library
+ * makes is checked; a failed one makes the call return NTT_ERR_NOMEM (a
+ * creating call returns NULL with that code) after freeing what the call had
+ * allocated, with nothing enqueued. The pool's pinned copy of a table falls
+ * back to pageable host memory instead. For testing, the environment variable
+ * NTT_FAIL_ALLOC=k makes the k-th allocation counted from when the variable
+ * took its current value fail.
  */
 #ifndef NTT_H
 #define NTT_H

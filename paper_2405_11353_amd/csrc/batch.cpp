@@ -120,7 +120,7 @@ static int build(ntt_batch* b, const ntt_job_desc* jobs, uint32_t n_jobs) {
     k.logN1 = logN1;
     if (path == NTT_PATH_FOURSTEP) {
       const size_t bytes = ((size_t)n << k.logN) * 8;
-      if (hipMalloc(&k.scratch, bytes) != hipSuccess) return NTT_ERR_NOMEM;
+      if (ntti::dev_malloc(&k.scratch, bytes) != hipSuccess) return NTT_ERR_NOMEM;
       b->scratch_bytes += bytes;
       for (uint32_t i = 0; i < n; ++i) k.items[i].scratch = (uint64_t*)k.scratch + ((size_t)i << k.logN);
       b->kernels += 2;
@@ -135,7 +135,7 @@ static int build(ntt_batch* b, const ntt_job_desc* jobs, uint32_t n_jobs) {
   std::vector<nttk::ItemDesc> all;
   all.reserve(off);
   for (auto& k : b->buckets) all.insert(all.end(), k.items.begin(), k.items.end());
-  if (hipMalloc(&b->d_desc, all.size() * sizeof(nttk::ItemDesc)) != hipSuccess) return NTT_ERR_NOMEM;
+  if (ntti::dev_malloc(&b->d_desc, all.size() * sizeof(nttk::ItemDesc)) != hipSuccess) return NTT_ERR_NOMEM;
   if (hipMemcpy(b->d_desc, all.data(), all.size() * sizeof(nttk::ItemDesc), hipMemcpyHostToDevice) != hipSuccess)
     return NTT_ERR_HIP;
   if (b->flags & NTT_BATCH_NO_GRAPH) return NTT_OK;

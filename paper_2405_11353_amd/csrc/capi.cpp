@@ -8,6 +8,7 @@
 #include <atomic>
 #include <mutex>
 #include <new>
+#include <string>
 #include <thread>
 #include <vector>
 
@@ -74,6 +75,37 @@ static void select_variant(const ntt_plan* p, uint32_t items, int* path, int* lo
 }
 
 namespace ntti {
+namespace {
+std::mutex g_alloc_mu;
+std::string g_alloc_env;  // NTT_FAIL_ALLOC as last seen
+long g_alloc_count = 0;   // allocations since it changed
+bool forced_failure() {
+  const char* e = getenv("NTT_FAIL_ALLOC");
+  std::lock_guard<std::mutex> g(g_alloc_mu);
+  const std::string v = e ? e : "";
+  if (v != g_alloc_env) {
+    g_alloc_env = v;
+    g_alloc_count = 0;
+  }
+  const long k = v.empty() ? 0 : atol(v.c_str());
+  return k > 0 && ++g_alloc_count == k;
+}
+}  // namespace
+hipError_t dev_malloc(void** p, size_t bytes) {
+  if (forced_failure()) {
+    *p = nullptr;
+    return hipErrorOutOfMemory;
+  }
+  return hipMalloc(p, bytes);
+}
+hipError_t host_malloc(void** p, size_t bytes) {
+  if (forced_failure()) {
+    *p = nullptr;
+    return hipErrorOutOfMemory;
+  }
+  return hipHostMalloc(p, bytes, hipHostMallocDefault);
+}
+
 void for_limbs(uint32_t L, const std::function<void(uint32_t)>& f) {
   const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
   const unsigned n = std::min<unsigned>(L, std::min(16u, hw));
@@ -237,8 +269,8 @@ ntt_plan* ntt_plan_create_ex(uint32_t N, const uint64_t* moduli, uint32_t L, uin
     nttp::twiddles(moduli[l], roots[l], p->logN, word, true, inv.data() + l * tw_bytes, cyclic);
     nttp::modinfo(moduli[l], word, mod.data() + l * mod_bytes);
   });
-  if (hipMalloc(&p->d_tw_fwd, fwd.size()) != hipSuccess || hipMalloc(&p->d_tw_inv, inv.size()) != hipSuccess ||
-      hipMalloc(&p->d_mod, mod.size()) != hipSuccess) {
+  if (ntti::dev_malloc(&p->d_tw_fwd, fwd.size()) != hipSuccess || ntti::dev_malloc(&p->d_tw_inv, inv.size()) != hipSuccess ||
+      ntti::dev_malloc(&p->d_mod, mod.size()) != hipSuccess) {
     release(p);
     fail(NTT_ERR_NOMEM);
     return nullptr;
@@ -252,7 +284,7 @@ ntt_plan* ntt_plan_create_ex(uint32_t N, const uint64_t* moduli, uint32_t L, uin
   }
   const char* dbg = getenv("NTT_DEBUG_CHECK");
   p->debug_check = (flags & NTT_DEBUG_CHECK) || (dbg && *dbg && strcmp(dbg, "0") != 0);
-  if (p->debug_check && hipMalloc(&p->d_flag, 256) != hipSuccess) {
+  if (p->debug_check && ntti::dev_malloc(&p->d_flag, 256) != hipSuccess) {
     release(p);
     fail(NTT_ERR_NOMEM);
     return nullptr;
@@ -360,13 +392,13 @@ static int get_scratch(ntt_plan* p, void* stream, size_t bytes, void** out) {
     (void)hipFree(s.ptr);
     s.ptr = nullptr;
     s.bytes = 0;
-    if (hipMalloc(&s.ptr, bytes) != hipSuccess) return NTT_ERR_NOMEM;
+    if (ntti::dev_malloc(&s.ptr, bytes) != hipSuccess) return NTT_ERR_NOMEM;
     s.bytes = bytes;
     *out = s.ptr;
     return NTT_OK;
   }
   void* ptr = nullptr;
-  if (hipMalloc(&ptr, bytes) != hipSuccess) return NTT_ERR_NOMEM;
+  if (ntti::dev_malloc(&ptr, bytes) != hipSuccess) return NTT_ERR_NOMEM;
   p->scratch.push_back({stream, ptr, bytes});
   *out = ptr;
   return NTT_OK;
@@ -405,8 +437,13 @@ static int paper_tables(ntt_plan* p) {
     }
     put(2 * (size_t)p->L * half + l, nttp::powmod(p->N % q, q - 2, q), q);
   }
-  if (hipMalloc(&p->d_paper, host.size()) != hipSuccess) return NTT_ERR_NOMEM;
-  if (hipMemcpy(p->d_paper, host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess) return NTT_ERR_HIP;
+  void* d = nullptr;
+  if (ntti::dev_malloc(&d, host.size()) != hipSuccess) return NTT_ERR_NOMEM;
+  if (hipMemcpy(d, host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(d);  // not kept: a later call builds the tables again
+    return NTT_ERR_HIP;
+  }
+  p->d_paper = d;
   return NTT_OK;
 }
 
@@ -435,7 +472,7 @@ static int row_tables(ntt_plan* p, int logN1, bool fwd, nttk::Launch* c) {
         nttp::twiddles(q, w2, logN2, p->word, !fwd, ct + l * cyc_bytes, true);
       });
       void* d = nullptr;
-      if (hipMalloc(&d, host.size()) != hipSuccess) return NTT_ERR_NOMEM;
+      if (ntti::dev_malloc(&d, host.size()) != hipSuccess) return NTT_ERR_NOMEM;
       if (hipMemcpy(d, host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess) {
         (void)hipFree(d);
         return NTT_ERR_HIP;

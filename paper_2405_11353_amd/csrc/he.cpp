@@ -131,9 +131,9 @@ ntt_bconv* ntt_bconv_create(uint32_t N, const uint64_t* src, uint32_t L, const u
     const uint64_t sinv = nttp::powmod(partial_product(c->src, L, t), t - 2, t);
     hd[j] = nttk::BcDst{t, 0 - t, 0 - inv, (uint64_t)(((u128)1 << 64) / t), sinv, shoup_companion(sinv, t), 0, 0};
   }
-  if (hipMalloc(&c->d_src, hs.size() * sizeof(nttk::BcSrc)) != hipSuccess ||
-      hipMalloc(&c->d_mat, hm.size() * sizeof(uint64_t)) != hipSuccess ||
-      hipMalloc(&c->d_dst, hd.size() * sizeof(nttk::BcDst)) != hipSuccess) {
+  if (ntti::dev_malloc(&c->d_src, hs.size() * sizeof(nttk::BcSrc)) != hipSuccess ||
+      ntti::dev_malloc(&c->d_mat, hm.size() * sizeof(uint64_t)) != hipSuccess ||
+      ntti::dev_malloc(&c->d_dst, hd.size() * sizeof(nttk::BcDst)) != hipSuccess) {
     bconv_release(c);
     fail(NTT_ERR_NOMEM);
     return nullptr;

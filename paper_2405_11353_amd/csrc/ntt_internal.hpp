@@ -105,4 +105,19 @@ int forward_fixed_scratch(const ntt_plan* p, void* data, uint32_t batch, void* s
 // f(l) for every l < L, spread over up to 16 host threads (table generation)
 void for_limbs(uint32_t L, const std::function<void(uint32_t)>& f);
 
+// Every device and pinned-host allocation of the library goes through these.
+// For tests of the failure paths, the environment variable NTT_FAIL_ALLOC=k
+// makes the k-th allocation after the variable last changed value fail (as
+// hipErrorOutOfMemory, *p = nullptr); unset or 0, nothing is forced.
+hipError_t dev_malloc(void** p, size_t bytes);
+hipError_t host_malloc(void** p, size_t bytes);
+template <class T>
+hipError_t dev_malloc(T** p, size_t bytes) {
+  return dev_malloc(reinterpret_cast<void**>(p), bytes);
+}
+template <class T>
+hipError_t host_malloc(T** p, size_t bytes) {
+  return host_malloc(reinterpret_cast<void**>(p), bytes);
+}
+
 }  // namespace ntti

@@ -56,7 +56,7 @@ int pool_host(int word, uint64_t q, uint32_t logN, HostTables* out) {
   if (it == g_host.end()) {
     // pinned when a device is there, so that uploads from it are asynchronous
     void* p = nullptr;
-    if (hipHostMalloc(&p, host.size(), hipHostMallocDefault) != hipSuccess) {
+    if (ntti::host_malloc(&p, host.size()) != hipSuccess) {
       p = new (std::nothrow) unsigned char[host.size()];
       if (!p) return NTT_ERR_NOMEM;
     }
@@ -82,7 +82,7 @@ int pool_get(int word, uint64_t q, uint32_t logN, PoolEntry* out) {
   if (rc != NTT_OK) return rc;
   const size_t tb = ((size_t)1 << logN) * nttp::tw_entry_bytes(word);
   void* d = nullptr;
-  if (hipMalloc(&d, host.bytes) != hipSuccess) return NTT_ERR_NOMEM;
+  if (ntti::dev_malloc(&d, host.bytes) != hipSuccess) return NTT_ERR_NOMEM;
   if (hipMemcpy(d, host.data, host.bytes, hipMemcpyHostToDevice) != hipSuccess) {
     (void)hipFree(d);
     return NTT_ERR_HIP;

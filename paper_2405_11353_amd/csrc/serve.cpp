@@ -544,15 +544,15 @@ ntt_server* ntt_server_create(const ntt_server_config* cfg) {
   if (!s->simulate) {
     ntti::tune_autoload();
     if (hipGetDevice(&s->device) != hipSuccess) rc = NTT_ERR_HIP;
-    if (rc == NTT_OK && hipMalloc(&s->base, cfg->hbm_budget_bytes) != hipSuccess) rc = NTT_ERR_NOMEM;
+    if (rc == NTT_OK && ntti::dev_malloc(&s->base, cfg->hbm_budget_bytes) != hipSuccess) rc = NTT_ERR_NOMEM;
     for (Slot& sl : s->slots) {
       if (rc != NTT_OK) break;
       sl.cap = cap;
       if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
           hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess)
         rc = NTT_ERR_HIP;
-      else if (hipMalloc(&sl.d_desc, cap * sizeof(nttk::ItemDesc)) != hipSuccess ||
-               hipHostMalloc(&sl.h_desc, cap * sizeof(nttk::ItemDesc), hipHostMallocDefault) != hipSuccess)
+      else if (ntti::dev_malloc(&sl.d_desc, cap * sizeof(nttk::ItemDesc)) != hipSuccess ||
+               ntti::host_malloc(&sl.h_desc, cap * sizeof(nttk::ItemDesc)) != hipSuccess)
         rc = NTT_ERR_NOMEM;
     }
   }

@@ -152,7 +152,7 @@ int ntt_autotune(uint32_t N, uint32_t flags, uint32_t items, uint32_t reps, ntt_
   hipStream_t s = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   int rc = NTT_OK;
-  if (hipMalloc(&buf, bytes) != hipSuccess) rc = NTT_ERR_NOMEM;
+  if (ntti::dev_malloc(&buf, bytes) != hipSuccess) rc = NTT_ERR_NOMEM;
   // zeros are valid canonical inputs; the kernels' timing does not depend on values
   if (rc == NTT_OK && (hipMemset(buf, 0, bytes) != hipSuccess || hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess ||
                        hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))

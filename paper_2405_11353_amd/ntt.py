@@ -13,7 +13,6 @@ import os
 PKG = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(PKG, "libntt.so")
 
-NTT_OK = 0
 NTT_WORD32 = 0x1
 NTT_ORDER_BITREV = 0x2
 NTT_CYCLIC = 0x4
@@ -45,6 +44,16 @@ class BatchInfo(ctypes.Structure):
 
 NTT_REQ_NTT, NTT_REQ_INTT, NTT_REQ_POLYMUL = 0, 1, 2
 NTT_SERVER_SIMULATE = 0x1
+# status codes (include/ntt.h)
+NTT_OK = 0
+NTT_ERR_ARG = -1
+NTT_ERR_N = -2
+NTT_ERR_MODULUS = -3
+NTT_ERR_NOMEM = -4
+NTT_ERR_HIP = -5
+NTT_ERR_BUDGET = -6
+NTT_ERR_UNSUPPORTED = -7
+NTT_ERR_STATE = -8
 NTT_ERR_TIMEOUT = -9
 NTT_ERR_SCRATCH = -10
 NTT_ERR_RANGE = -11
