@@ -971,6 +971,28 @@ k_row_st(const typename A::word* in, typename A::word* out, const typename A::tw
 // Inverse: the spectrum rows (or with MULIN the product of two) through the
 // cyclic inverse phases, the factors beta_r^-(...), and the merged inverse
 // first phase; rows written in place, in the lazy range the column pass takes.
+// Lane map of the inverse row pass's phases. A phase whose groups hold 8
+// offsets (stride 2^3) with 8 values per thread places, under the identity
+// t = (group << 3) + offset, two groups in each 16-lane LDS cycle: their
+// 8-word runs lie 64 + 4 padded words apart and share half their banks. The
+// map below gives each 16 lanes two offset bits and two group bits, so the
+// four groups' runs start 0, 4, 8 and 12 words apart (mod 16) and the 16
+// 64-bit accesses cover the 32 banks once. It is a permutation of [0, TPR):
+// lane bits 0-1 -> offset bits 0-1, 4 -> offset bit 2, 2-3 -> group bits 0-1,
+// 5 -> group bit 2. Rows of 16 lanes (one 16-lane cycle per row whatever the
+// map) keep the identity.
+#ifndef NTT_ROW_INV_LANES
+#define NTT_ROW_INV_LANES 1
+#endif
+template <int LOGN2, int LV>
+__device__ __forceinline__ uint32_t row_inv_lane(int p, uint32_t t) {
+  constexpr uint32_t TPR = (1u << LOGN2) >> LV;
+  if (!NTT_ROW_INV_LANES || LV != 3 || TPR < 32 || Sched<LOGN2, LV>::lgs(p) != 3) return t;
+  const uint32_t off = (t & 3u) | (((t >> 4) & 1u) << 2);
+  const uint32_t g = ((t >> 2) & 3u) | ((t >> 5) << 2);
+  return (g << 3) | off;
+}
+
 template <class A, int LOGN2, bool NATURAL, bool MULIN, int LV = 3>
 __global__ void __launch_bounds__(16 << (LOGN2 - LV))
 k_row_st_inv(const typename A::word* in, typename A::word* out, const typename A::tw_t* __restrict__ tw_all,
@@ -1054,22 +1076,24 @@ k_row_st_inv(const typename A::word* in, typename A::word* out, const typename A
 #pragma unroll
   for (int f = 0; f < ST::NF; ++f) bt[f] = trow[f << ST::LG];
 #pragma unroll
-  for (int i = 0; i < V; ++i) v[i] = sh[pad16(pos<LOGN2, LV>(S::NPH - 1, t, i))];
+  for (int i = 0; i < V; ++i) v[i] = sh[pad16(pos<LOGN2, LV>(S::NPH - 1, row_inv_lane<LOGN2, LV>(S::NPH - 1, t), i))];
   static_for_down<S::NPH - 1, 1>([&](auto P_) {
     constexpr int p = decltype(P_)::value;
+    const uint32_t tp = row_inv_lane<LOGN2, LV>(p, t);
     if constexpr (p < S::NPH - 1) {
+      const uint32_t tq = row_inv_lane<LOGN2, LV>(p + 1, t);
       wave_lds_sync();
 #pragma unroll
-      for (int i = 0; i < V; ++i) sh[pad16(pos<LOGN2, LV>(p + 1, t, i))] = v[i];
+      for (int i = 0; i < V; ++i) sh[pad16(pos<LOGN2, LV>(p + 1, tq, i))] = v[i];
       wave_lds_sync();
 #pragma unroll
-      for (int i = 0; i < V; ++i) v[i] = sh[pad16(pos<LOGN2, LV>(p, t, i))];
+      for (int i = 0; i < V; ++i) v[i] = sh[pad16(pos<LOGN2, LV>(p, tp, i))];
     }
-    gs_phase_cyc<A, S::rs(p), false>(a, v, cyc, S::s0(p), grp<LOGN2, LV>(p, t));
+    gs_phase_cyc<A, S::rs(p), false>(a, v, cyc, S::s0(p), grp<LOGN2, LV>(p, tp));
   });
   wave_lds_sync();
 #pragma unroll
-  for (int i = 0; i < V; ++i) sh[pad16(pos<LOGN2, LV>(1, t, i))] = v[i];
+  for (int i = 0; i < V; ++i) sh[pad16(pos<LOGN2, LV>(1, row_inv_lane<LOGN2, LV>(1, t), i))] = v[i];
   wave_lds_sync();
 #pragma unroll
   for (int i = 0; i < V; ++i) v[i] = a.mul(sh[pad16(pos<LOGN2, LV>(0, t, i))], bt[i & (ST::NF - 1)]);
