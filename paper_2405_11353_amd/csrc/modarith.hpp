@@ -40,7 +40,13 @@ struct ModInfo64 {
   uint64_t r1p;   // floor(r1 * 2^64 / q), Shoup companion of r1
   uint64_t n2q;   // 2^64 - 2q and 2^64 - 4q: the lazy reductions subtract 2q or
   uint64_t n4q;   // 4q by one 64-bit add of these (no borrow chain)
+  uint64_t cf;    // quotient estimate of the wide range's canonicalisation:
+                  // bits 0-31 c = floor(2^(s + 32 + e) / q), bits 32-39 s,
+                  // bits 40-47 e, where b = bit length of q and (s, e) =
+                  // (b - 28, 26) if b >= 28, else (0, b - 1)
 };
+
+static_assert(sizeof(ModInfo64) == 72, "the table generator writes 9 words per modulus");
 
 struct Tw64 {
   uint64_t w;   // twiddle in [0, q)
@@ -120,6 +126,12 @@ NTT_HD constexpr bool reduces_x(int rp, int j) {
 #define NTT_CT_FOLD 1
 #endif
 
+// 1: the wide range's canonicalisation subtracts an estimated multiple of q
+// (ModInfo64::cf) and then q at most once; 0: four conditional subtractions
+#ifndef NTT_CANON_EST
+#define NTT_CANON_EST 1
+#endif
+
 // WIDE (approximate quotient, every q < 2^60): forward values live in
 // [0, 16q) instead of [0, 8q). A CT butterfly whose x is below 12q needs no
 // reduction (x + T and x + 4q - T stay below 16q), and one that reduces
@@ -135,6 +147,7 @@ struct Arith64 {
   static constexpr bool kExact = EXACT;
   static constexpr bool kWide = WIDE;
   uint64_t q, L, nq, nL, n2q, n4q, R, nR;
+  uint32_t cc, cs, ce;  // the wide range's canonicalisation (ModInfo64::cf)
 
   NTT_HD void load(const ModInfo64& m) {
     q = m.q;
@@ -145,6 +158,9 @@ struct Arith64 {
     n4q = m.n4q;
     R = WIDE ? 8 * m.q : L;     // what a reducing CT butterfly subtracts from x
     nR = WIDE ? m.n8q : nL;
+    cc = lo32(m.cf);
+    cs = hi32(m.cf) & 0xffu;
+    ce = (hi32(m.cf) >> 8) & 0xffu;
   }
 
   // y * w mod q, result in [0, L) (L = 4q approx, 2q exact), any y < 2^64
@@ -210,6 +226,20 @@ struct Arith64 {
   }
   // canonical from [0, 2L) (forward; [0, 16q) with WIDE) or [0, L) (inverse)
   NTT_HD uint64_t canon_fwd(uint64_t x) const {
+    if (WIDE && NTT_CANON_EST) {
+      // k = floor(x / q) or one less: the top 32 bits of x (x >> s, below
+      // 2^32 for every x < 2^(b+4), which covers 16q) times the 32-bit
+      // reciprocal c. Truncating x and c each loses less than 2^-26 of a
+      // unit of x / q, so x - k q lies in [0, 2q) and one subtraction of q
+      // finishes; x - k q is formed as x + k (2^64 - q) mod 2^64.
+      const uint32_t k = umulhi32((uint32_t)(x >> cs), cc) >> ce;
+      const uint64_t lo = mad32(k, lo32(nq), x);
+      uint32_t hi = hi32(lo) + k * hi32(nq);
+#if defined(__HIP_DEVICE_COMPILE__)
+      asm("" : "+v"(hi));  // keep the 32-bit add, as in shoup_r
+#endif
+      return csub(((uint64_t)hi << 32) | lo32(lo), q, nq);
+    }
     if (WIDE) x = csub(x, R, nR);
     x = csub(x, L, nL);
     if (!EXACT) x = csub(x, 2 * q, n2q);

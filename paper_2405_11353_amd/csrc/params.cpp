@@ -121,7 +121,7 @@ static void put_entry(uint64_t w, const Recip& R, int word, void* out, size_t k)
 }
 
 size_t tw_entry_bytes(int word) { return word == 32 ? 8 : 16; }
-size_t modinfo_bytes(int word) { return word == 32 ? 32 : 64; }
+size_t modinfo_bytes(int word) { return word == 32 ? 32 : 72; }
 
 void twiddles(uint64_t q, uint64_t root, uint32_t logN, int word, bool inverse, void* out, bool cyclic) {
   const uint32_t N = 1u << logN;
@@ -181,7 +181,7 @@ void modinfo(uint64_t q, int word, void* out) {
     m[4] = (uint32_t)(((uint64_t)r1 << 32) / q);
     memcpy(out, m, sizeof m);
   } else {
-    uint64_t m[8] = {0};
+    uint64_t m[9] = {0};
     uint64_t inv = q;  // Newton iteration for q^-1 mod 2^64
     for (int i = 0; i < 6; ++i) inv *= 2u - q * inv;
     const uint64_t r1 = (uint64_t)(((u128)1 << 64) % q);
@@ -193,6 +193,11 @@ void modinfo(uint64_t q, int word, void* out) {
     m[5] = (uint64_t)(((u128)r1 << 64) / q);
     m[6] = 0 - 2 * q;
     m[7] = 0 - 4 * q;
+    // wide-range canonicalisation: floor(x / q) from x >> s times c >> e
+    const int b = 64 - __builtin_clzll(q);
+    const int s = b >= 28 ? b - 28 : 0, e = b >= 28 ? 26 : b - 1;
+    const uint64_t c = (uint64_t)(((u128)1 << (s + 32 + e)) / q);  // < 2^32
+    m[8] = c | ((uint64_t)s << 32) | ((uint64_t)e << 40);
     memcpy(out, m, sizeof m);
   }
 }

@@ -110,6 +110,39 @@ static int test64(uint64_t q) {
 // skipping one needs x below 12q and leaves them below 16q. Then whole
 // chains of stages under the two reduction patterns, from inputs at the top
 // of their ranges, against the 128-bit value of each output.
+// the canonicalisation's reciprocal word, from its definition: b = bit
+// length of q, (s, e) = (b - 28, 26) for b >= 28 else (0, b - 1),
+// c = floor(2^(s + 32 + e) / q)
+static uint64_t canon_word(uint64_t q) {
+  int b = 0;
+  while (b < 64 && (q >> b)) ++b;
+  const int s = b >= 28 ? b - 28 : 0, e = b >= 28 ? 26 : b - 1;
+  const u128 c = ((u128)1 << (s + 32 + e)) / q;
+  if (c >> 32) return 0;  // fails the checks below
+  return (uint64_t)c | ((uint64_t)s << 32) | ((uint64_t)e << 40);
+}
+
+// the wide range's canonicalisation alone, for moduli of every size class
+// around the estimate's switch at 28 bits: x below 16q (the wide range) and
+// up to 2^(b+4) (the estimate's own limit)
+static int test_canon(uint64_t q) {
+  ModInfo64 m{};
+  m.q = q;
+  m.nq = 0 - q;
+  m.n8q = 0 - 8 * q;
+  m.cf = canon_word(q);
+  Arith64<false, true> W;
+  W.load(m);
+  int b = 0;
+  while (q >> b) ++b;
+  const uint64_t top = b + 4 >= 64 ? ~0ull : (1ull << (b + 4)) - 1;
+  for (int it = 0; it < 100000; ++it) {
+    const uint64_t x = it == 0 ? 16 * q - 1 : it == 1 ? top : it & 1 ? rnd() % (16 * q) : rnd() % top;
+    CHECK(W.canon_fwd(x) == x % q, "canonical q=%llu x=%llu", (unsigned long long)q, (unsigned long long)x);
+  }
+  return 0;
+}
+
 static int test_wide(uint64_t q) {
   ModInfo64 m{};
   m.q = q;
@@ -117,8 +150,17 @@ static int test_wide(uint64_t q) {
   m.n2q = 0 - 2 * q;
   m.n4q = 0 - 4 * q;
   m.n8q = 0 - 8 * q;
+  m.cf = canon_word(q);
   Arith64<false, true> W;
   W.load(m);
+  // canonicalisation at every multiple of q in the range and its neighbours
+  for (uint64_t k = 0; k <= 16; ++k) {
+    for (int d = -2; d <= 2; ++d) {
+      const uint64_t x = k * q + (uint64_t)(int64_t)d;
+      if ((k == 0 && d < 0) || (k == 16 && d >= 0)) continue;
+      CHECK(W.canon_fwd(x) == x % q, "wide canonical at %llu q %+d", (unsigned long long)k, d);
+    }
+  }
   for (int it = 0; it < 200000; ++it) {
     const uint64_t w = rnd() % q;
     const Tw64 t{w, (uint64_t)(((u128)w << 64) / q)};
@@ -240,6 +282,14 @@ int main() {
                          12289ull};
   for (uint64_t q : qw)
     if (test_wide(q)) return 1;
+  // largest and smallest primes of bit lengths 2 .. 60
+  const uint64_t qc[] = {3ull, 7ull, 5ull, 509ull, 257ull, 131071ull, 65537ull, 134217689ull, 67108879ull,
+                         268435399ull, 134217757ull, 536870909ull, 268435459ull, 2147483647ull, 1073741827ull,
+                         4294967291ull, 2147483659ull, 8589934583ull, 4294967311ull, 35184372088777ull,
+                         17592186044423ull, 576460752303423433ull, 288230376151711813ull, 1152921504606846883ull,
+                         576460752303423619ull};
+  for (uint64_t q : qc)
+    if (test_canon(q)) return 1;
   const uint32_t q32[] = {998244353u, 469762049u, 167772161u, 1073479681u /* < 2^30 */, 12289u};
   for (uint32_t q : q32)
     if (test32(q)) return 1;

@@ -43,13 +43,23 @@ int main() {
   for (const P& pr : primes) {
     const uint64_t q = pr.q;
     if (pr.word == 64) {
-      // per-limb constants: q, -q, q^-1, 2^64 mod q and its companion, -2q, -4q (all mod 2^64)
-      uint64_t m[8];
+      // per-limb constants: q, -8q, -q, q^-1, 2^64 mod q and its companion, -2q, -4q (all mod
+      // 2^64), and the canonicalisation's reciprocal word
+      uint64_t m[9];
+      expect(nttp::modinfo_bytes(64) == sizeof m, "modinfo size", q, 0);
       nttp::modinfo(q, 64, m);
       const uint64_t r1 = (uint64_t)(((u128)1 << 64) % q);
       expect(m[0] == q && m[2] + q == 0 && m[3] * q == 1 && m[4] == r1, "modinfo", q, 0);
+      expect(m[1] + 8 * q == 0, "modinfo -8q", q, 1);
       expect(m[5] == (uint64_t)(((u128)r1 << 64) / q), "modinfo r1 companion", q, 5);
       expect(m[6] + 2 * q == 0 && m[7] + 4 * q == 0, "modinfo -2q, -4q", q, 6);
+      // c q <= 2^(s+32+e) < (c+1) q with c < 2^32; bit length b of q: s = b - 28, e = 26
+      const uint64_t c = m[8] & 0xffffffffu, sh = (m[8] >> 32) & 0xff, e = (m[8] >> 40) & 0xff;
+      int b = 0;
+      while (q >> b) ++b;
+      const u128 p2 = (u128)1 << (sh + 32 + e);
+      expect((int)sh == b - 28 && e == 26 && (m[8] >> 48) == 0, "modinfo canon shifts", q, 8);
+      expect((u128)c * q <= p2 && p2 < (u128)(c + 1) * q, "modinfo canon reciprocal", q, 8);
     }
     for (uint32_t logN = 12; logN <= 16; logN += 2) {
       const uint32_t N = 1u << logN;
