@@ -263,11 +263,14 @@ ntt_plan* ntt_plan_create_ex(uint32_t N, const uint64_t* moduli, uint32_t L, uin
 
   const size_t tw_bytes = (size_t)N * nttp::tw_entry_bytes(word);
   const size_t mod_bytes = nttp::modinfo_bytes(word);
-  std::vector<unsigned char> fwd(tw_bytes * L), inv(tw_bytes * L), mod(mod_bytes * L);
+  // d_mod holds the limbs' constants, then their scaled last-stage pairs
+  const size_t pair_bytes = 2 * nttp::tw_entry_bytes(word);
+  std::vector<unsigned char> fwd(tw_bytes * L), inv(tw_bytes * L), mod((mod_bytes + pair_bytes) * L);
   ntti::for_limbs(L, [&](uint32_t l) {
     nttp::twiddles(moduli[l], roots[l], p->logN, word, false, fwd.data() + l * tw_bytes, cyclic);
     nttp::twiddles(moduli[l], roots[l], p->logN, word, true, inv.data() + l * tw_bytes, cyclic);
     nttp::modinfo(moduli[l], word, mod.data() + l * mod_bytes);
+    nttp::mont_scale(moduli[l], word, inv.data() + l * tw_bytes, mod.data() + L * mod_bytes + l * pair_bytes);
   });
   if (ntti::dev_malloc(&p->d_tw_fwd, fwd.size()) != hipSuccess || ntti::dev_malloc(&p->d_tw_inv, inv.size()) != hipSuccess ||
       ntti::dev_malloc(&p->d_mod, mod.size()) != hipSuccess) {
@@ -275,6 +278,7 @@ ntt_plan* ntt_plan_create_ex(uint32_t N, const uint64_t* moduli, uint32_t L, uin
     fail(NTT_ERR_NOMEM);
     return nullptr;
   }
+  p->d_mscale = (unsigned char*)p->d_mod + L * mod_bytes;
   if (hipMemcpy(p->d_tw_fwd, fwd.data(), fwd.size(), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(p->d_tw_inv, inv.data(), inv.size(), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(p->d_mod, mod.data(), mod.size(), hipMemcpyHostToDevice) != hipSuccess) {
@@ -653,6 +657,7 @@ static int run_mul_inverse(const ntt_plan* pc, const void* a, const void* b, voi
   L.data = c;
   L.mul_a = a;
   L.mul_b = b;
+  L.mul_scale = p->d_mscale;
   L.tw = p->d_tw_inv;
   L.mods = p->d_mod;
   L.L = p->L;
@@ -743,6 +748,7 @@ static int run_polymul(const ntt_plan* pc, const void* a, const void* b, void* c
                                       p->L, batch, s)) != hipSuccess)
       return e == hipErrorNotSupported ? NTT_ERR_UNSUPPORTED : NTT_ERR_HIP;
     L.tw = p->d_tw_inv;
+    L.mul_scale = p->d_mscale;  // the fused row kernel's products are Montgomery products
     L.stage_mask = 2;
     L.data = c;
     L.scratch = sa;

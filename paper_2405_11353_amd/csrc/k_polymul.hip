@@ -113,7 +113,12 @@ k_row_polymul(typename A::word* sa, const typename A::word* __restrict__ sb,
   asm volatile("" : "+v"(twf_b));
   forward(vb, twf_b);
 #pragma unroll
-  for (int i = 0; i < V; ++i) va[i] = mulmod_general(va[i], a.canon_fwd(vb[i]), m);
+  for (int i = 0; i < V; ++i) {
+    // direct mode: Montgomery product, the factor 2^-w multiplied back in by
+    // the inverse column pass; descriptor mode (no scaled pair there): exact
+    if constexpr (IND) va[i] = mulmod_general(va[i], a.canon_fwd(vb[i]), m);
+    else va[i] = mulmod_mont(va[i], a.canon_fwd(vb[i]), m);
+  }
   // the wave's rows switch to the inverse table's first-phase twiddles; the
   // inverse phases' exchanges order the copy before their use
   wave_lds_sync();

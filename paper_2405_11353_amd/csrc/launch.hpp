@@ -42,6 +42,10 @@ struct Launch {
   int lv_col = 0;           // PATH_TWO, 64-bit: values per thread (log2, 3 or 4) of the column passes; 0 = default
   const void* mul_a = nullptr;  // PATH_TWO inverse: if set, transform mul_a * mul_b into data
   const void* mul_b = nullptr;
+  // PATH_TWO inverse column pass: [L][2] twiddle pairs that replace table
+  // slots 0 and 1 (N^-1 times 2^w, w the word size), set when the row pass's
+  // input is a Montgomery product (the fused product paths); else null
+  const void* mul_scale = nullptr;
   // PATH_TWO: if set, the row pass is the twisted one (k_row_tw) with these
   // tables of the direction being run: [L][N] twist, [L][N2] cyclic twiddles
   const void* twist = nullptr;

@@ -251,10 +251,12 @@ struct Arith64 {
   }
 };
 
-// General product x*y mod q for the pointwise kernel (neither operand known in
-// advance): Montgomery reduction of the 128-bit product gives x*y*2^-64 in
-// (-q, q), then a Shoup product by 2^64 mod q restores the factor.
-NTT_HD uint64_t mulmod_general(uint64_t x, uint64_t y, const ModInfo64& m) {
+// Montgomery product x*y*2^-64 mod q in [0, q), for any x*y < q*2^64 (so
+// that the 128-bit product's high word is below q): u = lo64(x*y) * q^-1 makes
+// x*y - u*q divisible by 2^64, and the quotient, hi64(x*y) - hi64(u*q), lies in
+// (-q, q). The fused product + inverse takes this and leaves the factor 2^-64
+// to the last inverse stage, whose N^-1 twiddles then carry 2^64 as well.
+NTT_HD uint64_t mulmod_mont(uint64_t x, uint64_t y, const ModInfo64& m) {
   uint32_t x0 = lo32(x), x1 = hi32(x), y0 = lo32(y), y1 = hi32(y);
   // 128-bit product t = th:tl
   uint64_t p00 = mad32(x0, y0, 0);
@@ -276,7 +278,14 @@ NTT_HD uint64_t mulmod_general(uint64_t x, uint64_t y, const ModInfo64& m) {
     uq_hi = s11;
   }
   uint64_t r = th - uq_hi;            // in (-q, q) as a signed value
-  r = (th < uq_hi) ? r + m.q : r;     // [0, q)
+  return (th < uq_hi) ? r + m.q : r;  // [0, q)
+}
+
+// General product x*y mod q for the pointwise kernel (neither operand known in
+// advance): the Montgomery product above, then a Shoup product by 2^64 mod q
+// restores the factor.
+NTT_HD uint64_t mulmod_general(uint64_t x, uint64_t y, const ModInfo64& m) {
+  const uint64_t r = mulmod_mont(x, y, m);
   // times 2^64 mod q (Shoup, exact quotient): [0, 2q) then canonical
   uint64_t Q = shoup_q_exact(r, m.r1p);
   uint64_t z = shoup_r(r, m.r1, Q, m.nq);
@@ -346,13 +355,18 @@ struct Arith32 {
   NTT_HD uint32_t canon_inv(uint32_t x) const { return csub(x, q); }
 };
 
-NTT_HD uint32_t mulmod_general(uint32_t x, uint32_t y, const ModInfo32& m) {
+// x*y*2^-32 mod q in [0, q) for x*y < q*2^32 (Montgomery, as at 64 bits)
+NTT_HD uint32_t mulmod_mont(uint32_t x, uint32_t y, const ModInfo32& m) {
   uint64_t t = (uint64_t)x * y;
   uint32_t u = (uint32_t)t * m.qinv;                 // t - u q = 0 mod 2^32
   uint32_t uq_hi = umulhi32(u, m.q);
   uint32_t th = (uint32_t)(t >> 32);
   uint32_t r = th - uq_hi;
-  r = (th < uq_hi) ? r + m.q : r;                    // x y 2^-32 mod q
+  return (th < uq_hi) ? r + m.q : r;                 // x y 2^-32 mod q
+}
+
+NTT_HD uint32_t mulmod_general(uint32_t x, uint32_t y, const ModInfo32& m) {
+  const uint32_t r = mulmod_mont(x, y, m);
   uint32_t Q = umulhi32(r, m.r1p);
   uint32_t z = r * m.r1 - Q * m.q;                   // [0, 2q)
   return z >= m.q ? z - m.q : z;

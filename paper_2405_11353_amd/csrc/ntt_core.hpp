@@ -123,14 +123,17 @@ __device__ __forceinline__ void ct_phase(const A& a, typename A::word (&v)[V],
 }
 
 // Inverse: the same pairs, stages in reverse order. HAS0: this phase contains
-// global stage 0, whose two outputs are both scaled (tables slots 0 and 1).
+// global stage 0, whose two outputs are both scaled (tables slots 0 and 1, or
+// the pair at t01 when given).
 template <class A, int RS, bool HAS0, int V>
 __device__ __forceinline__ void gs_phase(const A& a, typename A::word (&v)[V],
-                                         const typename A::tw_t* __restrict__ tw, uint32_t S0, uint32_t Hg) {
+                                         const typename A::tw_t* __restrict__ tw, uint32_t S0, uint32_t Hg,
+                                         const typename A::tw_t* t01 = nullptr) {
 #pragma unroll
   for (int k = RS - 1; k >= 0; --k) {
     if (HAS0 && k == 0) {
-      const typename A::tw_t w0 = tw[0], w1 = tw[1];
+      const typename A::tw_t* p01 = t01 ? t01 : tw;
+      const typename A::tw_t w0 = p01[0], w1 = p01[1];
 #pragma unroll
       for (int m = 0; m < V / 2; ++m) a.gs_last(v[m], v[m + V / 2], w0, w1);
     } else {
@@ -291,12 +294,16 @@ __device__ __forceinline__ void st_data(T* p, T v) {
 // NC columns per workgroup, N1/V threads per column (V = 2^LV values each);
 // columns are adjacent so each row segment read or written is NC words.
 // Forward: global stages [0, logN1), out-of-place allowed (in == out is fine).
-// Inverse: global stages [logN1-1 .. 0] with the N^-1 fold, canonical output.
+// Inverse: global stages [logN1-1 .. 0] with the N^-1 fold, canonical output;
+// with scale (direct mode), limb l's last stage takes the pair scale[2l],
+// scale[2l + 1] in place of table slots 0 and 1 (they also carry the
+// Montgomery factor that the fused product left in its input).
 template <class A, int LOGN1, int NC, bool FWD, bool IND = false, int LV = 4>
 __global__ void __launch_bounds__(NC << (LOGN1 - LV))
 k_col(const typename A::word* in, typename A::word* out, const typename A::tw_t* __restrict__ tw_all,
       const typename ModOf<A>::type* __restrict__ mods, uint32_t L, uint32_t logN, uint32_t items,
-      const ItemDesc* __restrict__ desc = nullptr, int io = 0) {
+      const ItemDesc* __restrict__ desc = nullptr, int io = 0,
+      const typename A::tw_t* __restrict__ scale = nullptr) {
   using W = typename A::word;
   using TW = typename A::tw_t;
   using M = typename ModOf<A>::type;
@@ -319,6 +326,7 @@ k_col(const typename A::word* in, typename A::word* out, const typename A::tw_t*
   // thread of the workgroup reads the same slots, which the compiler turns into
   // scalar loads; the forward pass reads the later phases' slots from LDS.
   const TW* tw;
+  const TW* t01 = nullptr;
   const W* src;
   W* dst;
   const size_t off = tile * NC + c;
@@ -332,6 +340,7 @@ k_col(const typename A::word* in, typename A::word* out, const typename A::tw_t*
     const uint32_t l = item % L;
     a.load(mods[l]);
     tw = tw_all + ((size_t)l << logN);
+    if (!FWD && scale) t01 = scale + 2 * l;
     const size_t base = ((size_t)item << logN) + off;
     src = in + base;
     dst = out + base;
@@ -372,7 +381,7 @@ k_col(const typename A::word* in, typename A::word* out, const typename A::tw_t*
 #pragma unroll
         for (int i = 0; i < V; ++i) v[i] = lds[pos<LOGN1, LV>(p, t, i) * LD + c];
       }
-      gs_phase<A, S::rs(p), p == 0>(a, v, tw, S::s0(p), p == 0 ? 0u : grp<LOGN1, LV>(p, t));
+      gs_phase<A, S::rs(p), p == 0>(a, v, tw, S::s0(p), p == 0 ? 0u : grp<LOGN1, LV>(p, t), t01);
     });
 #pragma unroll
     for (int i = 0; i < V; ++i) st_data<NT_ST_INV_OUT>(dst + (size_t)(i * TPC + t) * N2, a.canon_inv(v[i]));
@@ -453,8 +462,10 @@ __device__ __forceinline__ void stage_first_phase(TW (*tw0)[17], const TW* tw, u
 // element (r, c) to brv(c) * N1 + brv(r) with rows r = brv(k1), k1 in the tile.
 // Inverse: reads that layout (or rows in place), runs the row stages
 // backwards and writes rows in lazy range for the column pass.
-// MULIN (inverse only): the input is in * in2 elementwise mod q (the pointwise
-// product fused into the load), read from two buffers.
+// MULIN (inverse only, direct mode): the input is in * in2 * 2^-w elementwise
+// mod q (the pointwise product fused into the load as a Montgomery product,
+// w the word size), read from two buffers; the column pass that follows
+// multiplies the factor 2^w back in with its scaled last-stage pair.
 template <class A, int LOGN2, bool FWD, bool NATURAL, bool MULIN = false, bool IND = false, int LV = 4>
 __global__ void __launch_bounds__(16 << (LOGN2 - LV))
 k_row(const typename A::word* in, typename A::word* out, const typename A::tw_t* __restrict__ tw_all,
@@ -468,6 +479,7 @@ k_row(const typename A::word* in, typename A::word* out, const typename A::tw_t*
   constexpr int V = 1 << LV;
   constexpr uint32_t N2 = 1u << LOGN2, TPR = N2 / V, RSTR = N2 + N2 / 16 + 1;
   static_assert(TPR <= 64, "a row must fit in one wavefront");
+  static_assert(!(MULIN && (FWD || IND)), "the fused product runs with the direct-mode inverse");
   __shared__ W lds[16 * RSTR];
   __shared__ TW tw0[16][17];  // first-phase twiddles of the 16 rows
   const uint32_t logN1 = logN - LOGN2, N1 = 1u << logN1;
@@ -568,7 +580,7 @@ k_row(const typename A::word* in, typename A::word* out, const typename A::tw_t*
 #pragma unroll
       for (int j = 0; j < V; ++j) {
         W val = xa[j];
-        if constexpr (MULIN) val = mulmod_general(val, xb[j], *mi);
+        if constexpr (MULIN) val = mulmod_mont(val, xb[j], *mi);
         lds[rr * RSTR + pad16(cg + TPR * j)] = val;
       }
       __syncthreads();
@@ -585,7 +597,7 @@ k_row(const typename A::word* in, typename A::word* out, const typename A::tw_t*
 #pragma unroll
       for (int i = 0; i < V; ++i) {
         W val = xa[i];
-        if constexpr (MULIN) val = mulmod_general(val, xb[i], *mi);
+        if constexpr (MULIN) val = mulmod_mont(val, xb[i], *mi);
         sh[pad16(i * TPR + t)] = val;
       }
       wave_lds_sync();
@@ -780,7 +792,7 @@ k_row_tw(const typename A::word* in, typename A::word* out, const typename A::tw
 #pragma unroll
       for (int j = 0; j < V; ++j) {
         W val = xa[j];
-        if constexpr (MULIN) val = mulmod_general(val, xb[j], *mi);
+        if constexpr (MULIN) val = mulmod_mont(val, xb[j], *mi);
         lds[rr * RSTR + pad16(cg + TPR * j)] = val;
       }
       __syncthreads();
@@ -796,7 +808,7 @@ k_row_tw(const typename A::word* in, typename A::word* out, const typename A::tw
 #pragma unroll
       for (int i = 0; i < V; ++i) {
         W val = xa[i];
-        if constexpr (MULIN) val = mulmod_general(val, xb[i], *mi);
+        if constexpr (MULIN) val = mulmod_mont(val, xb[i], *mi);
         sh[pad16(i * TPR + t)] = val;
       }
       __syncthreads();
@@ -968,8 +980,8 @@ k_row_st(const typename A::word* in, typename A::word* out, const typename A::tw
   }
 }
 
-// Inverse: the spectrum rows (or with MULIN the product of two) through the
-// cyclic inverse phases, the factors beta_r^-(...), and the merged inverse
+// Inverse: the spectrum rows (or with MULIN the Montgomery product of two, as
+// in k_row) through the cyclic inverse phases, the factors beta_r^-(...), and the merged inverse
 // first phase; rows written in place, in the lazy range the column pass takes.
 // Lane map of the inverse row pass's phases. A phase whose groups hold 8
 // offsets (stride 2^3) with 8 values per thread places, under the identity
@@ -1048,7 +1060,7 @@ k_row_st_inv(const typename A::word* in, typename A::word* out, const typename A
 #pragma unroll
     for (int j = 0; j < V; ++j) {
       W val = xa[j];
-      if constexpr (MULIN) val = mulmod_general(val, xb[j], *mi);
+      if constexpr (MULIN) val = mulmod_mont(val, xb[j], *mi);
       lds[rr * RSTR + pad16(cg + TPR * j)] = val;
     }
   } else {
@@ -1065,7 +1077,7 @@ k_row_st_inv(const typename A::word* in, typename A::word* out, const typename A
 #pragma unroll
     for (int i = 0; i < V; ++i) {
       W val = xa[i];
-      if constexpr (MULIN) val = mulmod_general(val, xb[i], *mi);
+      if constexpr (MULIN) val = mulmod_mont(val, xb[i], *mi);
       sh[pad16(i * TPR + t)] = val;
     }
   }

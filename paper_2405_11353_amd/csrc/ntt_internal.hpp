@@ -25,6 +25,7 @@ struct ntt_plan {
   void* d_tw_fwd = nullptr;
   void* d_tw_inv = nullptr;
   void* d_mod = nullptr;
+  void* d_mscale = nullptr;  // inside d_mod's allocation: [L][2] scaled last-stage pairs
   bool auto_variant = true;  // choose per call from the tuning table / defaults
   int path = NTT_PATH_LDS;
   int logN1 = 0;

@@ -165,6 +165,15 @@ void twist(uint64_t q, uint64_t root, uint32_t logN, uint32_t logN1, int word, b
   }
 }
 
+void mont_scale(uint64_t q, int word, const void* inv_table, void* out) {
+  const Recip R = recip(q);
+  const uint64_t r = word == 32 ? (1ull << 32) % q : (uint64_t)(((u128)1 << 64) % q);
+  for (size_t k = 0; k < 2; ++k) {
+    const uint64_t w = word == 32 ? ((const uint32_t*)inv_table)[2 * k] : ((const uint64_t*)inv_table)[2 * k];
+    put_entry(mulmod(w, r, q), R, word, out, k);
+  }
+}
+
 uint64_t row_root(uint64_t q, uint64_t root, uint32_t logN1, bool cyclic) {
   return powmod(root, (cyclic ? 1ull : 2ull) << logN1, q);
 }

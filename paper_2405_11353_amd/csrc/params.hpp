@@ -43,6 +43,11 @@ void twist(uint64_t q, uint64_t root, uint32_t logN, uint32_t logN1, int word, b
 uint64_t row_root(uint64_t q, uint64_t root, uint32_t logN1, bool cyclic);
 // per-limb constants in the layout of nttk::ModInfo64 / ModInfo32
 void modinfo(uint64_t q, int word, void* out);
+// The fused product's last inverse stage: slots 0 and 1 of an inverse table
+// (N^-1, and the first stage's twiddle times N^-1) times 2^word mod q, as two
+// table entries with their companions. The fused product's Montgomery
+// products leave a factor 2^-word that these multiply back out.
+void mont_scale(uint64_t q, int word, const void* inv_table, void* out);
 size_t tw_entry_bytes(int word);
 size_t modinfo_bytes(int word);
 

@@ -101,6 +101,10 @@ static int test64(uint64_t q) {
     // general product
     const uint64_t u = rnd() % q, v = it < 9 ? ws_edge[it] % q : rnd() % q;
     CHECK(mulmod_general(u, v, m) == mulm(u, v, q), "general product");
+    // Montgomery product: x y 2^-64, for x y < q 2^64 (here x lazy below 8q)
+    const uint64_t u8 = it < 9 ? 8 * q - 1 - it : rnd() % (8 * q);
+    const uint64_t mt = mulmod_mont(u8, v, m);
+    CHECK(mt < q && mulm(mt, m.r1, q) == mulm(u8 % q, v, q), "Montgomery product");
   }
   return 0;
 }
@@ -267,6 +271,8 @@ static int test32(uint32_t q) {
     CHECK(A.canon_fwd(x4) == x4 % q && A.canon_inv(x2) == x2 % q, "32-bit canonical");
     const uint32_t u = (uint32_t)(rnd() % q), v = (uint32_t)(rnd() % q);
     CHECK(mulmod_general(u, v, m) == (uint32_t)((uint64_t)u * v % q), "32-bit general product");
+    const uint32_t mt = mulmod_mont(u, v, m);
+    CHECK(mt < q && (uint64_t)mt * m.r1 % q == (uint64_t)u * v % q, "32-bit Montgomery product");
   }
   return 0;
 }

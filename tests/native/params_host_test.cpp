@@ -84,6 +84,14 @@ int main() {
         check_entry(iv.data(), pr.word, 0, ninv, q, "N^-1 slot 0");
         const uint64_t e1 = cyclic ? 0 : brv(1, logN);
         check_entry(iv.data(), pr.word, 1, nttp::mulmod(inv(nttp::powmod(root, e1, q), q), ninv, q), q, "slot 1");
+        // the fused product's pair: slots 0 and 1 times 2^word mod q
+        std::vector<unsigned char> ms(2 * eb);
+        nttp::mont_scale(q, pr.word, iv.data(), ms.data());
+        const uint64_t rw = (uint64_t)(((u128)1 << pr.word) % q);
+        check_entry(ms.data(), pr.word, 0, nttp::mulmod(ninv, rw, q), q, "scaled slot 0");
+        check_entry(ms.data(), pr.word, 1,
+                    nttp::mulmod(nttp::mulmod(inv(nttp::powmod(root, e1, q), q), ninv, q), rw, q), q,
+                    "scaled slot 1");
         for (uint32_t logN1 = 6; logN1 + 6 <= logN && logN1 <= 9; ++logN1) {
           const uint32_t N1 = 1u << logN1, N2 = N >> logN1;
           std::vector<unsigned char> tf(N * eb), ti(N * eb);
