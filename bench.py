@@ -30,6 +30,7 @@ HBM_PEAK_GBS = 8000.0                 # MI355X HBM3E
 INT32_MUL_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # 39.3: one int32 multiply per lane per clock
 MULS_PER_SHOUP = 9                    # 32x32 products in one 64-bit Shoup product (approx quotient)
 MULS_PER_GENERAL = 21                 # 32x32 products in one general 64-bit modular product
+MULS_PER_MONT = 11                    # 32x32 products in one 64-bit Montgomery product (the fused product)
 
 
 def log(*a):
@@ -1468,7 +1469,7 @@ def main():
                                        stages=logn2, extra_muls=0, words_in=0, words_out=1, tw_bytes=tw_row)
         kernels["inv_row_pass_mul"] = dict(fn=lambda b: plan.pointwise_inverse_stage(b[:2], b[2:], b[:2], 0, batch=2),
                                            items=2 * L, stages=logn2, extra_muls=N, words_in=2, words_out=0,
-                                           general_muls=N, tw_bytes=tw_twist)
+                                           mont_muls=N, tw_bytes=tw_twist)
         kernels["inv_col_pass"] = dict(fn=lambda b: plan.inverse_stage(b[:2], 1, batch=2), items=2 * L,
                                        stages=logn1, extra_muls=N // 2, words_in=0, words_out=1, tw_bytes=tw_col)
     else:
@@ -1479,7 +1480,7 @@ def main():
         us = time_kernel(k["fn"], args.kernel_reps)
         bytes_alg = k["items"] * N * 8 * (k["words_in"] + k["words_out"]) + k.get("tw_bytes", 0)
         muls = k["items"] * (((N // 2) * k["stages"] + k["extra_muls"]) * MULS_PER_SHOUP
-                             + k.get("general_muls", 0) * MULS_PER_GENERAL)
+                             + k.get("general_muls", 0) * MULS_PER_GENERAL + k.get("mont_muls", 0) * MULS_PER_MONT)
         gbs = bytes_alg / (us * 1e-6) / 1e9
         tops = muls / (us * 1e-6) / 1e12
         traffic = counter_traffic(name)
