@@ -158,7 +158,10 @@ int ntt_polymul(const ntt_plan* plan, const void* d_a, const void* d_b, void* d_
  * NTT_ERR_UNSUPPORTED unless the plan's variant is NTT_PATH_FOURSTEP. */
 int ntt_forward_stage(const ntt_plan* plan, void* d_data, uint32_t batch, int stage, void* stream);
 /* Same for ntt_pointwise_mul_inverse: stage 0 is the fused product + first
- * inverse kernel (d_a, d_b -> scratch), stage 1 the second (scratch -> d_c). */
+ * inverse kernel (d_a, d_b -> scratch), stage 1 the second (scratch -> d_c).
+ * The intermediate is the row transform of the Montgomery product
+ * a*b*2^-w mod q (w = 64, or 32 with NTT_WORD32); stage 1 multiplies 2^w back
+ * in with its last stage, so the two stages together equal the fused call. */
 int ntt_pointwise_mul_inverse_stage(const ntt_plan* plan, const void* d_a, const void* d_b, void* d_c,
                                     uint32_t batch, int stage, void* stream);
 int ntt_inverse_stage(const ntt_plan* plan, void* d_data, uint32_t batch, int stage, void* stream);
