@@ -105,6 +105,7 @@ static int test64(uint64_t q) {
     const uint64_t u8 = it < 9 ? 8 * q - 1 - it : rnd() % (8 * q);
     const uint64_t mt = mulmod_mont(u8, v, m);
     CHECK(mt < q && mulm(mt, m.r1, q) == mulm(u8 % q, v, q), "Montgomery product");
+    CHECK(mulmod_general(u8, v, m) == mulm(u8 % q, v, q), "general product, lazy first operand");
   }
   return 0;
 }

@@ -8,6 +8,7 @@ import seeded_inputs as si
 
 P18 = si.ntt_primes(60, 18, 8)
 FAKE = 0x10000  # addresses are never dereferenced in simulate mode
+MODREC = 72     # bytes of one 64-bit modulus record, stored with each (q, N) pair's tables
 
 
 @pytest.fixture(scope="module")
@@ -52,7 +53,7 @@ def test_budget_admission_and_rejection(ntt):
     poly = L * N * 8
     # a POLYMUL at N = 2^16 holds the column-pass outputs of both operands,
     # beside the twiddle tables of its L (q, N) pairs
-    budget = 2 * poly + L * (32 * N + 64) + (64 << 10)
+    budget = 2 * poly + L * (32 * N + MODREC) + (64 << 10)
     with sim(ntt, hbm_budget_bytes=budget, n_streams=4, simulate_ns_per_item=50000.0) as s:
         with pytest.raises(ntt.NttError) as e:
             s.submit(ntt.NTT_REQ_POLYMUL, N, P18[:L + 1], FAKE, FAKE, b=FAKE)   # > budget
@@ -156,11 +157,11 @@ def test_undersized_buffers_are_refused_before_submit(ntt):
 
 
 def test_twiddle_tables_count_against_the_budget(ntt):
-    """A job's tables (32N + 64 bytes per (q, N)) and its working memory must
+    """A job's tables (32N + 72 bytes per (q, N)) and its working memory must
     fit the budget together; tables stay resident across jobs and are
     evicted, least recently used first, when space is needed."""
     N = 1 << 17
-    table = 32 * N + 64
+    table = 32 * N + MODREC
     ws = 8 * N                              # four-step intermediate of one limb
     with sim(ntt, hbm_budget_bytes=ws + table - 1, n_streams=1) as s:
         with pytest.raises(ntt.NttError):   # fits the arena only without its table
