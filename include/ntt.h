@@ -335,7 +335,7 @@ void ntt_batch_destroy(ntt_batch* batch);
  * arrival order whenever one of n_streams device streams is free and the
  * job's working memory (an operand copy for POLYMUL, four-step scratch for
  * N >= 2^14) and the twiddle tables of its (q, N) pairs that are not resident
- * yet (32N + 64 bytes each) fit in the server's hbm_budget_bytes arena, after
+ * yet (32N + 72 bytes each) fit in the server's hbm_budget_bytes arena, after
  * evicting resident tables no admitted job uses (least recently used first);
  * a job that cannot fit alone is refused with NTT_ERR_BUDGET; jobs admitted
  * together run as one batch (descriptor table + one launch per (phase, N)),
