@@ -98,10 +98,13 @@ k_row_polymul(typename A::word* sa, const typename A::word* __restrict__ sb,
       }
     });
   };
-  // one operand at a time, so that only one row's working set is live. The
-  // product needs a * b below q * 2^w: b's transform is made canonical, and a's
-  // stays in its lazy range [0, 8q) (8q * q < q * 2^64)
+  // one operand at a time, so that only one row's working set is live: a's
+  // transform is made canonical before b's row is loaded (the product needs
+  // a * b below q * 2^w, which a lazy a below 8q would also meet, but leaving
+  // a lazy measured slower: the loop gives b's loads their latency)
   forward(va, twf);
+#pragma unroll
+  for (int i = 0; i < V; ++i) va[i] = a.canon_fwd(va[i]);
 #pragma unroll
   for (int i = 0; i < V; ++i) vb[i] = rowb[i * TPR + t];
   // b's transform reads the same twiddles; an opaque copy of the table
