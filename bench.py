@@ -520,8 +520,8 @@ def bench_batched(ntt, si, torch, reps=10):
     inv = ntt.Batch([(j.N, primes[:j.L], ntt.NTT_JOB_INVERSE, t) for j, t in zip(jobs, tensors)])
     eager = ntt.Batch([(j.N, primes[:j.L], ntt.NTT_JOB_FORWARD, t) for j, t in zip(jobs, tensors)],
                       flags=ntt.NTT_BATCH_NO_GRAPH)
-    branches = ntt.Batch([(j.N, primes[:j.L], ntt.NTT_JOB_FORWARD, t) for j, t in zip(jobs, tensors)],
-                         flags=ntt.NTT_BATCH_BRANCHES)
+    serial = ntt.Batch([(j.N, primes[:j.L], ntt.NTT_JOB_FORWARD, t) for j, t in zip(jobs, tensors)],
+                       flags=ntt.NTT_BATCH_SERIAL)
     import oracle
     # the oracle's forward of the first and last limb of every job
     chk_limbs = [sorted({0, j.L - 1}) for j in jobs]
@@ -559,16 +559,16 @@ def bench_batched(ntt, si, torch, reps=10):
         return e0.elapsed_time(e1) / n * 1e3
 
     reload()
-    branches.run()
-    check_forward("graph batch with parallel branches")
+    serial.run()
+    check_forward("graph batch with the buckets in sequence")
     # the three launch forms take turns over several rounds and each reports
     # its median round, so drift of the GPU's clock falls on all of them alike
-    rounds = {"graph": [], "eager": [], "branches": []}
+    rounds = {"graph": [], "eager": [], "serial": []}
     for _ in range(5):
         rounds["graph"].append(timed(fwd.run, reps))
         rounds["eager"].append(timed(eager.run, reps))
-        rounds["branches"].append(timed(branches.run, reps))
-    us_graph, us_eager, us_branches = (float(np.median(rounds[k])) for k in ("graph", "eager", "branches"))
+        rounds["serial"].append(timed(serial.run, reps))
+    us_graph, us_eager, us_serial = (float(np.median(rounds[k])) for k in ("graph", "eager", "serial"))
     # autotuned: every bucket size is tuned at its own item count, then the
     # batch is rebuilt (buckets pick their variants from the tuning table). The
     # process's table (the shipped one) is saved first and restored after, so
@@ -609,7 +609,7 @@ def bench_batched(ntt, si, torch, reps=10):
 
     us_call = timed(per_call, max(2, reps // 2))
     info = fwd.info
-    for b in (fwd, inv, eager, branches):
+    for b in (fwd, inv, eager, serial):
         b.close()
     for p_ in plans.values():
         p_.close()
@@ -618,7 +618,7 @@ def bench_batched(ntt, si, torch, reps=10):
            "tuned_graph_us": round(us_tuned, 1), "tuned_ntt_per_s": round(n_ntt / (us_tuned * 1e-6), 1),
            "tuned_choices": choices,
            "graph_alg_GBs": round(16 * words / (us_graph * 1e-6) / 1e9, 1),
-           "eager_us": round(us_eager, 1), "branches_graph_us": round(us_branches, 1),
+           "eager_us": round(us_eager, 1), "serial_graph_us": round(us_serial, 1),
            "rounds_us": {k: [round(t, 1) for t in v] for k, v in rounds.items()},
            "per_call_us": round(us_call, 1),
            "per_call_ntt_per_s": round(n_ntt / (us_call * 1e-6), 1),
@@ -627,7 +627,7 @@ def bench_batched(ntt, si, torch, reps=10):
            "checked": "forward of every job (first and last limb) vs the oracle, for the default and the tuned "
                       "batch; forward + inverse of every job is the identity"}
     log(f"batched: autotuned graph {us_tuned:.0f} us; choices {choices}")
-    log(f"batched: {n_ntt} NTTs in {us_graph:.0f} us (graph), {us_branches:.0f} us (graph of parallel branches), {us_eager:.0f} us (eager), "
+    log(f"batched: {n_ntt} NTTs in {us_graph:.0f} us (graph of parallel branches), {us_serial:.0f} us (graph, buckets in sequence), {us_eager:.0f} us (eager), "
         f"{us_call:.0f} us (per-call) -> {res['graph_ntt_per_s'] / 1e6:.2f} M NTT/s")
     return res
 

@@ -316,8 +316,11 @@ typedef struct {
   uint64_t scratch_bytes, twiddle_pool_bytes;
 } ntt_batch_info;
 #define NTT_BATCH_NO_GRAPH 0x1u  /* launch the kernels directly on each run */
-#define NTT_BATCH_BRANCHES 0x2u  /* the graph holds the buckets as parallel branches
-                                    instead of one after another, largest first */
+#define NTT_BATCH_BRANCHES 0x2u  /* the graph holds the buckets as parallel branches,
+                                    forked from and joined to the run's stream: the
+                                    default, so this flag changes nothing */
+#define NTT_BATCH_SERIAL 0x4u    /* the graph holds the buckets one after another,
+                                    largest first (not with NTT_BATCH_BRANCHES) */
 ntt_batch* ntt_batch_create(const ntt_job_desc* jobs, uint32_t n_jobs, uint32_t flags);
 int ntt_batch_run(ntt_batch* batch, void* stream);
 int ntt_batch_get_info(const ntt_batch* batch, ntt_batch_info* info);

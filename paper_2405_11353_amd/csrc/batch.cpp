@@ -3,8 +3,8 @@
 // twiddle tables (from the process-wide pool) and modulus constants; items
 // are bucketed by (N, direction), each bucket runs the variant the tuning
 // table (or the default) picks for its size, and the buckets are captured as
-// one graph: one bucket after another (largest first), or as parallel
-// branches.
+// one graph: as parallel branches (the default), or one bucket after another
+// (largest first).
 #include <algorithm>
 #include <map>
 #include <new>
@@ -140,13 +140,12 @@ static int build(ntt_batch* b, const ntt_job_desc* jobs, uint32_t n_jobs) {
     return NTT_ERR_HIP;
   if (b->flags & NTT_BATCH_NO_GRAPH) return NTT_OK;
 
-  // one graph: every bucket in turn on the capture stream; or with
-  // NTT_BATCH_BRANCHES, a fork from the capture stream to a branch per
-  // bucket, joined back
+  // one graph: a fork from the capture stream to a branch per bucket, joined
+  // back; or with NTT_BATCH_SERIAL every bucket in turn on the capture stream
   if (hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess)
     return NTT_ERR_HIP;
-  if (!(b->flags & NTT_BATCH_BRANCHES)) {
+  if (b->flags & NTT_BATCH_SERIAL) {
     if (hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal) != hipSuccess) return NTT_ERR_HIP;
     hipError_t e = hipSuccess;
     for (auto& k : b->buckets)
@@ -187,7 +186,8 @@ static int build(ntt_batch* b, const ntt_job_desc* jobs, uint32_t n_jobs) {
 extern "C" {
 
 ntt_batch* ntt_batch_create(const ntt_job_desc* jobs, uint32_t n_jobs, uint32_t flags) {
-  if (!jobs || n_jobs == 0 || (flags & ~(NTT_BATCH_NO_GRAPH | NTT_BATCH_BRANCHES))) {
+  if (!jobs || n_jobs == 0 || (flags & ~(NTT_BATCH_NO_GRAPH | NTT_BATCH_BRANCHES | NTT_BATCH_SERIAL)) ||
+      ((flags & NTT_BATCH_BRANCHES) && (flags & NTT_BATCH_SERIAL))) {
     ntt_set_last_error(NTT_ERR_ARG);
     return nullptr;
   }

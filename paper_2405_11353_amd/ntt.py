@@ -28,6 +28,7 @@ _lib = None
 NTT_JOB_FORWARD, NTT_JOB_INVERSE = 0, 1
 NTT_BATCH_NO_GRAPH = 0x1
 NTT_BATCH_BRANCHES = 0x2
+NTT_BATCH_SERIAL = 0x4
 
 
 class JobDesc(ctypes.Structure):

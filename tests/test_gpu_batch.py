@@ -45,7 +45,7 @@ SPECS = [(4, 3, 0), (8, 1, 0), (12, 2, 0), (13, 4, 0), (14, 3, 0), (15, 2, 0), (
          (12, 5, 1), (16, 2, 1), (10, 2, 0), (16, 1, 0), (12, 1, 0)]
 
 
-@pytest.mark.parametrize("flags", [0, 1, 2])
+@pytest.mark.parametrize("flags", [0, 1, 2, 4])
 def test_batch_mixed_jobs_match_oracle(ntt, flags):
     log(f"case batch mixed flags={flags}")
     jobs = make_jobs(1, SPECS)
@@ -106,6 +106,8 @@ def test_batch_round_trip_uneven_cfg(ntt):
 def test_batch_argument_errors(ntt):
     import torch
     t = torch.zeros(1024, dtype=torch.int64, device="cuda")
+    with pytest.raises(ntt.NttError):               # two graph forms at once
+        ntt.Batch([(1024, P18[:1], 0, t)], flags=ntt.NTT_BATCH_BRANCHES | ntt.NTT_BATCH_SERIAL)
     with pytest.raises(ntt.NttError):
         ntt.Batch([(1000, P18[:1], 0, t)])          # N not a power of two
     with pytest.raises(ntt.NttError):
