@@ -362,6 +362,27 @@ def test_fused_pointwise_inverse(ntt, logn, bitrev, variant, row_twist):
             np.testing.assert_array_equal(got[1, l], oracle.negacyclic_mul(a[1, l], b[1, l], q))
 
 
+@pytest.mark.parametrize("logn,logn1,bitrev", [(14, 7, False), (16, 8, False), (17, 9, True)])
+@pytest.mark.parametrize("row_twist", [True, False])
+def test_fused_pointwise_inverse_u32(ntt, logn, logn1, bitrev, row_twist):
+    """32-bit words: the fused product is a Montgomery product at 2^32 and the
+    inverse column pass multiplies 2^32 back in; against the unfused oracle."""
+    N, moduli = 1 << logn, Q32[:2]
+    log(f"case fused pointwise+inverse u32 N={N} logn1={logn1} bitrev={bitrev} row_twist={row_twist}")
+    plan = ntt.Plan(N, moduli, flags=ntt.NTT_WORD32 | (ntt.NTT_ORDER_BITREV if bitrev else 0))
+    plan.set_variant(ntt.NTT_PATH_FOURSTEP, logn1)
+    plan.set_row_twist(row_twist)
+    a = si.poly_batch(51, 2, moduli, N)
+    b = si.poly_batch(52, 2, moduli, N)
+    da, db = to_dev(a, 32), to_dev(b, 32)
+    plan.forward(da)
+    plan.forward(db)
+    dc = to_dev(np.zeros_like(a), 32)
+    plan.pointwise_inverse(da, db, dc)
+    ref = oracle_inv(oracle.pointwise_batch(oracle_fwd(a, moduli), oracle_fwd(b, moduli), moduli)[0], moduli)
+    np.testing.assert_array_equal(from_dev(dc, 32).reshape(a.shape), ref)
+
+
 @pytest.mark.parametrize("logn,logn1", [(14, 7), (16, 8), (17, 9)])
 @pytest.mark.parametrize("row_twist", [True, False])
 def test_fused_pointwise_inverse_exact_quotient(ntt, logn, logn1, row_twist):
