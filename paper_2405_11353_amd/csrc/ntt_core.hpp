@@ -289,6 +289,17 @@ __device__ __forceinline__ void st_data(T* p, T v) {
   if constexpr (NT) __builtin_nontemporal_store(v, p);
   else *p = v;
 }
+// The same at a per-lane 32-bit byte offset from a workgroup-uniform base:
+// the global instruction then takes the base from SGPRs and the offset as is,
+// instead of a 64-bit address computed per lane and per access.
+template <bool NT, class T>
+__device__ __forceinline__ T ld_off(const T* ubase, uint32_t boff) {
+  return ld_data<NT>((const T*)((const char*)ubase + boff));
+}
+template <bool NT, class T>
+__device__ __forceinline__ void st_off(T* ubase, uint32_t boff, T v) {
+  st_data<NT>((T*)((char*)ubase + boff), v);
+}
 
 // ============================================================ column pass
 // NC columns per workgroup, N1/V threads per column (V = 2^LV values each);
@@ -327,9 +338,11 @@ k_col(const typename A::word* in, typename A::word* out, const typename A::tw_t*
   // scalar loads; the forward pass reads the later phases' slots from LDS.
   const TW* tw;
   const TW* t01 = nullptr;
+  // src / dst: the tile's first column of the item (workgroup-uniform); a
+  // lane's words lie at byte offsets (row * N2 + c) * 8 from them
   const W* src;
   W* dst;
-  const size_t off = tile * NC + c;
+  const size_t off = tile * NC;
   if constexpr (IND) {
     const ItemDesc d = desc[item];
     a.load(*(const M*)d.mod);
@@ -345,10 +358,16 @@ k_col(const typename A::word* in, typename A::word* out, const typename A::tw_t*
     src = in + base;
     dst = out + base;
   }
+  // value i of a lane sits in row i * TPC + t (natural) or pos(last phase, t,
+  // i) = pos(last phase, t, 0) + (i << lgs): a uniform row step per i and one
+  // per-lane byte offset
+  constexpr int LGL = S::lgs(S::NPH - 1);
+  const uint32_t off_nat = (t * N2 + c) * (uint32_t)sizeof(W);
+  const uint32_t off_pos = (pos<LOGN1, LV>(S::NPH - 1, t, 0) * N2 + c) * (uint32_t)sizeof(W);
   W v[V];
   if constexpr (FWD) {
 #pragma unroll
-    for (int i = 0; i < V; ++i) v[i] = ld_data<NT_LD_IN>(src + (size_t)(i * TPC + t) * N2);
+    for (int i = 0; i < V; ++i) v[i] = ld_off<NT_LD_IN>(src + (size_t)(i * TPC) * N2, off_nat);
     if constexpr (TWL) {
       for (uint32_t k = threadIdx.x; k < N1; k += blockDim.x) twl[k] = tw[k];
     }
@@ -367,10 +386,10 @@ k_col(const typename A::word* in, typename A::word* out, const typename A::tw_t*
       }
     });
 #pragma unroll
-    for (int i = 0; i < V; ++i) st_data<NT_ST_MID>(dst + (size_t)pos<LOGN1, LV>(S::NPH - 1, t, i) * N2, v[i]);
+    for (int i = 0; i < V; ++i) st_off<NT_ST_MID>(dst + ((size_t)i << LGL) * N2, off_pos, v[i]);
   } else {
 #pragma unroll
-    for (int i = 0; i < V; ++i) v[i] = ld_data<NT_LD_MID>(src + (size_t)pos<LOGN1, LV>(S::NPH - 1, t, i) * N2);
+    for (int i = 0; i < V; ++i) v[i] = ld_off<NT_LD_MID>(src + ((size_t)i << LGL) * N2, off_pos);
     static_for_down<S::NPH - 1, 0>([&](auto P_) {
       constexpr int p = decltype(P_)::value;
       if constexpr (p < S::NPH - 1) {
@@ -384,7 +403,7 @@ k_col(const typename A::word* in, typename A::word* out, const typename A::tw_t*
       gs_phase<A, S::rs(p), p == 0>(a, v, tw, S::s0(p), p == 0 ? 0u : grp<LOGN1, LV>(p, t), t01);
     });
 #pragma unroll
-    for (int i = 0; i < V; ++i) st_data<NT_ST_INV_OUT>(dst + (size_t)(i * TPC + t) * N2, a.canon_inv(v[i]));
+    for (int i = 0; i < V; ++i) st_off<NT_ST_INV_OUT>(dst + (size_t)(i * TPC) * N2, off_nat, a.canon_inv(v[i]));
   }
 }
 
@@ -547,11 +566,14 @@ k_row(const typename A::word* in, typename A::word* out, const typename A::tw_t*
       for (int i = 0; i < V; ++i) sh[pad16(pos<LOGN2, LV>(S::NPH - 1, t, i))] = a.canon_fwd(v[i]);
       __syncthreads();
       const uint32_t rr = threadIdx.x % 16, cg = threadIdx.x / 16;
-      W* dst = out + pbase + tile * 16 + rr;
+      // column cc = cg + TPR j goes to row brv(cc) = brv(cg) + brv(TPR j) (disjoint
+      // bits): a uniform base per j and one byte offset per lane
+      W* dst = out + pbase + tile * 16;
+      const uint32_t lane_off = (rr + brv(cg, LOGN2) * N1) * (uint32_t)sizeof(W);
 #pragma unroll
       for (int j = 0; j < V; ++j) {
         const uint32_t cc = cg + TPR * j;
-        st_data<NT_ST_OUT>(dst + (size_t)brv(cc, LOGN2) * N1, lds[rr * RSTR + pad16(cc)]);
+        st_off<NT_ST_OUT>(dst + (size_t)brv(TPR * j, LOGN2) * N1, lane_off, lds[rr * RSTR + pad16(cc)]);
       }
     } else {
       if (S::NPH > 1) wave_lds_sync();
@@ -565,16 +587,19 @@ k_row(const typename A::word* in, typename A::word* out, const typename A::tw_t*
   } else {
     if constexpr (NATURAL) {
       const uint32_t rr = threadIdx.x % 16, cg = threadIdx.x / 16;
-      const size_t off = pbase + tile * 16 + rr;
+      // row brv(cg + TPR j) = brv(cg) + brv(TPR j): a uniform base per j and one
+      // byte offset per lane
+      const size_t off = pbase + tile * 16;
       const W* src = in + off;
+      const uint32_t lane_off = (rr + brv(cg, LOGN2) * N1) * (uint32_t)sizeof(W);
       // every load is issued before the first product, so that a wave has all
       // of its loads in flight at once rather than one pair per product
       W xa[V], xb[MULIN ? V : 1];
 #pragma unroll
       for (int j = 0; j < V; ++j) {
-        const size_t e = (size_t)brv(cg + TPR * j, LOGN2) * N1;
-        xa[j] = ld_data<NT_LD_IN>(src + e);
-        if constexpr (MULIN) xb[j] = ld_data<NT_LD_IN>(in2 + off + e);
+        const size_t e = (size_t)brv(TPR * j, LOGN2) * N1;
+        xa[j] = ld_off<NT_LD_IN>(src + e, lane_off);
+        if constexpr (MULIN) xb[j] = ld_off<NT_LD_IN>(in2 + off + e, lane_off);
       }
       stage();
 #pragma unroll
@@ -759,11 +784,14 @@ k_row_tw(const typename A::word* in, typename A::word* out, const typename A::tw
       for (int i = 0; i < V; ++i) sh[pad16(pos<LOGN2, LV>(S::NPH - 1, t, i))] = a.canon_fwd(v[i]);
       __syncthreads();
       const uint32_t rr = threadIdx.x % 16, cg = threadIdx.x / 16;
-      W* dst = out + pbase + tile * 16 + rr;
+      // column cc = cg + TPR j goes to row brv(cc) = brv(cg) + brv(TPR j) (disjoint
+      // bits): a uniform base per j and one byte offset per lane
+      W* dst = out + pbase + tile * 16;
+      const uint32_t lane_off = (rr + brv(cg, LOGN2) * N1) * (uint32_t)sizeof(W);
 #pragma unroll
       for (int j = 0; j < V; ++j) {
         const uint32_t cc = cg + TPR * j;
-        st_data<NT_ST_OUT>(dst + (size_t)brv(cc, LOGN2) * N1, lds[rr * RSTR + pad16(cc)]);
+        st_off<NT_ST_OUT>(dst + (size_t)brv(TPR * j, LOGN2) * N1, lane_off, lds[rr * RSTR + pad16(cc)]);
       }
     } else {
       if (S::NPH > 1) wave_lds_sync();
@@ -778,16 +806,19 @@ k_row_tw(const typename A::word* in, typename A::word* out, const typename A::tw
     if (has_entry) cyc[cyc_pos<LOGN2, LV>(threadIdx.x)] = cyc_entry;
     if constexpr (NATURAL) {
       const uint32_t rr = threadIdx.x % 16, cg = threadIdx.x / 16;
-      const size_t off = pbase + tile * 16 + rr;
+      // row brv(cg + TPR j) = brv(cg) + brv(TPR j): a uniform base per j and one
+      // byte offset per lane
+      const size_t off = pbase + tile * 16;
       const W* src = in + off;
+      const uint32_t lane_off = (rr + brv(cg, LOGN2) * N1) * (uint32_t)sizeof(W);
       // every load is issued before the first product, so that a wave has all
       // of its loads in flight at once rather than one pair per product
       W xa[V], xb[MULIN ? V : 1];
 #pragma unroll
       for (int j = 0; j < V; ++j) {
-        const size_t e = (size_t)brv(cg + TPR * j, LOGN2) * N1;
-        xa[j] = ld_data<NT_LD_IN>(src + e);
-        if constexpr (MULIN) xb[j] = ld_data<NT_LD_IN>(in2 + off + e);
+        const size_t e = (size_t)brv(TPR * j, LOGN2) * N1;
+        xa[j] = ld_off<NT_LD_IN>(src + e, lane_off);
+        if constexpr (MULIN) xb[j] = ld_off<NT_LD_IN>(in2 + off + e, lane_off);
       }
 #pragma unroll
       for (int j = 0; j < V; ++j) {
@@ -963,11 +994,14 @@ k_row_st(const typename A::word* in, typename A::word* out, const typename A::tw
     for (int i = 0; i < V; ++i) sh[pad16(pos<LOGN2, LV>(S::NPH - 1, t, i))] = a.canon_fwd(v[i]);
     __syncthreads();
     const uint32_t rr = threadIdx.x % 16, cg = threadIdx.x / 16;
-    W* dst = out + pbase + tile * 16 + rr;
+    // column cc = cg + TPR j goes to row brv(cc) = brv(cg) + brv(TPR j) (disjoint
+    // bits): a uniform base per j and one byte offset per lane
+    W* dst = out + pbase + tile * 16;
+    const uint32_t lane_off = (rr + brv(cg, LOGN2) * N1) * (uint32_t)sizeof(W);
 #pragma unroll
     for (int j = 0; j < V; ++j) {
       const uint32_t cc = cg + TPR * j;
-      st_data<NT_ST_OUT>(dst + (size_t)brv(cc, LOGN2) * N1, lds[rr * RSTR + pad16(cc)]);
+      st_off<NT_ST_OUT>(dst + (size_t)brv(TPR * j, LOGN2) * N1, lane_off, lds[rr * RSTR + pad16(cc)]);
     }
   } else {
     if (S::NPH > 1) wave_lds_sync();
@@ -1046,14 +1080,17 @@ k_row_st_inv(const typename A::word* in, typename A::word* out, const typename A
   W v[V];
   if constexpr (NATURAL) {
     const uint32_t rr = threadIdx.x % 16, cg = threadIdx.x / 16;
-    const size_t off = pbase + tile * 16 + rr;
+    // row brv(cg + TPR j) = brv(cg) + brv(TPR j): a uniform base per j and one
+    // byte offset per lane
+    const size_t off = pbase + tile * 16;
     const W* src = in + off;
+    const uint32_t lane_off = (rr + brv(cg, LOGN2) * N1) * (uint32_t)sizeof(W);
     W xa[V], xb[MULIN ? V : 1];
 #pragma unroll
     for (int j = 0; j < V; ++j) {
-      const size_t e = (size_t)brv(cg + TPR * j, LOGN2) * N1;
-      xa[j] = ld_data<NT_LD_IN>(src + e);
-      if constexpr (MULIN) xb[j] = ld_data<NT_LD_IN>(in2 + off + e);
+      const size_t e = (size_t)brv(TPR * j, LOGN2) * N1;
+      xa[j] = ld_off<NT_LD_IN>(src + e, lane_off);
+      if constexpr (MULIN) xb[j] = ld_off<NT_LD_IN>(in2 + off + e, lane_off);
     }
     first.put(tw0);
     if (has_entry) cyc[cyc_pos<LOGN2, LV>(threadIdx.x)] = cyc_entry;
