@@ -1014,9 +1014,6 @@ k_row_st(const typename A::word* in, typename A::word* out, const typename A::tw
   }
 }
 
-// Inverse: the spectrum rows (or with MULIN the Montgomery product of two, as
-// in k_row) through the cyclic inverse phases, the factors beta_r^-(...), and the merged inverse
-// first phase; rows written in place, in the lazy range the column pass takes.
 // Lane map of the inverse row pass's phases. A phase whose groups hold 8
 // offsets (stride 2^3) with 8 values per thread places, under the identity
 // t = (group << 3) + offset, two groups in each 16-lane LDS cycle: their
@@ -1039,6 +1036,10 @@ __device__ __forceinline__ uint32_t row_inv_lane(int p, uint32_t t) {
   return (g << 3) | off;
 }
 
+// Inverse: the spectrum rows (or with MULIN the Montgomery product of two, as
+// in k_row) through the cyclic inverse phases, the factors beta_r^-(...), and
+// the merged inverse first phase; rows written in place, in the lazy range the
+// column pass takes.
 template <class A, int LOGN2, bool NATURAL, bool MULIN, int LV = 3>
 __global__ void __launch_bounds__(16 << (LOGN2 - LV))
 k_row_st_inv(const typename A::word* in, typename A::word* out, const typename A::tw_t* __restrict__ tw_all,
