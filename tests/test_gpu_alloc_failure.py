@@ -161,3 +161,29 @@ def test_conversion_plan_creation(ntt):
         outcomes.append("ok")
         break
     assert outcomes[0] == "create" and outcomes[-1] == "ok", outcomes
+
+
+def test_autotune_allocations(ntt, tmp_path):
+    """The autotuner's own plan and timing buffer: a failure at either is
+    NTT_ERR_NOMEM. The process's tuning table is saved first and restored
+    after, so later tests run with the table they would otherwise see."""
+    saved = str(tmp_path / "tune.json")
+    ntt.ntt_tune_save(saved)
+    outcomes = []
+    try:
+        for k in range(1, 10):
+            log(f"case allocation {k} fails: autotune 2^12")
+            with failing(k):
+                try:
+                    best = ntt.ntt_autotune(1 << 12, items=8, reps=2)
+                except ntt.NttError as e:
+                    assert e.code == ntt.NTT_ERR_NOMEM, e
+                    outcomes.append("fail")
+                    continue
+            assert best["us_per_call"] > 0
+            outcomes.append("ok")
+            break
+    finally:
+        ntt.ntt_tune_clear()
+        ntt.ntt_tune_load(saved)
+    assert outcomes[0] == "fail" and outcomes[-1] == "ok", outcomes
