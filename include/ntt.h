@@ -253,6 +253,10 @@ int ntt_plan_get_row_form(const ntt_plan* plan, uint32_t batch, int* row_twist, 
 
 /* The variant a call with `batch` polynomials would run (after tuning). */
 int ntt_plan_get_variant_for(const ntt_plan* plan, uint32_t batch, int* path, int* log_n1, int* exact);
+/* Columns per tile of the four-step column passes a call on `batch`
+ * polynomials runs with: 16 or 32 (64-bit words, as tuned), 32 (32-bit
+ * words), 0 off the four-step path. */
+int ntt_plan_get_col_tile(const ntt_plan* plan, uint32_t batch, int* columns);
 
 /* Thread-local code of the last failed call that returns a pointer, and a
  * static description of any code. */
@@ -283,6 +287,7 @@ typedef struct {
   float us_per_call;  /* measured time of the winner */
   int32_t row_twist;  /* four-step: NTT_ROW_TWIST_* mask of the faster row forms; -1 otherwise */
   int32_t lv_col;     /* four-step, 64-bit: log2 values per thread of the column passes (4), 0 = default (3) */
+  int32_t col_tile;   /* four-step, 64-bit: columns per column-pass tile (32), 0 = default (16) */
 } ntt_tune_choice;
 int ntt_autotune(uint32_t N, uint32_t flags, uint32_t items, uint32_t reps, ntt_tune_choice* best);
 int ntt_tune_save(const char* path);
@@ -295,8 +300,9 @@ int ntt_tune_clear(void);
  * contiguous 64-bit words at d_data, limb l reduced mod moduli[l] (q < 2^61,
  * prime, 2N | q-1). Items (polynomial, limb) are bucketed by (N, op); each
  * bucket runs the tuned (or default) variant; the buckets' kernels are
- * captured once, at creation, into one hipGraph (one bucket after another,
- * the largest first), so a run is a single hipGraphLaunch. Twiddle tables come from a process-wide pool
+ * captured once, at creation, into one hipGraph (the buckets as parallel
+ * branches; with NTT_BATCH_SERIAL one after another, the largest first), so a
+ * run is a single hipGraphLaunch. Twiddle tables come from a process-wide pool
  * keyed by (device, q, N) and stay resident. The batch owns its descriptor
  * table, four-step scratch and graph; the caller owns the job buffers, which
  * must stay valid (the graph holds their addresses). Natural-order spectra. */

@@ -51,27 +51,30 @@ static void default_variant(ntt_plan* p) {
 }
 
 // the variant a call on `items` transforms runs with; twist (the row-form
-// mask) and lv_col (column passes' values per thread, 0 = default) as tuned
-// with it, or the plan's own
+// mask), lv_col (column passes' values per thread, 0 = default) and col_tile
+// (their columns per tile, 0 = default) as tuned with it, or the plan's own
 static void select_variant(const ntt_plan* p, uint32_t items, int* path, int* logN1, int* exact,
-                           int* twist = nullptr, int* lv_col = nullptr) {
+                           int* twist = nullptr, int* lv_col = nullptr, int* col_tile = nullptr) {
   *path = p->path;
   *logN1 = p->logN1;
   *exact = p->exact;
-  int tw = -1, lv = 0;
+  int tw = -1, lv = 0, ct = 0;
   if (p->auto_variant) {
     int tp, tn1, tex;
-    if (ntti::tune_lookup(p->word, (int)p->logN, items, &tp, &tn1, &tex, &tw, &lv) && variant_ok(p, tp, tn1, tex)) {
+    if (ntti::tune_lookup(p->word, (int)p->logN, items, &tp, &tn1, &tex, &tw, &lv, &ct) &&
+        variant_ok(p, tp, tn1, tex)) {
       *path = tp;
       *logN1 = tn1;
       *exact = tex;
     } else {
       tw = -1;
       lv = 0;
+      ct = 0;
     }
   }
   if (twist) *twist = (p->auto_twist && tw >= 0) ? tw : p->row_twist;
   if (lv_col) *lv_col = p->tune_lv_col ? p->tune_lv_col : (p->word == 64 ? lv : 0);
+  if (col_tile) *col_tile = p->tune_col_tile ? p->tune_col_tile : (p->word == 64 ? ct : 0);
 }
 
 namespace ntti {
@@ -331,6 +334,14 @@ int ntt_plan_get_variant_for(const ntt_plan* p, uint32_t batch, int* path, int* 
   return NTT_OK;
 }
 
+int ntt_plan_get_col_tile(const ntt_plan* p, uint32_t batch, int* columns) {
+  if (!p || batch == 0 || !columns) return NTT_ERR_ARG;
+  int pa, n1, ex, tw, lv, ct;
+  select_variant(p, batch * p->L, &pa, &n1, &ex, &tw, &lv, &ct);
+  *columns = pa != NTT_PATH_FOURSTEP ? 0 : p->word == 32 ? 32 : (ct == 32 ? 32 : 16);
+  return NTT_OK;
+}
+
 int ntt_plan_get_row_form(const ntt_plan* p, uint32_t batch, int* row_twist, int* log_values) {
   if (!p || batch == 0) return NTT_ERR_ARG;
   int pa, n1, ex, tw, lv;
@@ -536,8 +547,8 @@ static int run_ntt(const ntt_plan* pc, void* data, uint32_t batch, void* stream,
   // the input of a whole transform, or of its first kernel, is canonical
   if ((stage_mask & 1) && (rc = ntti::debug_range(pc, data, batch, stream)) != NTT_OK) return rc;
   ntt_plan* p = const_cast<ntt_plan*>(pc);
-  int path, logN1, exact, twist_mask, lv_col;
-  select_variant(p, batch * p->L, &path, &logN1, &exact, &twist_mask, &lv_col);
+  int path, logN1, exact, twist_mask, lv_col, col_tile;
+  select_variant(p, batch * p->L, &path, &logN1, &exact, &twist_mask, &lv_col, &col_tile);
   if (is_paper_path(path)) {
     if (stage_mask != 3 || fixed_scratch) return NTT_ERR_UNSUPPORTED;
     return run_paper(p, data, batch, stream, fwd, path);
@@ -559,6 +570,7 @@ static int run_ntt(const ntt_plan* pc, void* data, uint32_t batch, void* stream,
   c.stream = (hipStream_t)stream;
   c.stage_mask = stage_mask;
   c.lv_col = lv_col;
+  c.col_tile = col_tile;
   if (stage_mask != 3 && c.path != nttk::PATH_TWO) return NTT_ERR_UNSUPPORTED;
   bool twisted = c.path == nttk::PATH_TWO && (twist_mask & (fwd ? NTT_ROW_TWIST_FWD : NTT_ROW_TWIST_INV));
   if (fixed_scratch) {
@@ -639,8 +651,8 @@ static int run_mul_inverse(const ntt_plan* pc, const void* a, const void* b, voi
                            (rc = ntti::debug_range(pc, b, batch, stream)) != NTT_OK))
     return rc;
   ntt_plan* p = const_cast<ntt_plan*>(pc);
-  int path, logN1, exact, twist_mask, lv_col;
-  select_variant(p, batch * p->L, &path, &logN1, &exact, &twist_mask, &lv_col);
+  int path, logN1, exact, twist_mask, lv_col, col_tile;
+  select_variant(p, batch * p->L, &path, &logN1, &exact, &twist_mask, &lv_col, &col_tile);
   if (path != NTT_PATH_FOURSTEP) {
     if (stage_mask != 3) return NTT_ERR_UNSUPPORTED;
     // no fused kernel for this shape: the two steps, still on the device
@@ -666,6 +678,7 @@ static int run_mul_inverse(const ntt_plan* pc, const void* a, const void* b, voi
   L.stream = (hipStream_t)stream;
   L.stage_mask = stage_mask;
   L.lv_col = lv_col;
+  L.col_tile = col_tile;
   if (L.natural) {
     rc = get_scratch(p, stream, ntt_workspace_bytes(p, batch), &L.scratch);
     if (rc != NTT_OK) return rc;

@@ -40,6 +40,7 @@ struct Launch {
   hipStream_t stream = nullptr;
   int stage_mask = 3;       // PATH_TWO: bit 0 runs the first kernel, bit 1 the second
   int lv_col = 0;           // PATH_TWO, 64-bit: values per thread (log2, 3 or 4) of the column passes; 0 = default
+  int col_tile = 0;         // PATH_TWO, 64-bit: columns per column-pass tile (32), 0 = default (16)
   const void* mul_a = nullptr;  // PATH_TWO inverse: if set, transform mul_a * mul_b into data
   const void* mul_b = nullptr;
   // PATH_TWO inverse column pass: [L][2] twiddle pairs that replace table

@@ -49,6 +49,7 @@ struct ntt_plan {
   int row_twist = NTT_ROW_TWIST_DEFAULT;  // directions whose four-step row pass is twisted
   bool auto_twist = true;             // until set: the tuning table's row form, if it has one
   int tune_lv_col = 0;                // the autotuner's own override of the column passes' values per thread
+  int tune_col_tile = 0;              // and of their columns per tile
 };
 
 namespace ntti {
@@ -58,11 +59,12 @@ int ilog2(uint32_t x);
 void default_variant(int word, int logN, int* path, int* logN1);
 // tuned variant for (word, logN, items) if the tuning table has one
 // twist: the row-form mask (NTT_ROW_TWIST_*) tuned with it, -1 if none;
-// lv_col: log2 of the values per thread of the column passes, 0 = default
+// lv_col: log2 of the values per thread of the column passes, 0 = default;
+// col_tile: their columns per tile (32), 0 = default
 bool tune_lookup(int word, int logN, uint32_t items, int* path, int* logN1, int* exact, int* twist = nullptr,
-                 int* lv_col = nullptr);
+                 int* lv_col = nullptr, int* col_tile = nullptr);
 void tune_store(int word, int logN, uint32_t items, int path, int logN1, int exact, float us, int twist = -1,
-                int lv_col = 0);
+                int lv_col = 0, int col_tile = 0);
 // load the table named by NTT_TUNE_CACHE once per process (no-op if unset)
 void tune_autoload();
 

@@ -29,6 +29,7 @@ struct TVal {
   float us;
   int twist = -1;  // row-form mask tuned with the variant, -1: none
   int lv_col = 0;  // column passes' values per thread (log2), 0: default
+  int col_tile = 0;  // column passes' columns per tile (32), 0: default
 };
 std::mutex g_mu;
 std::map<TKey, TVal> g_table;
@@ -68,7 +69,8 @@ void default_variant(int word, int logN, int* path, int* logN1) {
   }
 }
 
-bool tune_lookup(int word, int logN, uint32_t items, int* path, int* logN1, int* exact, int* twist, int* lv_col) {
+bool tune_lookup(int word, int logN, uint32_t items, int* path, int* logN1, int* exact, int* twist, int* lv_col,
+                 int* col_tile) {
   std::lock_guard<std::mutex> g(g_mu);
   if (g_table.empty()) return false;
   const int b = items_bucket(items);
@@ -89,13 +91,14 @@ bool tune_lookup(int word, int logN, uint32_t items, int* path, int* logN1, int*
   *exact = best->exact;
   if (twist) *twist = best->twist;
   if (lv_col) *lv_col = best->lv_col;
+  if (col_tile) *col_tile = best->col_tile;
   return true;
 }
 
 void tune_store(int word, int logN, uint32_t items, int path, int logN1, int exact, float us, int twist,
-                int lv_col) {
+                int lv_col, int col_tile) {
   std::lock_guard<std::mutex> g(g_mu);
-  g_table[TKey{word, logN, items_bucket(items)}] = TVal{path, logN1, exact, us, twist, lv_col};
+  g_table[TKey{word, logN, items_bucket(items)}] = TVal{path, logN1, exact, us, twist, lv_col, col_tile};
 }
 
 uint64_t tuning_prime(uint32_t N, int word) {
@@ -158,22 +161,25 @@ int ntt_autotune(uint32_t N, uint32_t flags, uint32_t items, uint32_t reps, ntt_
                        hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
     rc = NTT_ERR_HIP;
   // candidates: the LDS kernel, and every four-step split with either
-  // quotient flavour (64-bit) and 8 or 16 values per thread in the column
-  // passes (64-bit), all timed as forward transforms with merged row passes;
-  // then, for a four-step winner, the row form of each direction
+  // quotient flavour (64-bit), and 8 or 16 values per thread and 16 or 32
+  // columns per tile in the column passes (64-bit), all timed as forward
+  // transforms with merged row passes; then, for a four-step winner, the row
+  // form of each direction
   struct Cand {
-    int path, logN1, exact, lv;
+    int path, logN1, exact, lv, tile;
   };
   std::vector<Cand> cands;
   const int lg = ilog2(N);
-  if (lg <= 3) cands.push_back({NTT_PATH_TINY, 0, 0, 0});
-  if (lg >= 4 && lg <= nttk::lds_max_logn(word)) cands.push_back({NTT_PATH_LDS, 0, 0, 0});
+  if (lg <= 3) cands.push_back({NTT_PATH_TINY, 0, 0, 0, 0});
+  if (lg >= 4 && lg <= nttk::lds_max_logn(word)) cands.push_back({NTT_PATH_LDS, 0, 0, 0, 0});
   for (int a = nttk::kTwoPassMinLog; a <= nttk::kTwoPassMaxLog; ++a)
     if (nttk::shape_supported(word, 0, nttk::PATH_TWO, lg, a)) {
-      cands.push_back({NTT_PATH_FOURSTEP, a, 0, 0});
+      cands.push_back({NTT_PATH_FOURSTEP, a, 0, 0, 0});
       if (word == 64) {
-        cands.push_back({NTT_PATH_FOURSTEP, a, 1, 0});
-        cands.push_back({NTT_PATH_FOURSTEP, a, 0, 4});
+        cands.push_back({NTT_PATH_FOURSTEP, a, 1, 0, 0});
+        cands.push_back({NTT_PATH_FOURSTEP, a, 0, 4, 0});
+        cands.push_back({NTT_PATH_FOURSTEP, a, 0, 0, 32});
+        cands.push_back({NTT_PATH_FOURSTEP, a, 0, 4, 32});
       }
     }
   // one timed configuration: `reps` calls after two warm-up calls
@@ -190,7 +196,7 @@ int ntt_autotune(uint32_t N, uint32_t flags, uint32_t items, uint32_t reps, ntt_
     *us = ms * 1000.f / reps;
     return true;
   };
-  Cand best{-1, 0, 0, 0};
+  Cand best{-1, 0, 0, 0, 0};
   float best_us = 1e30f;
   for (const Cand& c : cands) {
     if (rc != NTT_OK) break;
@@ -198,6 +204,7 @@ int ntt_autotune(uint32_t N, uint32_t flags, uint32_t items, uint32_t reps, ntt_
     if (c.exact && ntt_plan_set_quotient(plan, 1) != NTT_OK) continue;
     if (ntt_plan_set_row_twist(plan, 0) != NTT_OK) continue;
     plan->tune_lv_col = c.lv;
+    plan->tune_col_tile = c.tile;
     float us;
     if (time_us(true, &us) && us < best_us) {
       best_us = us;
@@ -205,6 +212,7 @@ int ntt_autotune(uint32_t N, uint32_t flags, uint32_t items, uint32_t reps, ntt_
     }
   }
   plan->tune_lv_col = 0;
+  plan->tune_col_tile = 0;
   int twist = -1;
   if (rc == NTT_OK && best.path == NTT_PATH_FOURSTEP && ntt_plan_set_variant(plan, best.path, best.logN1) == NTT_OK &&
       (!best.exact || ntt_plan_set_quotient(plan, 1) == NTT_OK)) {
@@ -213,6 +221,7 @@ int ntt_autotune(uint32_t N, uint32_t flags, uint32_t items, uint32_t reps, ntt_
     // twisted rows move less memory, which pays when kernels overlap (calls
     // on several streams) and which a call timed alone does not see.
     plan->tune_lv_col = best.lv;
+    plan->tune_col_tile = best.tile;
     int mask = NTT_ROW_TWIST_DEFAULT;
     for (int bit : {NTT_ROW_TWIST_FWD, NTT_ROW_TWIST_INV}) {
       float merged, twisted;
@@ -225,10 +234,11 @@ int ntt_autotune(uint32_t N, uint32_t flags, uint32_t items, uint32_t reps, ntt_
     }
     twist = mask == NTT_ROW_TWIST_DEFAULT ? -1 : mask;
     plan->tune_lv_col = 0;
+    plan->tune_col_tile = 0;
   }
   if (rc == NTT_OK && best.path < 0) rc = NTT_ERR_UNSUPPORTED;
   if (rc == NTT_OK) {
-    tune_store(word, lg, items, best.path, best.logN1, best.exact, best_us, twist, best.lv);
+    tune_store(word, lg, items, best.path, best.logN1, best.exact, best_us, twist, best.lv, best.tile);
     if (best_out) {
       best_out->path = best.path;
       best_out->log_n1 = best.logN1;
@@ -236,6 +246,7 @@ int ntt_autotune(uint32_t N, uint32_t flags, uint32_t items, uint32_t reps, ntt_
       best_out->us_per_call = best_us;
       best_out->row_twist = twist;
       best_out->lv_col = best.lv;
+      best_out->col_tile = best.tile;
     }
   }
   if (e0) (void)hipEventDestroy(e0);
@@ -256,9 +267,9 @@ int ntt_tune_save(const char* path) {
   for (auto& kv : g_table) {
     fprintf(f,
             "%s\n  {\"word\": %d, \"log_n\": %d, \"items_log2\": %d, \"path\": %d, \"log_n1\": %d, "
-            "\"exact\": %d, \"us\": %.3f, \"row_twist\": %d, \"lv_col\": %d}",
+            "\"exact\": %d, \"us\": %.3f, \"row_twist\": %d, \"lv_col\": %d, \"col_tile\": %d}",
             first ? "" : ",", kv.first.word, kv.first.logN, kv.first.items_log2, kv.second.path, kv.second.logN1,
-            kv.second.exact, kv.second.us, kv.second.twist, kv.second.lv_col);
+            kv.second.exact, kv.second.us, kv.second.twist, kv.second.lv_col, kv.second.col_tile);
     first = false;
   }
   fprintf(f, "\n]}\n");
@@ -309,15 +320,19 @@ int ntt_tune_load(const char* path) {
         field(b, e, "us", &us) && (w == 32 || w == 64) && in(lg, 1, 17) && in(il, 0, 40) &&
         in(pa, NTT_PATH_TINY, NTT_PATH_FOURSTEP) && in(n1, 0, 9) && in(ex, 0, 1) && in(us, 0, 1e9)) {
       // optional fields of later tables: the row form and the column passes'
-      // values per thread (an entry without them keeps the plan's own)
-      double tw = -1, lvc = 0;
-      const bool has_tw = field(b, e, "row_twist", &tw), has_lv = field(b, e, "lv_col", &lvc);
-      if ((has_tw && !in(tw, -1, 3)) || (has_lv && !(lvc == 0 || lvc == 3 || lvc == 4))) {
+      // values per thread and columns per tile (an entry without them keeps
+      // the plan's own)
+      double tw = -1, lvc = 0, ct = 0;
+      const bool has_tw = field(b, e, "row_twist", &tw), has_lv = field(b, e, "lv_col", &lvc),
+                 has_ct = field(b, e, "col_tile", &ct);
+      if ((has_tw && !in(tw, -1, 3)) || (has_lv && !(lvc == 0 || lvc == 3 || lvc == 4)) ||
+          (has_ct && !(ct == 0 || ct == 16 || ct == 32))) {
         pos = e + 1;
         continue;
       }
       std::lock_guard<std::mutex> g(g_mu);
-      g_table[TKey{(int)w, (int)lg, (int)il}] = TVal{(int)pa, (int)n1, (int)ex, (float)us, (int)tw, (int)lvc};
+      g_table[TKey{(int)w, (int)lg, (int)il}] =
+          TVal{(int)pa, (int)n1, (int)ex, (float)us, (int)tw, (int)lvc, ct == 32 ? 32 : 0};
       ++count;
     }
     pos = e + 1;

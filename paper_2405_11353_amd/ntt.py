@@ -86,7 +86,8 @@ class ServerStats(ctypes.Structure):
 
 class TuneChoice(ctypes.Structure):
     _fields_ = [("path", ctypes.c_int32), ("log_n1", ctypes.c_int32), ("exact", ctypes.c_int32),
-                ("us_per_call", ctypes.c_float), ("row_twist", ctypes.c_int32), ("lv_col", ctypes.c_int32)]
+                ("us_per_call", ctypes.c_float), ("row_twist", ctypes.c_int32), ("lv_col", ctypes.c_int32),
+                ("col_tile", ctypes.c_int32)]
 
 
 class NttError(RuntimeError):
@@ -137,6 +138,7 @@ def lib() -> ctypes.CDLL:
             "ntt_set_last_error": (None, [i32]),
             "ntt_plan_get_variant_for": (i32, [vp, u32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]),
             "ntt_plan_get_row_form": (i32, [vp, u32, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+            "ntt_plan_get_col_tile": (i32, [vp, u32, ctypes.POINTER(i32)]),
             "ntt_autotune": (i32, [u32, u32, u32, u32, ctypes.POINTER(TuneChoice)]),
             "ntt_tune_save": (i32, [ctypes.c_char_p]),
             "ntt_tune_load": (i32, [ctypes.c_char_p]),
@@ -324,11 +326,19 @@ def ntt_plan_get_row_form(plan: int, batch: int) -> tuple[int, int]:
     return tw.value, lv.value
 
 
+def ntt_plan_get_col_tile(plan: int, batch: int) -> int:
+    """Columns per tile of the four-step column passes a call on `batch`
+    polynomials runs with (0 off the four-step path)."""
+    c = ctypes.c_int32()
+    _check(lib().ntt_plan_get_col_tile(plan, batch, ctypes.byref(c)), "ntt_plan_get_col_tile")
+    return c.value
+
+
 def ntt_autotune(N: int, items: int, reps: int = 20, flags: int = 0) -> dict:
     out = TuneChoice()
     _check(lib().ntt_autotune(N, flags, items, reps, ctypes.byref(out)), "ntt_autotune")
     return {"path": out.path, "log_n1": out.log_n1, "exact": out.exact, "us_per_call": out.us_per_call,
-            "row_twist": out.row_twist, "lv_col": out.lv_col}
+            "row_twist": out.row_twist, "lv_col": out.lv_col, "col_tile": out.col_tile}
 
 
 def ntt_tune_save(path: str) -> None:

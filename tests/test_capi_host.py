@@ -177,9 +177,9 @@ def test_tune_load_survives_damaged_tables(lib, tmp_path):
 
 
 def test_tune_table_row_form_and_values_per_thread_fields(lib, tmp_path):
-    """Entries carry the tuned row form and column values per thread; both
-    survive a save and load, tables without them still load, and values out
-    of range drop the entry."""
+    """Entries carry the tuned row form and the column passes' values per
+    thread and columns per tile; they survive a save and load, tables without
+    them still load, and values out of range drop the entry."""
     import paper_2405_11353_amd as ntt
     ntt.ntt_tune_clear()
     f = tmp_path / "t.json"
@@ -187,16 +187,22 @@ def test_tune_table_row_form_and_values_per_thread_fields(lib, tmp_path):
     arch = f.read_text().split('"arch": "')[1].split('"')[0]
     head = '{"arch": "%s", "entries": [' % arch
     e = '{"word": 64, "log_n": 16, "items_log2": 6, "path": 3, "log_n1": 8, "exact": 0, "us": 9.5%s}'
-    f.write_text(head + e % ', "row_twist": 3, "lv_col": 4' + "]}")
+    f.write_text(head + e % ', "row_twist": 3, "lv_col": 4, "col_tile": 32' + "]}")
     ntt.ntt_tune_load(str(f))
     ntt.ntt_tune_save(str(f))
-    assert '"row_twist": 3, "lv_col": 4' in f.read_text()
+    assert '"row_twist": 3, "lv_col": 4, "col_tile": 32' in f.read_text()
+    f.write_text(head + e % ', "col_tile": 16' + "]}")   # 16 is the default tile
+    ntt.ntt_tune_clear()
+    ntt.ntt_tune_load(str(f))
+    ntt.ntt_tune_save(str(f))
+    assert '"col_tile": 0' in f.read_text()
     f.write_text(head + e % "" + "]}")                  # an older table: no new fields
     ntt.ntt_tune_clear()
     ntt.ntt_tune_load(str(f))
     ntt.ntt_tune_save(str(f))
-    assert '"row_twist": -1, "lv_col": 0' in f.read_text()
-    for bad in (', "row_twist": 4', ', "row_twist": -2', ', "lv_col": 5', ', "lv_col": 2'):
+    assert '"row_twist": -1, "lv_col": 0, "col_tile": 0' in f.read_text()
+    for bad in (', "row_twist": 4', ', "row_twist": -2', ', "lv_col": 5', ', "lv_col": 2', ', "col_tile": 24',
+                ', "col_tile": -16'):
         f.write_text(head + e % bad + "]}")
         ntt.ntt_tune_clear()
         with pytest.raises(ntt.NttError):

@@ -121,7 +121,7 @@ def test_autotune_and_plan_selection(ntt, tmp_path):
     ntt.ntt_tune_clear()
     best = ntt.ntt_autotune(1 << 16, items=96, reps=5)
     assert best["path"] in (ntt.NTT_PATH_LDS, ntt.NTT_PATH_FOURSTEP) and best["us_per_call"] > 0
-    assert best["lv_col"] in (0, 4)
+    assert best["lv_col"] in (0, 4) and best["col_tile"] in (0, 32)
     # -1: the plan's default row forms (kept unless another is clearly faster)
     assert best["row_twist"] in ((-1, 0, 1, 2) if best["path"] == ntt.NTT_PATH_FOURSTEP else (-1,))
     plan = ntt.Plan(1 << 16, P18[:2])
@@ -144,25 +144,30 @@ def test_autotune_and_plan_selection(ntt, tmp_path):
     ntt.ntt_tune_clear()
 
 
-@pytest.mark.parametrize("logn,logn1,twist,lv", [(16, 8, 3, 4), (16, 7, 1, 4), (17, 9, 2, 4), (14, 6, 3, 0),
-                                                 (16, 8, 0, 4)])
-def test_tuned_row_form_and_values_per_thread(ntt, tmp_path, logn, logn1, twist, lv):
-    """A tuning table that picks the row form of each direction and 16 values
-    per thread in the column passes: a plan in automatic mode runs with them
-    and still matches the oracle (forward, fused product + inverse)."""
+@pytest.mark.parametrize("logn,logn1,twist,lv,tile", [(16, 8, 3, 4, 0), (16, 7, 1, 4, 0), (17, 9, 2, 4, 0),
+                                                      (14, 6, 3, 0, 0), (16, 8, 0, 4, 0), (16, 8, 3, 0, 32),
+                                                      (16, 8, 3, 4, 32), (17, 9, 2, 0, 32), (17, 9, 0, 4, 32),
+                                                      (14, 6, 3, 0, 32), (13, 7, 1, 0, 32)])
+def test_tuned_row_form_and_values_per_thread(ntt, tmp_path, logn, logn1, twist, lv, tile):
+    """A tuning table that picks the row form of each direction, 16 values per
+    thread and 32 columns per tile in the column passes: a plan in automatic
+    mode runs with them and still matches the oracle (forward, fused product
+    + inverse, inverse)."""
     import ctypes
-    log(f"case tuned row form N=2^{logn} logn1={logn1} twist={twist} lv={lv}")
+    log(f"case tuned row form N=2^{logn} logn1={logn1} twist={twist} lv={lv} tile={tile}")
     f = tmp_path / "arch.json"
     ntt.ntt_tune_clear()
     ntt.ntt_tune_save(str(f))
     arch = f.read_text().split('"arch": "')[1].split('"')[0]
     f.write_text('{"arch": "%s", "entries": [{"word": 64, "log_n": %d, "items_log2": 2, "path": 3, "log_n1": %d, '
-                 '"exact": 0, "us": 1, "row_twist": %d, "lv_col": %d}]}' % (arch, logn, logn1, twist, lv))
+                 '"exact": 0, "us": 1, "row_twist": %d, "lv_col": %d, "col_tile": %d}]}'
+                 % (arch, logn, logn1, twist, lv, tile))
     ntt.ntt_tune_load(str(f))
     N, moduli = 1 << logn, P18[:2]
     try:
         plan = ntt.Plan(N, moduli)
         assert ntt.ntt_plan_get_variant_for(plan.handle, 2)[:2] == (ntt.NTT_PATH_FOURSTEP, logn1)
+        assert ntt.ntt_plan_get_col_tile(plan.handle, 2) == (tile or 16)
         a = si.poly_batch(logn + twist, 2, moduli, N)
         b = si.poly_batch(logn + twist + 1, 2, moduli, N)
         da, db = to_dev(a), to_dev(b)
