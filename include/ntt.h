@@ -267,9 +267,9 @@ const char* ntt_strerror(int code);
 /* ---- autotuner ------------------------------------------------------------
  * Times every kernel variant the library has for (N, word size, `items`
  * transforms per call) on the current GPU: the LDS-resident kernel, each
- * four-step split N1 x N2, and for 64-bit words both quotient flavours and 8
- * or 16 values per thread (so 2 or 1 threads per 16 values of a column) in
- * the column passes; `reps` timed calls each after two warm-up calls, with
+ * four-step split N1 x N2, and for 64-bit words both quotient flavours, 8
+ * or 16 values per thread (so 2 or 1 threads per 16 values of a column) and
+ * 16 or 32 columns per tile in the column passes; `reps` timed calls each after two warm-up calls, with
  * HIP events on a private stream. For a four-step winner it then times each
  * direction's row pass merged and twisted and keeps the faster. The winner
  * goes into a process-wide table that plans in automatic mode (the default)
@@ -279,7 +279,9 @@ const char* ntt_strerror(int code);
  * first plan, batch or server creation a process loads the file named by
  * NTT_TUNE_CACHE, or, if that variable is unset, tune_<arch>.json next to
  * libntt.so (an empty NTT_TUNE_CACHE loads nothing).
- * Synchronous; allocates items*N words of device memory while it runs. */
+ * The timed calls rotate over copies of the batch (512 MiB in all, at most
+ * 64 copies) so that each reads its data from memory rather than the caches.
+ * Synchronous; allocates those copies of items*N words while it runs. */
 typedef struct {
   int32_t path;       /* NTT_PATH_* */
   int32_t log_n1;     /* four-step column length log2 */

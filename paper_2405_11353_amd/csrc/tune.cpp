@@ -6,6 +6,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <string>
@@ -150,16 +151,23 @@ int ntt_autotune(uint32_t N, uint32_t flags, uint32_t items, uint32_t reps, ntt_
   std::vector<uint64_t> moduli(1, q);
   ntt_plan* plan = ntt_plan_create_ex(N, moduli.data(), 1, flags, nullptr);
   if (!plan) return ntt_last_error();
+  // the calls rotate over enough copies of the batch that each reads its
+  // data from memory, as a stream of real work does, not from the caches
+  // (the Infinity Cache alone holds 256 MiB): 512 MiB in all, at most 64
   const size_t bytes = (size_t)items * N * (word / 8);
+  const size_t nbuf = std::max<size_t>(1, std::min<size_t>(64, ((size_t)512 << 20) / bytes));
   void* buf = nullptr;
   hipStream_t s = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   int rc = NTT_OK;
-  if (ntti::dev_malloc(&buf, bytes) != hipSuccess) rc = NTT_ERR_NOMEM;
+  if (ntti::dev_malloc(&buf, nbuf * bytes) != hipSuccess) rc = NTT_ERR_NOMEM;
   // zeros are valid canonical inputs; the kernels' timing does not depend on values
-  if (rc == NTT_OK && (hipMemset(buf, 0, bytes) != hipSuccess || hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess ||
+  if (rc == NTT_OK && (hipMemset(buf, 0, nbuf * bytes) != hipSuccess ||
+                       hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess ||
                        hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
     rc = NTT_ERR_HIP;
+  uint32_t next = 0;
+  auto batch_buf = [&]() { return (void*)((unsigned char*)buf + (next++ % nbuf) * bytes); };
   // candidates: the LDS kernel, and every four-step split with either
   // quotient flavour (64-bit), and 8 or 16 values per thread and 16 or 32
   // columns per tile in the column passes (64-bit), all timed as forward
@@ -185,10 +193,11 @@ int ntt_autotune(uint32_t N, uint32_t flags, uint32_t items, uint32_t reps, ntt_
   // one timed configuration: `reps` calls after two warm-up calls
   auto time_us = [&](bool fwd, float* us) {
     bool ok = true;
-    for (uint32_t r = 0; r < 2 && ok; ++r) ok = (fwd ? ntt_forward : ntt_inverse)(plan, buf, items, s) == NTT_OK;
+    for (uint32_t r = 0; r < 2 && ok; ++r) ok = (fwd ? ntt_forward : ntt_inverse)(plan, batch_buf(), items, s) == NTT_OK;
     if (!ok || hipStreamSynchronize(s) != hipSuccess) return false;
     (void)hipEventRecord(e0, s);
-    for (uint32_t r = 0; r < reps && ok; ++r) ok = (fwd ? ntt_forward : ntt_inverse)(plan, buf, items, s) == NTT_OK;
+    for (uint32_t r = 0; r < reps && ok; ++r)
+      ok = (fwd ? ntt_forward : ntt_inverse)(plan, batch_buf(), items, s) == NTT_OK;
     (void)hipEventRecord(e1, s);
     if (!ok || hipEventSynchronize(e1) != hipSuccess) return false;
     float ms = 0;
