@@ -167,6 +167,7 @@ def test_autotune_allocations(ntt, tmp_path):
     """The autotuner's own plan and timing buffer: a failure at either is
     NTT_ERR_NOMEM. The process's tuning table is saved first and restored
     after, so later tests run with the table they would otherwise see."""
+    ntt.Plan(1 << 12, P18[:1]).close()      # the process's table is loaded at its first plan
     saved = str(tmp_path / "tune.json")
     ntt.ntt_tune_save(saved)
     outcomes = []
