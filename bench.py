@@ -1315,7 +1315,10 @@ def main():
     base = torch.from_numpy(host.view(np.int64)).cuda()
     sets = [base.clone() for _ in range(n_sets)]
     plan = ntt.Plan(N, moduli)
-    path, logn1 = plan.variant
+    # what the step's calls run with (the tuning table's choice per batch size):
+    # the forward on `polys` polynomials, the fused product + inverse on half
+    path, logn1 = ntt.ntt_plan_get_variant_for(plan.handle, polys)[:2]
+    path_inv, logn1_inv = ntt.ntt_plan_get_variant_for(plan.handle, polys // 2)[:2]
     stream = torch.cuda.current_stream()
 
     def step(buf, st=None):
@@ -1445,33 +1448,37 @@ def main():
     # with the transform's reads, the row pass with its writes (forward), and
     # the fused product + inverse with reading both spectra (its row pass) and
     # writing the product (its column pass). Counter bytes (traffic) beside.
-    if path == ntt.NTT_PATH_FOURSTEP:
+    if path == ntt.NTT_PATH_FOURSTEP and path_inv == ntt.NTT_PATH_FOURSTEP:
         logn2 = int(math.log2(N)) - logn1
-        twist_mask, _ = ntt.ntt_plan_get_row_form(plan.handle, 4)
+        logn2_inv = int(math.log2(N)) - logn1_inv
+        twist_fwd, _ = ntt.ntt_plan_get_row_form(plan.handle, polys)
+        twist_inv, _ = ntt.ntt_plan_get_row_form(plan.handle, polys // 2)
 
-        def row_table_bytes(twisted, lv):
+        def row_table_bytes(twisted, lv, lg1, lg2):
             """Table bytes one launch reads per limb set: the merged row pass all N
             slots; the split-twist pass each row's first-phase twiddles (2^P - 1),
             its NF * TPR twist factors, and the N2 cyclic twiddles."""
             if not twisted:
                 return L * 16 * N
-            n1, n2 = 1 << logn1, 1 << logn2
-            p_ = logn2 % lv or lv
+            n1, n2 = 1 << lg1, 1 << lg2
+            p_ = lg2 % lv or lv
             return L * 16 * (n1 * ((1 << p_) - 1) + n1 * (1 << (lv - p_)) * (n2 >> lv) + n2)
 
         # column passes read table slots [0, N1) of each limb
         tw_col = L * 16 * (1 << logn1)
-        tw_row = row_table_bytes(twist_mask & ntt.NTT_ROW_TWIST_FWD, 4)
-        tw_twist = row_table_bytes(twist_mask & ntt.NTT_ROW_TWIST_INV, 3)
+        tw_col_inv = L * 16 * (1 << logn1_inv)
+        tw_row = row_table_bytes(twist_fwd & ntt.NTT_ROW_TWIST_FWD, 4, logn1, logn2)
+        tw_twist = row_table_bytes(twist_inv & ntt.NTT_ROW_TWIST_INV, 3, logn1_inv, logn2_inv)
         kernels["fwd_col_pass"] = dict(fn=lambda b: plan.forward_stage(b, 0, batch=4), items=polys * L,
                                        stages=logn1, extra_muls=0, words_in=1, words_out=0, tw_bytes=tw_col)
         kernels["fwd_row_pass"] = dict(fn=lambda b: plan.forward_stage(b, 1, batch=4), items=polys * L,
                                        stages=logn2, extra_muls=0, words_in=0, words_out=1, tw_bytes=tw_row)
         kernels["inv_row_pass_mul"] = dict(fn=lambda b: plan.pointwise_inverse_stage(b[:2], b[2:], b[:2], 0, batch=2),
-                                           items=2 * L, stages=logn2, extra_muls=N, words_in=2, words_out=0,
+                                           items=2 * L, stages=logn2_inv, extra_muls=N, words_in=2, words_out=0,
                                            mont_muls=N, tw_bytes=tw_twist)
         kernels["inv_col_pass"] = dict(fn=lambda b: plan.inverse_stage(b[:2], 1, batch=2), items=2 * L,
-                                       stages=logn1, extra_muls=N // 2, words_in=0, words_out=1, tw_bytes=tw_col)
+                                       stages=logn1_inv, extra_muls=N // 2, words_in=0, words_out=1,
+                                       tw_bytes=tw_col_inv)
     else:
         kernels["pointwise"] = dict(fn=lambda b: plan.pointwise(b[:2], b[2:], b[:2], batch=2), items=2 * L,
                                     stages=0, extra_muls=0, words_in=2, words_out=1)
@@ -1593,7 +1600,8 @@ def main():
         "dtype": "u64",
         "data": "synthetic: seeded uniform residues mod 24 primes q < 2^60, q = 1 mod 2^17",
         "config": {"workload": w.name, "N": N, "L": L, "polys": polys, "ntts_per_step": ntts_per_step,
-                   "variant": {"path": "fourstep" if path == ntt.NTT_PATH_FOURSTEP else "lds", "log_n1": logn1},
+                   "variant": {"path": "fourstep" if path == ntt.NTT_PATH_FOURSTEP else "lds", "log_n1": logn1,
+                               "log_n1_inverse": logn1_inv},
                    "rotating_sets": n_sets, "footprint_MiB": n_sets * set_bytes >> 20,
                    "streams": len(streams), "untimed_steady_ms": args.steady_ms,
                    "clock_warmup_ms": args.clock_warmup_ms},
