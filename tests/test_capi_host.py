@@ -61,6 +61,16 @@ def test_plan_argument_validation(lib):
         assert lib.ntt_last_error() == code, (args, lib.ntt_last_error())
 
 
+def test_plan_queries_reject_null_plans(lib):
+    """The per-call variant queries check their plan and batch before reading
+    anything (no GPU needed)."""
+    out = ctypes.c_int32()
+    p = ctypes.byref(out)
+    assert lib.ntt_plan_get_col_tile(None, 1, p) == -1
+    assert lib.ntt_plan_get_row_form(None, 1, p, p) == -1
+    assert lib.ntt_plan_get_variant_for(None, 1, p, p, p) == -1
+
+
 def test_strerror_covers_codes(lib):
     lib.ntt_strerror.restype = ctypes.c_char_p
     for c in range(0, -12, -1):
